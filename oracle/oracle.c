@@ -1,0 +1,395 @@
+/*
+ * oracle.c -- plain, slow FP64 CPU reference for the TCUDB join-aggregate
+ * operator (Hu, Li, Tseng, "TCUDB: Accelerating Database with Tensor
+ * Processors", SIGMOD 2022).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the checker, not the product: only
+ * the test suite, the smoke check and the benchmark's CPU-baseline leg may load
+ * it.  It shares no code, header, table or helper with the HIP library.
+ *
+ * What it computes is the SQL definition of the operator, not the matrix
+ * method.  For relation A with records (group g, key k, value v) and relation B
+ * with records (key k, group h, value w), the operator of Section 3.3
+ * (group-by aggregate over a join, Lemma Q3) in the form of the matrix
+ * multiplication query of Section 2.3 / Fig. "matrix multiplication query" is
+ *
+ *     C[g,h] = sum over pairs (a in A, b in B) with a.key == b.key,
+ *              a.group == g, b.group == h  of  a.val * b.val      (bag semantics)
+ *
+ * evaluated here as a hash join: B is bucketed by key, and every A record is
+ * paired with every B record of its bucket.  Every sum is accumulated with the
+ * compensated dot product Dot2 of Ogita, Rump and Oishi ("Accurate sum and dot
+ * product", SIAM J. Sci. Comput. 26(6), 2005): TwoProduct through an FMA plus
+ * Knuth's TwoSum, so the oracle's own error is about one rounding of the result
+ * plus a term of order (n u)^2 sum |a.val * b.val|.
+ *
+ * Records whose key or group falls outside [0,K) x [0,M) (resp. [0,K) x [0,N))
+ * take part in nothing: they are the records the operator skips and reports.
+ * A NULL value column stands for COUNT (every value is 1), Section 3.3.
+ *
+ * Build: gcc -O2 -std=c11 -fopenmp -fPIC -shared -ffp-contract=off.
+ * -ffp-contract=off is required: a contracted a*b+c inside TwoSum/TwoProduct
+ * would break the error-free transformations.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+/* ---------------------------------------------------------------- Dot2 --- */
+
+typedef struct { double hi, lo; } acc2;
+
+/* Knuth's TwoSum: s + e == a + b exactly. */
+static inline void two_sum(double a, double b, double *s, double *e) {
+    double x = a + b;
+    double z = x - a;
+    *e = (a - (x - z)) + (b - z);
+    *s = x;
+}
+
+/* TwoProduct with an FMA: p + e == a * b exactly (barring underflow). */
+static inline void two_prod(double a, double b, double *p, double *e) {
+    double x = a * b;
+    *e = fma(a, b, -x);
+    *p = x;
+}
+
+static inline void acc2_add(acc2 *acc, double a, double b) {
+    double p, ep, s, es;
+    two_prod(a, b, &p, &ep);
+    two_sum(acc->hi, p, &s, &es);
+    acc->hi = s;
+    acc->lo += es + ep;
+}
+
+static inline double acc2_value(acc2 a) { return a.hi + a.lo; }
+
+/* ------------------------------------------------------------- buckets --- */
+
+static inline int in_range(int32_t x, int32_t n) { return x >= 0 && x < n; }
+
+/*
+ * Stable counting sort of the valid records of a relation by `primary`.
+ * A record is valid when primary in [0,np) and secondary in [0,ns).
+ * On return off[0..np] are bucket offsets into order[], which lists record
+ * indices in increasing index order inside each bucket.  If `secondary_sorted`
+ * is set, each bucket is additionally ordered by the secondary column
+ * (stable), which the per-cell queries use for binary search.
+ */
+static int bucket_records(int64_t n, const int32_t *primary, int32_t np,
+                          const int32_t *secondary, int32_t ns,
+                          int secondary_sorted, int64_t **off_out, int64_t **order_out) {
+    int64_t *off = (int64_t *)calloc((size_t)np + 1, sizeof(int64_t));
+    int64_t *order = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!off || !order) { free(off); free(order); return -1; }
+    for (int64_t i = 0; i < n; ++i)
+        if (in_range(primary[i], np) && in_range(secondary[i], ns)) off[primary[i] + 1]++;
+    for (int32_t b = 0; b < np; ++b) off[b + 1] += off[b];
+    if (!secondary_sorted) {
+        int64_t *pos = (int64_t *)malloc((size_t)np * sizeof(int64_t));
+        if (!pos) { free(off); free(order); return -1; }
+        memcpy(pos, off, (size_t)np * sizeof(int64_t));
+        for (int64_t i = 0; i < n; ++i)
+            if (in_range(primary[i], np) && in_range(secondary[i], ns)) order[pos[primary[i]]++] = i;
+        free(pos);
+    } else {
+        /* first a stable sort by secondary, then a stable sort by primary */
+        int64_t *soff = (int64_t *)calloc((size_t)ns + 1, sizeof(int64_t));
+        int64_t *tmp = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+        int64_t *pos = (int64_t *)malloc((size_t)(np > ns ? np : ns) * sizeof(int64_t));
+        if (!soff || !tmp || !pos) { free(soff); free(tmp); free(pos); free(off); free(order); return -1; }
+        for (int64_t i = 0; i < n; ++i)
+            if (in_range(primary[i], np) && in_range(secondary[i], ns)) soff[secondary[i] + 1]++;
+        for (int32_t b = 0; b < ns; ++b) soff[b + 1] += soff[b];
+        memcpy(pos, soff, (size_t)ns * sizeof(int64_t));
+        for (int64_t i = 0; i < n; ++i)
+            if (in_range(primary[i], np) && in_range(secondary[i], ns)) tmp[pos[secondary[i]]++] = i;
+        memcpy(pos, off, (size_t)np * sizeof(int64_t));
+        int64_t nvalid = off[np];
+        for (int64_t t = 0; t < nvalid; ++t) {
+            int64_t i = tmp[t];
+            order[pos[primary[i]]++] = i;
+        }
+        free(soff); free(tmp); free(pos);
+    }
+    *off_out = off;
+    *order_out = order;
+    return 0;
+}
+
+static inline double value_of(const double *val, int64_t i) { return val ? val[i] : 1.0; }
+
+static int set_threads(int nthreads) {
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    int used = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        used = omp_get_num_threads();
+    }
+    return used;
+}
+
+/* -------------------------------------------------------------- encode --- */
+
+/*
+ * Value-filled encoding of one relation into a dense R x Ccols row-major
+ * matrix (Section 3.1 for 0/1 entries, Section 3.3 for value entries):
+ * out[row, col] = sum of val over the records with that (row, col).
+ * Duplicate coordinates add up (bag semantics); the sum runs in record order.
+ * Returns the number of records skipped because a coordinate is out of range.
+ */
+int64_t orc_encode(int64_t n, const int32_t *row, const int32_t *col, const double *val,
+                   int32_t R, int32_t Ccols, double *out) {
+    memset(out, 0, (size_t)R * (size_t)Ccols * sizeof(double));
+    int64_t skipped = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!in_range(row[i], R) || !in_range(col[i], Ccols)) { skipped++; continue; }
+        out[(int64_t)row[i] * Ccols + col[i]] += value_of(val, i);
+    }
+    return skipped;
+}
+
+/* ------------------------------------------------------------- forward --- */
+
+/*
+ * C for a set of groups g of A (all of [0,M) when rows == NULL):
+ *   C[r, h] = sum_{a: a.group == rows[r]} sum_{b: b.key == a.key, b.group == h} a.val * b.val
+ *   cnt[r, h] = number of such pairs (optional, exact).
+ * C (and cnt) are nrows x N row-major (M x N when rows == NULL).
+ * Returns the number of OpenMP threads used, or -1 on allocation failure.
+ */
+int orc_join_agg_rows(int64_t nA, const int32_t *ag, const int32_t *ak, const double *av,
+                      int64_t nB, const int32_t *bk, const int32_t *bh, const double *bw,
+                      int32_t M, int32_t K, int32_t N,
+                      int64_t nrows, const int32_t *rows, double *C, int64_t *cnt, int nthreads) {
+    int used = set_threads(nthreads);
+    int64_t *boff, *border, *aoff, *aorder;
+    if (bucket_records(nB, bk, K, bh, N, 0, &boff, &border)) return -1;
+    if (bucket_records(nA, ag, M, ak, K, 0, &aoff, &aorder)) { free(boff); free(border); return -1; }
+    int64_t R = rows ? nrows : M;
+    int failed = 0;
+#pragma omp parallel
+    {
+        acc2 *acc = (acc2 *)malloc((size_t)N * sizeof(acc2));
+        int64_t *pc = (int64_t *)malloc((size_t)N * sizeof(int64_t));
+        if (!acc || !pc) {
+#pragma omp atomic write
+            failed = 1;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t r = 0; r < R; ++r) {
+                int32_t g = rows ? rows[r] : (int32_t)r;
+                memset(acc, 0, (size_t)N * sizeof(acc2));
+                memset(pc, 0, (size_t)N * sizeof(int64_t));
+                if (in_range(g, M)) {
+                    for (int64_t t = aoff[g]; t < aoff[g + 1]; ++t) {
+                        int64_t i = aorder[t];
+                        double v = value_of(av, i);
+                        int32_t k = ak[i];
+                        for (int64_t u = boff[k]; u < boff[k + 1]; ++u) {
+                            int64_t j = border[u];
+                            acc2_add(&acc[bh[j]], v, value_of(bw, j));
+                            pc[bh[j]]++;
+                        }
+                    }
+                }
+                for (int32_t h = 0; h < N; ++h) {
+                    C[r * N + h] = acc2_value(acc[h]);
+                    if (cnt) cnt[r * N + h] = pc[h];
+                }
+            }
+        }
+        free(acc);
+        free(pc);
+    }
+    free(boff); free(border); free(aoff); free(aorder);
+    return failed ? -1 : used;
+}
+
+/*
+ * C and the pair count at individual cells (cg[c], ch[c]): the same sum as
+ * above restricted to one (g, h).  B is bucketed by key and ordered by group
+ * inside each bucket, so each A record finds its partners with a binary search.
+ * Cells outside [0,M) x [0,N) give 0.
+ */
+int orc_join_agg_cells(int64_t nA, const int32_t *ag, const int32_t *ak, const double *av,
+                       int64_t nB, const int32_t *bk, const int32_t *bh, const double *bw,
+                       int32_t M, int32_t K, int32_t N,
+                       int64_t ncells, const int32_t *cg, const int32_t *ch,
+                       double *out, int64_t *cnt, int nthreads) {
+    int used = set_threads(nthreads);
+    int64_t *boff, *border, *aoff, *aorder;
+    if (bucket_records(nB, bk, K, bh, N, 1, &boff, &border)) return -1;
+    if (bucket_records(nA, ag, M, ak, K, 0, &aoff, &aorder)) { free(boff); free(border); return -1; }
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t c = 0; c < ncells; ++c) {
+        int32_t g = cg[c], h = ch[c];
+        acc2 acc = {0.0, 0.0};
+        int64_t pairs = 0;
+        if (in_range(g, M) && in_range(h, N)) {
+            for (int64_t t = aoff[g]; t < aoff[g + 1]; ++t) {
+                int64_t i = aorder[t];
+                int32_t k = ak[i];
+                /* lower bound of group h inside bucket k */
+                int64_t lo = boff[k], hi = boff[k + 1];
+                while (lo < hi) {
+                    int64_t mid = lo + (hi - lo) / 2;
+                    if (bh[border[mid]] < h) lo = mid + 1; else hi = mid;
+                }
+                for (int64_t u = lo; u < boff[k + 1] && bh[border[u]] == h; ++u) {
+                    acc2_add(&acc, value_of(av, i), value_of(bw, border[u]));
+                    pairs++;
+                }
+            }
+        }
+        out[c] = acc2_value(acc);
+        if (cnt) cnt[c] = pairs;
+    }
+    free(boff); free(border); free(aoff); free(aorder);
+    return used;
+}
+
+/*
+ * Right-hand side of Freivalds' check: out[g] = sum_h C[g,h] r[h], evaluated
+ * from the records in O(nA + nB) by regrouping the defining double sum:
+ *   t[k]   = sum_{b: b.key == k} b.val * r[b.group]
+ *   out[g] = sum_{a: a.group == g} a.val * t[a.key]
+ * (R. Freivalds, "Probabilistic machines can use less running time", IFIP 1977.)
+ */
+int orc_freivalds(int64_t nA, const int32_t *ag, const int32_t *ak, const double *av,
+                  int64_t nB, const int32_t *bk, const int32_t *bh, const double *bw,
+                  int32_t M, int32_t K, int32_t N, const double *r, double *out, int nthreads) {
+    int used = set_threads(nthreads);
+    int64_t *boff, *border, *aoff, *aorder;
+    if (bucket_records(nB, bk, K, bh, N, 0, &boff, &border)) return -1;
+    if (bucket_records(nA, ag, M, ak, K, 0, &aoff, &aorder)) { free(boff); free(border); return -1; }
+    double *t = (double *)malloc((size_t)K * sizeof(double));
+    if (!t) { free(boff); free(border); free(aoff); free(aorder); return -1; }
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int32_t k = 0; k < K; ++k) {
+        acc2 acc = {0.0, 0.0};
+        for (int64_t u = boff[k]; u < boff[k + 1]; ++u) {
+            int64_t j = border[u];
+            acc2_add(&acc, value_of(bw, j), r[bh[j]]);
+        }
+        t[k] = acc2_value(acc);
+    }
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int32_t g = 0; g < M; ++g) {
+        acc2 acc = {0.0, 0.0};
+        for (int64_t u = aoff[g]; u < aoff[g + 1]; ++u) {
+            int64_t i = aorder[u];
+            acc2_add(&acc, value_of(av, i), t[ak[i]]);
+        }
+        out[g] = acc2_value(acc);
+    }
+    free(t); free(boff); free(border); free(aoff); free(aorder);
+    return used;
+}
+
+/* ------------------------------------------------------------ gradient --- */
+
+/*
+ * Gradient of L = sum_{g,h} W[g,h] C[g,h] with respect to the value columns,
+ * by differentiating the defining sum term by term:
+ *   dL/d a_i.val = sum_{b: b.key == a_i.key} W[a_i.group, b.group] * b.val
+ *   dL/d b_j.val = sum_{a: a.key == b_j.key} W[a.group, b_j.group] * a.val
+ * For records idx[0..nidx) of the chosen relation (all records when idx ==
+ * NULL).  which == 0 selects A, which == 1 selects B.  Records that take part
+ * in nothing (out-of-range coordinates) get 0.
+ */
+int orc_grad(int64_t nA, const int32_t *ag, const int32_t *ak, const double *av,
+             int64_t nB, const int32_t *bk, const int32_t *bh, const double *bw,
+             int32_t M, int32_t K, int32_t N, const double *W,
+             int which, int64_t nidx, const int64_t *idx, double *out, int nthreads) {
+    int used = set_threads(nthreads);
+    int64_t *off, *order;
+    if (which == 0) {
+        if (bucket_records(nB, bk, K, bh, N, 0, &off, &order)) return -1;
+        int64_t R = idx ? nidx : nA;
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int64_t r = 0; r < R; ++r) {
+            int64_t i = idx ? idx[r] : r;
+            acc2 acc = {0.0, 0.0};
+            if (i >= 0 && i < nA && in_range(ag[i], M) && in_range(ak[i], K)) {
+                int32_t k = ak[i];
+                const double *wrow = W + (int64_t)ag[i] * N;
+                for (int64_t u = off[k]; u < off[k + 1]; ++u) {
+                    int64_t j = order[u];
+                    acc2_add(&acc, wrow[bh[j]], value_of(bw, j));
+                }
+            }
+            out[r] = acc2_value(acc);
+        }
+    } else {
+        if (bucket_records(nA, ak, K, ag, M, 0, &off, &order)) return -1;
+        int64_t R = idx ? nidx : nB;
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int64_t r = 0; r < R; ++r) {
+            int64_t j = idx ? idx[r] : r;
+            acc2 acc = {0.0, 0.0};
+            if (j >= 0 && j < nB && in_range(bk[j], K) && in_range(bh[j], N)) {
+                int32_t k = bk[j], h = bh[j];
+                for (int64_t u = off[k]; u < off[k + 1]; ++u) {
+                    int64_t i = order[u];
+                    acc2_add(&acc, W[(int64_t)ag[i] * N + h], value_of(av, i));
+                }
+            }
+            out[r] = acc2_value(acc);
+        }
+    }
+    free(off); free(order);
+    return used;
+}
+
+/* --------------------------------------------------------------- split --- */
+
+/*
+ * Fixed-point slicing of a dense R x L row-major matrix, used by the
+ * mixed-precision form of the contraction (the paper's feasibility test of
+ * Section 4.2.1 picks a narrow matrix-unit type from per-column min/max
+ * metadata; the mixed form generalises that to several narrow slices).
+ *
+ * axis == 0: one scale per row; axis == 1: one scale per column.  For a line
+ * (row or column) with largest magnitude mx:
+ *   e = the exponent with 2^(e-1) <= mx < 2^e   (e = 0 when mx == 0),
+ *   r_0 = x / 2^e  (so |r_0| < 1),
+ *   for p = 1..nslices:  t = r_{p-1} * 2^bits,  d_p = trunc(t),  r_p = t - d_p,
+ * so that x = 2^e * (sum_p d_p 2^(-bits p) + r_s 2^(-bits s)) exactly, every
+ * d_p an integer with |d_p| < 2^bits and the sign of x.  Every step is exact in
+ * FP64 (power-of-two scalings and the removal of an integer part).
+ * slices[p][row][col] holds d_(p+1); exps[line] holds e.
+ * Returns 0, or the 1-based index of the first line holding a NaN or infinity
+ * (that line's outputs are then undefined).
+ */
+int64_t orc_split(int32_t R, int32_t L, const double *X, int axis, int nslices, int bits,
+                  int32_t *exps, double *slices) {
+    int64_t nlines = axis == 0 ? R : L;
+    int64_t len = axis == 0 ? L : R;
+    int64_t bad = 0;
+    for (int64_t line = 0; line < nlines; ++line) {
+        double mx = 0.0;
+        for (int64_t t = 0; t < len; ++t) {
+            double x = axis == 0 ? X[line * L + t] : X[t * L + line];
+            if (!isfinite(x)) { if (!bad) bad = line + 1; mx = 0.0; break; }
+            if (fabs(x) > mx) mx = fabs(x);
+        }
+        int e = 0;
+        if (mx > 0.0) frexp(mx, &e);
+        exps[line] = e;
+        for (int64_t t = 0; t < len; ++t) {
+            int64_t at = axis == 0 ? line * L + t : t * L + line;
+            double r = ldexp(X[at], -e);
+            for (int p = 0; p < nslices; ++p) {
+                double tt = ldexp(r, bits);
+                double d = trunc(tt);
+                slices[(int64_t)p * R * L + at] = d;
+                r = tt - d;
+            }
+        }
+    }
+    return bad;
+}
