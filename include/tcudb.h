@@ -1,0 +1,152 @@
+/*
+ * tcudb.h -- C ABI of libtcudb.so: the join-aggregate-as-GEMM operator of
+ * TCUDB (Hu, Li, Tseng, SIGMOD 2022) on AMD Instinct MI355X (gfx950).
+ *
+ * The operator answers the matrix multiplication query of Section 2.3 and,
+ * generally, the group-by aggregate over a two-way join of Section 3.3
+ * (Lemma Q3, queries Q3/Q4): for relation A of records (g, k, v) and relation
+ * B of records (k, h, w),
+ *
+ *     C[g,h] = sum over pairs (a, b) with a.k == b.k, a.g == g, b.h == h of a.v * b.w
+ *
+ * computed as in Sections 3.1 and 3.3: encode X[g,k] = sum of a.v (M x K),
+ * Y[k,h] = sum of b.w (K x N), then one matrix product C = X * Y (M x N).
+ *
+ * Conventions shared by every call:
+ *  - Array pointers are DEVICE pointers owned by the caller.  The library never
+ *    allocates, frees or keeps caller memory and keeps no mutable global state.
+ *  - Work is enqueued on the caller's stream and is asynchronous unless a call
+ *    says otherwise; results are valid once the stream has reached that point.
+ *  - Matrices are dense row-major with the leading dimension equal to the
+ *    column count, unless a call takes explicit leading dimensions.
+ *  - Host-side argument errors return a negative status and enqueue nothing.
+ *  - Records with a key or group outside its range are never written out of
+ *    bounds: they are skipped and counted in a status block at the start of
+ *    the workspace, which tcu_sync_status() reads back.
+ *  - A NULL value column means COUNT: every value is 1 (Section 3.3).
+ *  - Calls that share one workspace must not overlap (same stream or ordered).
+ */
+#ifndef TCUDB_H
+#define TCUDB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TCU_OK = 0,
+    TCU_ERR_ARG = -1,        /* NULL required pointer, bad size or enum        */
+    TCU_ERR_KEY_RANGE = -2,  /* device: a record had an out-of-range key/group */
+    TCU_ERR_WORKSPACE = -3,  /* workspace NULL, misaligned or too small        */
+    TCU_ERR_INFEASIBLE = -4, /* mixed form: tolerance not reachable            */
+    TCU_ERR_NONFINITE = -5,  /* mixed form: NaN or infinity in an encoding     */
+    TCU_ERR_HIP = -6         /* a HIP runtime call failed                      */
+} tcu_status;
+
+typedef enum { TCU_F64 = 0, TCU_F32 = 1 } tcu_dtype;
+
+typedef enum {
+    TCU_PREC_FP64 = 0,       /* FP64 encodings, FP64 matrix-core product       */
+    TCU_PREC_SPLIT_BF16 = 1  /* FP64 encodings split into BF16 integer slices,
+                                FP32 exact partial sums, FP64 combination     */
+} tcu_precision;
+
+/* One relation, struct of arrays with n records.
+ * For A: group = g in [0,M) (A.col_num of the MM query), key = k in [0,K)
+ *        (A.row_num).
+ * For B: group = h in [0,N) (B.row_num), key = k in [0,K) (B.col_num).
+ * val: n values of `dtype`, or NULL for COUNT. */
+typedef struct {
+    int64_t n;
+    const int32_t *group;
+    const int32_t *key;
+    const void *val;
+    tcu_dtype dtype;
+} tcu_relation;
+
+/* Flags for tcu_workspace_bytes. */
+#define TCU_WS_BACKWARD 1 /* size for tcu_join_agg_bwd as well               */
+#define TCU_WS_COUNT 2    /* size for the optional pair-count output         */
+
+/* Status block read back by tcu_sync_status (host copy). */
+typedef struct {
+    uint32_t flags;        /* bit 0: out-of-range record, bit 1: non-finite   */
+    uint32_t slices;       /* mixed form: slices used by the last call        */
+    uint64_t skipped_a;    /* records of A skipped by the last call           */
+    uint64_t skipped_b;    /* records of B skipped by the last call           */
+} tcu_status_info;
+
+/* Bytes of device workspace the calls below need for these shapes (Section
+ * 3.3 encodings X and Y, plus the status block; with TCU_WS_BACKWARD one more
+ * K-sized gradient matrix; in the mixed form the BF16 slices).  The
+ * workspace must be 256-byte aligned.  Returns 0 for invalid shapes. */
+size_t tcu_workspace_bytes(const tcu_relation *A, const tcu_relation *B, int32_t M, int32_t K,
+                           int32_t N, tcu_precision p, int flags);
+
+/* Step a1, the encoding of Sections 3.1/3.3 ("fill"): out (rows x cols,
+ * FP64, row-major, leading dimension cols) is overwritten with
+ *   transpose == 0: out[group, key] = sum of val   (A -> X, rows = M, cols = K)
+ *   transpose == 1: out[key, group] = sum of val   (B -> Y, rows = K, cols = N)
+ * Duplicate coordinates add up (FP64 atomics: order-dependent rounding);
+ * unique coordinates give the values bit for bit.  Out-of-range records are
+ * skipped and counted as A's skips in the workspace status block.
+ * ws: at least tcu_workspace_bytes(...) for any shapes (256 bytes suffice). */
+tcu_status tcu_encode(const tcu_relation *R, int transpose, int32_t rows, int32_t cols,
+                      double *out, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Step a2 alone, the contraction of Section 3.3: C = op(A) * op(B) in FP64 on
+ * the matrix cores, op(A) m x k, op(B) k x n, C m x n (leading dimension ldc).
+ * trans_a == 0: A is m x k row-major (lda >= k); 1: A is k x m (lda >= m).
+ * trans_b == 0: B is k x n row-major (ldb >= n); 1: B is n x k (ldb >= k).
+ * C is overwritten.  k == 0 gives C = 0. */
+tcu_status tcu_gemm_f64(int trans_a, int trans_b, int32_t m, int32_t n, int32_t k,
+                        const double *A, int64_t lda, const double *B, int64_t ldb,
+                        double *C, int64_t ldc, hipStream_t stream);
+
+/* Steps a1-a3, the operator (Sections 2.3, 3.3): C (M x N FP64 row-major,
+ * rows g ascending, columns h ascending) = the join-aggregate above.
+ * count (M x N int32, or NULL): exact number of joined pairs per (g,h); SQL's
+ * result holds exactly the cells with count > 0 (a dense C shows 0 elsewhere).
+ * p == TCU_PREC_SPLIT_BF16 runs the mixed form to componentwise accuracy
+ * `tol` relative to K * max|X[g,:]| * max|Y[:,h]| (tol <= 0: 2^-52) and makes
+ * one device-to-host synchronisation to read the encodings' exponent range.
+ * Device-side conditions (out-of-range records) are reported by
+ * tcu_sync_status. */
+tcu_status tcu_join_agg_fwd(const tcu_relation *A, const tcu_relation *B, int32_t M, int32_t K,
+                            int32_t N, tcu_precision p, double tol, double *C, int32_t *count,
+                            void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Step a4, the adjoint of the operator for L = sum_{g,h} dC[g,h] C[g,h]:
+ *   dA_val[i] = sum_{b: b.k == a_i.k} dC[a_i.g, b.h] * b.w = (dC Y^T)[a_i.g, a_i.k]
+ *   dB_val[j] = sum_{a: a.k == b_j.k} dC[a.g, b_j.h] * a.v = (X^T dC)[b_j.k, b_j.h]
+ * X and Y are re-encoded from the records (activation checkpointing: the
+ * forward keeps no matrices).  Either output may be NULL.  Skipped records
+ * get 0.  Gradients are FP64 whatever the value dtype.  Needs a workspace
+ * sized with TCU_WS_BACKWARD. */
+tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_t M, int32_t K,
+                            int32_t N, tcu_precision p, double tol, const double *dC,
+                            double *dA_val, double *dB_val, void *ws, size_t ws_bytes,
+                            hipStream_t stream);
+
+/* SYNCHRONISES the stream, then reads the workspace status block written by
+ * the last call that used `ws`.  Returns TCU_ERR_KEY_RANGE if records were
+ * skipped, TCU_ERR_NONFINITE if the mixed form met NaN/Inf, else TCU_OK.
+ * info (may be NULL) receives the whole block. */
+tcu_status tcu_sync_status(void *ws, hipStream_t stream, tcu_status_info *info);
+
+/* Static description of a status code. */
+const char *tcu_status_str(tcu_status s);
+
+/* Library version string. */
+const char *tcu_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TCUDB_H */

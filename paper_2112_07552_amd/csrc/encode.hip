@@ -1,0 +1,142 @@
+// encode.hip -- step a1 (encoding, Sections 3.1 and 3.3 of TCUDB) and the
+// record gathers of the adjoint.
+//
+// The encoding places every record's value at its (group, key) cell of a
+// dense row-major matrix; duplicate cells add up.  It is an HBM-bound
+// scatter: per record it reads 4 + 4 + sizeof(val) bytes and performs one
+// 8-byte FP64 atomic add (no return) into the matrix, which the zero pass
+// wrote beforehand.  Unique coordinates (the measured workload) give the
+// record values bit for bit, since 0 + v == v.
+#include "internal.h"
+
+namespace tcu {
+namespace {
+
+constexpr int kThreads = 256;
+
+__global__ void __launch_bounds__(kThreads) zero_f64_kernel(double *__restrict__ p, size_t n,
+                                                            int vec) {
+    const size_t stride = (size_t)gridDim.x * kThreads;
+    const size_t t0 = (size_t)blockIdx.x * kThreads + threadIdx.x;
+    if (vec) {
+        // p is 16-byte aligned: 16-byte stores over the even prefix, then the odd tail
+        const size_t n2 = n / 2;
+        double2 *p2 = reinterpret_cast<double2 *>(p);
+        for (size_t i = t0; i < n2; i += stride) p2[i] = make_double2(0.0, 0.0);
+        if (t0 == 0 && (n & 1)) p[n - 1] = 0.0;
+    } else {
+        for (size_t i = t0; i < n; i += stride) p[i] = 0.0;
+    }
+}
+
+__global__ void zero_status_kernel(StatusBlock *st) {
+    uint32_t *w = reinterpret_cast<uint32_t *>(st);
+    w[threadIdx.x] = 0u;  // 64 threads x 4 bytes
+}
+
+// Counts this wave's invalid records and adds them to the status block once
+// (st == nullptr: a repeated pass whose skips were already counted).
+__device__ inline void report_skips(bool bad, StatusBlock *st, int which) {
+    const unsigned long long mask = __ballot(bad);
+    if (st != nullptr && mask != 0ull && (threadIdx.x & 63) == 0) {
+        atomicOr(&st->flags, kFlagKeyRange);
+        atomicAdd(which == 0 ? &st->skipped_a : &st->skipped_b,
+                  (unsigned long long)__popcll(mask));
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+encode_kernel(int64_t n, const int32_t *__restrict__ grp, const int32_t *__restrict__ key,
+              const T *__restrict__ val, int transpose, int rows, int cols,
+              double *__restrict__ out, StatusBlock *st, int which) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    bool bad = false;
+    if (i < n) {
+        const int g = grp[i], k = key[i];
+        const int r = transpose ? k : g;
+        const int c = transpose ? g : k;
+        if ((unsigned)r < (unsigned)rows && (unsigned)c < (unsigned)cols) {
+            const double v = val ? (double)val[i] : 1.0;
+            unsafeAtomicAdd(out + (size_t)r * (size_t)cols + c, v);
+        } else {
+            bad = true;
+        }
+    }
+    report_skips(bad, st, which);
+}
+
+__global__ void __launch_bounds__(kThreads)
+gather_kernel(int64_t n, const int32_t *__restrict__ grp, const int32_t *__restrict__ key,
+              int transpose, int rows, int cols, const double *__restrict__ src,
+              double *__restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const int g = grp[i], k = key[i];
+    const int r = transpose ? k : g;
+    const int c = transpose ? g : k;
+    double v = 0.0;
+    if ((unsigned)r < (unsigned)rows && (unsigned)c < (unsigned)cols)
+        v = src[(size_t)r * (size_t)cols + c];
+    dst[i] = v;
+}
+
+__global__ void __launch_bounds__(kThreads)
+f64_to_i32_kernel(const double *__restrict__ src, int32_t *__restrict__ dst, size_t n) {
+    const size_t stride = (size_t)gridDim.x * kThreads;
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride)
+        dst[i] = (int32_t)src[i];
+}
+
+inline unsigned grid_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+inline unsigned capped_grid(size_t n) {
+    size_t g = (n + kThreads - 1) / kThreads;
+    const size_t cap = 256 * 64;  // 64 blocks per CU is plenty for a stream
+    return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+}  // namespace
+
+hipError_t launch_zero_f64(double *p, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int vec = ((uintptr_t)p & 15) == 0;
+    zero_f64_kernel<<<capped_grid(vec ? n / 2 + 1 : n), kThreads, 0, s>>>(p, n, vec);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_status(StatusBlock *st, hipStream_t s) {
+    zero_status_kernel<<<1, 64, 0, s>>>(st);
+    return hipGetLastError();
+}
+
+hipError_t launch_encode(const tcu_relation &R, int transpose, int rows, int cols, double *out,
+                         StatusBlock *st, int which, hipStream_t s) {
+    if (R.n == 0) return hipSuccess;
+    const unsigned grid = grid_for(R.n);
+    if (R.dtype == TCU_F32)
+        encode_kernel<float><<<grid, kThreads, 0, s>>>(
+            R.n, R.group, R.key, static_cast<const float *>(R.val), transpose, rows, cols, out, st,
+            which);
+    else
+        encode_kernel<double><<<grid, kThreads, 0, s>>>(
+            R.n, R.group, R.key, static_cast<const double *>(R.val), transpose, rows, cols, out,
+            st, which);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const tcu_relation &R, int transpose, int rows, int cols,
+                         const double *src, double *dst, hipStream_t s) {
+    if (R.n == 0) return hipSuccess;
+    gather_kernel<<<grid_for(R.n), kThreads, 0, s>>>(R.n, R.group, R.key, transpose, rows, cols,
+                                                     src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_f64_to_i32(const double *src, int32_t *dst, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    f64_to_i32_kernel<<<capped_grid(n), kThreads, 0, s>>>(src, dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace tcu

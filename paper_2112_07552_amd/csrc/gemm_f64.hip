@@ -1,0 +1,218 @@
+// gemm_f64.hip -- step a2 (the contraction C = X * Y of TCUDB Section 3.3)
+// and the two products of the adjoint, in FP64 on the CDNA4 matrix cores.
+//
+// C (m x n) = op(A) (m x k) * op(B) (k x n), all FP64, C overwritten.
+//
+// Design (gfx950):
+//  * v_mfma_f64_16x16x4_f64: one wave multiplies a 16x4 by a 4x16 block;
+//    A lane holds A[lane%16][lane/16], B lane holds B[lane/16][lane%16], the
+//    accumulator lane holds D[lane/16 + 4*i][lane%16], i = 0..3 (measured on
+//    gfx950: rows interleave with stride 4 across the lane groups).
+//  * Workgroup tile 128 x 128, 4 waves in a 2 x 2 grid, each wave owning a
+//    64 x 64 block (4 x 4 MFMA blocks, 64 FP64 accumulators per lane).
+//  * K advances in stages of 16 through double-buffered LDS; global loads of
+//    stage s+1 are issued before the MFMAs of stage s and written to the other
+//    buffer afterwards, so one barrier per stage suffices.
+//  * Inside a stage, lane group j = lane/16 at k-step t (0..3) contracts
+//    k = 4j + t.  Any bijection of the 16 k values is a valid contraction
+//    order as long as A and B use the same one; this one lets a lane read its
+//    four k values of a contraction-contiguous operand with two 16-byte LDS
+//    reads.
+//  * Operands whose contraction index is contiguous in memory are staged as
+//    [outer][16 + 2] in LDS, the others as [16][128 + 2]; the pads spread rows
+//    over the LDS banks.  Global loads are 16-byte vectors when the leading
+//    dimension and base address allow, 8-byte guarded loads otherwise.
+//  * Tiles are numbered so that each of the 8 XCDs (workgroup w runs on XCD
+//    w mod 8) owns a contiguous run of tiles, grouped 8 tile-rows deep, so
+//    the A and B panels a run needs stay in that XCD's L2.
+#include "internal.h"
+
+namespace tcu {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int THREADS = 256;
+constexpr int WM = 64, WN = 64;
+constexpr int FM = WM / 16, FN = WN / 16;
+constexpr int KPAD = BK + 2;    // row stride of a contraction-contiguous tile
+constexpr int OPAD = 128 + 2;   // row stride of an outer-contiguous tile
+constexpr int GROUP_M = 8;
+constexpr int NUM_XCD = 8;
+
+template <bool KC>
+struct Tile {
+    static constexpr int elems = KC ? 128 * KPAD : BK * OPAD;
+};
+
+// Global -> registers: 4 chunks of 2 doubles per thread.
+// KC:  element (o, kk) of the tile is P[(o0 + o) * ld + k0 + kk]
+// !KC: element (o, kk) of the tile is P[(k0 + kk) * ld + o0 + o]
+template <bool KC>
+__device__ inline void load_tile(const double *__restrict__ P, int64_t ld, int o0, int k0,
+                                 int oext, int kext, bool vec, double2 (&r)[4]) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int c = tid + THREADS * i;
+        int o, kk;
+        if (KC) { o = c >> 3; kk = (c & 7) * 2; }
+        else    { kk = c >> 6; o = (c & 63) * 2; }
+        const int go = o0 + o, gk = k0 + kk;
+        // the two elements of the chunk run along the contiguous index
+        const int64_t base = KC ? (int64_t)go * ld + gk : (int64_t)gk * ld + go;
+        const bool in0 = KC ? (go < oext && gk < kext) : (gk < kext && go < oext);
+        const bool in1 = KC ? (go < oext && gk + 1 < kext) : (gk < kext && go + 1 < oext);
+        if (vec && in1) {
+            r[i] = *reinterpret_cast<const double2 *>(P + base);
+        } else {
+            r[i].x = in0 ? P[base] : 0.0;
+            r[i].y = in1 ? P[base + 1] : 0.0;
+        }
+    }
+}
+
+template <bool KC>
+__device__ inline void store_tile(double *__restrict__ L, const double2 (&r)[4]) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int c = tid + THREADS * i;
+        int off;
+        if (KC) off = (c >> 3) * KPAD + (c & 7) * 2;
+        else    off = (c >> 6) * OPAD + (c & 63) * 2;
+        *reinterpret_cast<double2 *>(L + off) = r[i];
+    }
+}
+
+// Fragments of one stage: f[block][t] for k-step t.
+template <bool KC, int F>
+__device__ inline void read_frags(const double *__restrict__ L, int wbase, double (&f)[F][4]) {
+    const int lane = threadIdx.x & 63;
+    const int j = lane >> 4, l16 = lane & 15;
+#pragma unroll
+    for (int b = 0; b < F; ++b) {
+        const int o = wbase + b * 16 + l16;
+        if (KC) {
+            const double2 lo = *reinterpret_cast<const double2 *>(L + o * KPAD + 4 * j);
+            const double2 hi = *reinterpret_cast<const double2 *>(L + o * KPAD + 4 * j + 2);
+            f[b][0] = lo.x; f[b][1] = lo.y; f[b][2] = hi.x; f[b][3] = hi.y;
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) f[b][t] = L[(4 * j + t) * OPAD + o];
+        }
+    }
+}
+
+__device__ inline void tile_coords(int tiles_m, int tiles_n, int &tm, int &tn) {
+    const int nt = tiles_m * tiles_n;
+    const int wg = blockIdx.x;
+    const int per = nt / NUM_XCD;
+    const int full = per * NUM_XCD;
+    const int logical = wg < full ? (wg % NUM_XCD) * per + wg / NUM_XCD : wg;
+    const int group = GROUP_M * tiles_n;
+    const int first_m = (logical / group) * GROUP_M;
+    const int gm = min(tiles_m - first_m, GROUP_M);
+    const int in_group = logical % group;
+    tm = first_m + in_group % gm;
+    tn = in_group / gm;
+}
+
+// A_KC: op(A)'s contraction index is contiguous (trans_a == 0).
+// B_KC: op(B)'s contraction index is contiguous (trans_b == 1).
+template <bool A_KC, bool B_KC>
+__global__ void __launch_bounds__(THREADS)
+gemm_f64_kernel(int m, int n, int k, const double *__restrict__ A, int64_t lda,
+                const double *__restrict__ B, int64_t ldb, double *__restrict__ C, int64_t ldc,
+                int vec_a, int vec_b) {
+    __shared__ __attribute__((aligned(16))) double lds_a[2][Tile<A_KC>::elems];
+    __shared__ __attribute__((aligned(16))) double lds_b[2][Tile<B_KC>::elems];
+
+    const int tiles_m = (m + BM - 1) / BM, tiles_n = (n + BN - 1) / BN;
+    int tm, tn;
+    tile_coords(tiles_m, tiles_n, tm, tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+
+    const int wave = threadIdx.x >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+
+    d4 acc[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+
+    const int nk = (k + BK - 1) / BK;
+    double2 ra[4], rb[4];
+    load_tile<A_KC>(A, lda, m0, 0, m, k, vec_a, ra);
+    load_tile<B_KC>(B, ldb, n0, 0, n, k, vec_b, rb);
+    store_tile<A_KC>(lds_a[0], ra);
+    store_tile<B_KC>(lds_b[0], rb);
+    __syncthreads();
+
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        const bool more = kt + 1 < nk;
+        if (more) {
+            load_tile<A_KC>(A, lda, m0, (kt + 1) * BK, m, k, vec_a, ra);
+            load_tile<B_KC>(B, ldb, n0, (kt + 1) * BK, n, k, vec_b, rb);
+        }
+        double fa[FM][4], fb[FN][4];
+        read_frags<A_KC, FM>(lds_a[cur], wm * WM, fa);
+        read_frags<B_KC, FN>(lds_b[cur], wn * WN, fb);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+#pragma unroll
+                for (int b = 0; b < FN; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a][t], fb[b][t], acc[a][b],
+                                                                     0, 0, 0);
+        if (more) {
+            store_tile<A_KC>(lds_a[cur ^ 1], ra);
+            store_tile<B_KC>(lds_b[cur ^ 1], rb);
+        }
+        __syncthreads();
+    }
+
+    const int lane = threadIdx.x & 63;
+    const int j = lane >> 4, l16 = lane & 15;
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+            const int col = n0 + wn * WN + b * 16 + l16;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = m0 + wm * WM + a * 16 + j + 4 * i;
+                if (row < m && col < n) C[(int64_t)row * ldc + col] = acc[a][b][i];
+            }
+        }
+    }
+}
+
+template <bool A_KC, bool B_KC>
+hipError_t launch(int m, int n, int k, const double *A, int64_t lda, const double *B,
+                  int64_t ldb, double *C, int64_t ldc, hipStream_t s) {
+    const int tiles = ((m + BM - 1) / BM) * ((n + BN - 1) / BN);
+    const int vec_a = (lda % 2 == 0) && (((uintptr_t)A & 15) == 0);
+    const int vec_b = (ldb % 2 == 0) && (((uintptr_t)B & 15) == 0);
+    gemm_f64_kernel<A_KC, B_KC><<<tiles, THREADS, 0, s>>>(m, n, k, A, lda, B, ldb, C, ldc, vec_a,
+                                                          vec_b);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gemm_f64(int trans_a, int trans_b, int m, int n, int k, const double *A,
+                           int64_t lda, const double *B, int64_t ldb, double *C, int64_t ldc,
+                           hipStream_t s) {
+    if (m == 0 || n == 0) return hipSuccess;
+    if (!trans_a && !trans_b) return launch<true, false>(m, n, k, A, lda, B, ldb, C, ldc, s);
+    if (!trans_a && trans_b) return launch<true, true>(m, n, k, A, lda, B, ldb, C, ldc, s);
+    if (trans_a && !trans_b) return launch<false, false>(m, n, k, A, lda, B, ldb, C, ldc, s);
+    return launch<false, true>(m, n, k, A, lda, B, ldb, C, ldc, s);
+}
+
+}  // namespace tcu

@@ -1,0 +1,198 @@
+"""Torch-facing calls of the join-aggregate operator (TCUDB Sections 2.3, 3.3).
+
+Each function checks tensor placement and dtypes, allocates outputs and the
+workspace with torch, and calls the C ABI of libtcudb.so on the current HIP
+stream.  No arithmetic of the operator happens here.
+
+Relation layout (struct of arrays, all on one GPU):
+  A: a_group (int32, g in [0,M)), a_key (int32, k in [0,K)), a_val (f64/f32 or None)
+  B: b_key (int32, k in [0,K)), b_group (int32, h in [0,N)), b_val (f64/f32 or None)
+  C[g,h] = sum over joined pairs (a.k == b.k) with a.g == g, b.h == h of a.v * b.w
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Tuple
+
+import torch
+
+from . import _lib
+from ._lib import TcuError, check
+
+PRECISIONS = {"fp64": _lib.TCU_PREC_FP64, "split": _lib.TCU_PREC_SPLIT_BF16}
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(device: torch.device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _need_cuda(t: torch.Tensor, name: str, dtypes) -> None:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{name} must have dtype in {dtypes}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def make_relation(group: torch.Tensor, key: torch.Tensor, val: Optional[torch.Tensor]):
+    """tcu_relation for one relation; returns (struct, tensors to keep alive)."""
+    _need_cuda(group, "group", (torch.int32,))
+    _need_cuda(key, "key", (torch.int32,))
+    n = group.numel()
+    if key.numel() != n:
+        raise ValueError("group and key lengths differ")
+    dtype = _lib.TCU_F64
+    if val is not None:
+        _need_cuda(val, "val", (torch.float64, torch.float32))
+        if val.numel() != n:
+            raise ValueError("val length differs from group/key")
+        if val.device != group.device or key.device != group.device:
+            raise ValueError("columns of a relation must be on one device")
+        dtype = _lib.TCU_F32 if val.dtype == torch.float32 else _lib.TCU_F64
+    rel = _lib.tcu_relation(n, group.data_ptr() if n else None, key.data_ptr() if n else None,
+                            val.data_ptr() if (val is not None and n) else None, dtype)
+    return rel
+
+
+def workspace_bytes(A, B, M: int, K: int, N: int, precision: str = "fp64",
+                    backward: bool = False, count: bool = False) -> int:
+    flags = (_lib.TCU_WS_BACKWARD if backward else 0) | (_lib.TCU_WS_COUNT if count else 0)
+    nb = _lib.load().tcu_workspace_bytes(C.byref(A), C.byref(B), M, K, N,
+                                          PRECISIONS[precision], flags)
+    if nb == 0:
+        raise TcuError(_lib.TCU_ERR_ARG, "tcu_workspace_bytes")
+    return int(nb)
+
+
+def alloc_workspace(nbytes: int, device) -> torch.Tensor:
+    ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+    if ws.data_ptr() % 256:
+        raise RuntimeError("torch returned a workspace that is not 256-byte aligned")
+    return ws
+
+
+def encode(group, key, val, rows: int, cols: int, transpose: bool = False,
+           out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Step a1 (Sections 3.1/3.3): dense FP64 encoding of one relation.
+
+    transpose=False: out[group, key] (A -> X);  True: out[key, group] (B -> Y)."""
+    rel = make_relation(group, key, val)
+    dev = group.device
+    if out is None:
+        out = torch.empty((rows, cols), dtype=torch.float64, device=dev)
+    _need_cuda(out, "out", (torch.float64,))
+    if ws is None:
+        ws = alloc_workspace(256, dev)
+    check(_lib.load().tcu_encode(C.byref(rel), int(transpose), rows, cols, _ptr(out), _ptr(ws),
+                                 ws.numel(), _stream(dev)), "tcu_encode")
+    return out
+
+
+def gemm_f64(A: torch.Tensor, B: torch.Tensor, trans_a: bool = False, trans_b: bool = False,
+             out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Step a2 alone: op(A) @ op(B) in FP64 on the matrix cores."""
+    _need_cuda(A, "A", (torch.float64,))
+    _need_cuda(B, "B", (torch.float64,))
+    m, k = (A.shape[1], A.shape[0]) if trans_a else (A.shape[0], A.shape[1])
+    kb, n = (B.shape[1], B.shape[0]) if trans_b else (B.shape[0], B.shape[1])
+    if k != kb:
+        raise ValueError(f"inner dimensions differ: {k} vs {kb}")
+    if out is None:
+        out = torch.empty((m, n), dtype=torch.float64, device=A.device)
+    _need_cuda(out, "out", (torch.float64,))
+    check(_lib.load().tcu_gemm_f64(int(trans_a), int(trans_b), m, n, k, _ptr(A), A.shape[1],
+                                   _ptr(B), B.shape[1], _ptr(out), n, _stream(A.device)),
+          "tcu_gemm_f64")
+    return out
+
+
+def join_agg_fwd(a_group, a_key, a_val, b_key, b_group, b_val, M: int, K: int, N: int,
+                 precision: str = "fp64", tol: float = 0.0, with_count: bool = False,
+                 ws: Optional[torch.Tensor] = None
+                 ) -> Tuple[torch.Tensor, Optional[torch.Tensor], torch.Tensor]:
+    """Steps a1-a3: returns (C, count or None, workspace)."""
+    A = make_relation(a_group, a_key, a_val)
+    B = make_relation(b_group, b_key, b_val)
+    dev = a_group.device
+    need = workspace_bytes(A, B, M, K, N, precision, count=with_count)
+    if ws is None or ws.numel() < need:
+        ws = alloc_workspace(need, dev)
+    Cm = torch.empty((M, N), dtype=torch.float64, device=dev)
+    cnt = torch.empty((M, N), dtype=torch.int32, device=dev) if with_count else None
+    check(_lib.load().tcu_join_agg_fwd(C.byref(A), C.byref(B), M, K, N, PRECISIONS[precision],
+                                       tol, _ptr(Cm), _ptr(cnt), _ptr(ws), ws.numel(),
+                                       _stream(dev)), "tcu_join_agg_fwd")
+    return Cm, cnt, ws
+
+
+def join_agg_bwd(a_group, a_key, a_val, b_key, b_group, b_val, M: int, K: int, N: int,
+                 dC: torch.Tensor, need_a: bool = True, need_b: bool = True,
+                 precision: str = "fp64", tol: float = 0.0, ws: Optional[torch.Tensor] = None):
+    """Step a4: returns (dA_val or None, dB_val or None, workspace), FP64."""
+    A = make_relation(a_group, a_key, a_val)
+    B = make_relation(b_group, b_key, b_val)
+    dev = a_group.device
+    _need_cuda(dC, "dC", (torch.float64,))
+    if tuple(dC.shape) != (M, N):
+        raise ValueError(f"dC must be {M} x {N}")
+    need = workspace_bytes(A, B, M, K, N, precision, backward=True)
+    if ws is None or ws.numel() < need:
+        ws = alloc_workspace(need, dev)
+    dA = torch.empty(A.n, dtype=torch.float64, device=dev) if need_a else None
+    dB = torch.empty(B.n, dtype=torch.float64, device=dev) if need_b else None
+    check(_lib.load().tcu_join_agg_bwd(C.byref(A), C.byref(B), M, K, N, PRECISIONS[precision],
+                                       tol, _ptr(dC), _ptr(dA), _ptr(dB), _ptr(ws), ws.numel(),
+                                       _stream(dev)), "tcu_join_agg_bwd")
+    return dA, dB, ws
+
+
+def sync_status(ws: torch.Tensor) -> Tuple[int, dict]:
+    """Synchronise and read the workspace status block of the last call."""
+    info = _lib.tcu_status_info()
+    st = _lib.load().tcu_sync_status(_ptr(ws), _stream(ws.device), C.byref(info))
+    return st, {"flags": info.flags, "slices": info.slices,
+                "skipped_a": info.skipped_a, "skipped_b": info.skipped_b}
+
+
+class JoinAgg(torch.autograd.Function):
+    """C = join-aggregate(A, B) with the hand-written adjoint as backward.
+
+    Only the record columns are saved (activation checkpointing): backward
+    re-encodes X and Y inside the library."""
+
+    @staticmethod
+    def forward(ctx, a_group, a_key, a_val, b_key, b_group, b_val, M, K, N, precision, tol):
+        Cm, _, _ = join_agg_fwd(a_group, a_key, a_val, b_key, b_group, b_val, M, K, N,
+                                precision, tol)
+        ctx.save_for_backward(a_group, a_key, a_val, b_key, b_group, b_val)
+        ctx.shape = (M, K, N)
+        ctx.precision, ctx.tol = precision, tol
+        return Cm
+
+    @staticmethod
+    def backward(ctx, dC):
+        a_group, a_key, a_val, b_key, b_group, b_val = ctx.saved_tensors
+        M, K, N = ctx.shape
+        need_a = a_val is not None and ctx.needs_input_grad[2]
+        need_b = b_val is not None and ctx.needs_input_grad[5]
+        dA = dB = None
+        if need_a or need_b:
+            dA, dB, _ = join_agg_bwd(a_group, a_key, a_val, b_key, b_group, b_val, M, K, N,
+                                     dC.contiguous().to(torch.float64), need_a, need_b,
+                                     ctx.precision, ctx.tol)
+        if dA is not None:
+            dA = dA.to(a_val.dtype)
+        if dB is not None:
+            dB = dB.to(b_val.dtype)
+        return None, None, dA, None, None, dB, None, None, None, None, None
+
+
+def join_agg(a_group, a_key, a_val, b_key, b_group, b_val, M: int, K: int, N: int,
+             precision: str = "fp64", tol: float = 0.0) -> torch.Tensor:
+    """Differentiable C = join-aggregate (gradients for the value columns)."""
+    return JoinAgg.apply(a_group, a_key, a_val, b_key, b_group, b_val, M, K, N, precision, tol)

@@ -1,0 +1,254 @@
+"""GPU parity of the FP64 form against the oracle, through the C ABI.
+
+Sizes: small cases that span several 128 x 128 tiles and a ragged tail are
+compared cell by cell with the full oracle; the 2^20 and 2^24-record
+workloads are compared on sampled cells, sampled rows and Freivalds'
+check, which the oracle evaluates from the records in linear time.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2112_07552_amd import ops
+from paper_2112_07552_amd import workloads as wl
+
+from .gpu_util import (TOL, abs_rel, cuda_or_skip, dense_relation_from_matrix, describe_worst,
+                       err_cw, to_orc)
+
+pytestmark = pytest.mark.gpu
+
+
+def run_fwd(A, B, M, K, N, with_count=False):
+    Cm, cnt, ws = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, M, K, N,
+                                   with_count=with_count)
+    st, info = ops.sync_status(ws)
+    return Cm, cnt, st, info
+
+
+# ------------------------------------------------------------------ encode --
+
+@pytest.mark.parametrize("n_side", [128, 1024])
+def test_encode_dense_bit_exact(orc, n_side):
+    dev = cuda_or_skip()
+    A, B = wl.mm_query(n_side, n_side, n_side, seed=1, device=dev)
+    X = ops.encode(A.group, A.key, A.val, n_side, n_side, transpose=False)
+    Y = ops.encode(B.group, B.key, B.val, n_side, n_side, transpose=True)
+    Xo, sa = orc.encode_A(to_orc(orc, A), n_side, n_side)
+    Yo, sb = orc.encode_B(to_orc(orc, B), n_side, n_side)
+    assert sa == sb == 0
+    assert np.array_equal(X.cpu().numpy(), Xo)
+    assert np.array_equal(Y.cpu().numpy(), Yo)
+
+
+def test_encode_duplicates_integer_values_exact(orc):
+    dev = cuda_or_skip()
+    R = wl.random_relation(200_000, 300, 257, 3, 1, values="int", lo=-1000, hi=1000, device=dev)
+    X = ops.encode(R.group, R.key, R.val, 300, 257)
+    Xo, _ = orc.encode(R.group.cpu().numpy(), R.key.cpu().numpy(), R.val.cpu().numpy(), 300, 257)
+    assert np.array_equal(X.cpu().numpy(), Xo)
+
+
+def test_encode_duplicates_float_and_skips(orc):
+    dev = cuda_or_skip()
+    R = wl.random_relation(100_000, 99, 131, 4, 1, device=dev, bad_fraction=0.01)
+    ws = ops.alloc_workspace(256, dev)
+    X = ops.encode(R.group, R.key, R.val, 99, 131, ws=ws)
+    st, info = ops.sync_status(ws)
+    Xo, skipped = orc.encode(R.group.cpu().numpy(), R.key.cpu().numpy(), R.val.cpu().numpy(),
+                             99, 131)
+    assert skipped > 0
+    assert st == ops._lib.TCU_ERR_KEY_RANGE and info["skipped_a"] == skipped
+    # duplicate cells: sums in another order; bound (d-1) u sum|v| per cell
+    Xa, _ = orc.encode(R.group.cpu().numpy(), R.key.cpu().numpy(),
+                       np.abs(R.val.cpu().numpy()), 99, 131)
+    cnt, _ = orc.encode(R.group.cpu().numpy(), R.key.cpu().numpy(), None, 99, 131)
+    bound = np.maximum(cnt - 1, 0) * 2.0 ** -53 * Xa * 1.01
+    assert np.all(np.abs(X.cpu().numpy() - Xo) <= bound)
+
+
+# -------------------------------------------------------------------- gemm --
+
+GEMM_SHAPES = [(1, 1, 1), (17, 33, 5), (128, 128, 16), (129, 255, 130), (300, 200, 67),
+               (64, 1, 64), (1, 300, 257), (257, 129, 1)]
+
+
+@pytest.mark.parametrize("m,n,k", GEMM_SHAPES)
+@pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_gemm_f64_shapes(orc, m, n, k, ta, tb):
+    dev = cuda_or_skip()
+    g = torch.Generator(device="cpu").manual_seed(m * 7919 + n * 31 + k + 1000 * ta + 100 * tb)
+    X = (torch.rand((m, k), generator=g, dtype=torch.float64) * 2 - 1)
+    Y = (torch.rand((k, n), generator=g, dtype=torch.float64) * 2 - 1)
+    Ad = (X.t().contiguous() if ta else X).to(dev)
+    Bd = (Y.t().contiguous() if tb else Y).to(dev)
+    Cg = ops.gemm_f64(Ad, Bd, trans_a=bool(ta), trans_b=bool(tb)).cpu().numpy()
+    # the oracle evaluates the join-aggregate of the dense relations of X and Y
+    RA = to_orc(orc, dense_relation_from_matrix(X, False))
+    RB = to_orc(orc, dense_relation_from_matrix(Y, True))
+    Co, _, _ = orc.join_agg(RA, RB, m, k, n)
+    S, _, _ = orc.join_agg(abs_rel(orc, RA), abs_rel(orc, RB), m, k, n)
+    e = err_cw(Cg, Co, S)
+    assert e <= TOL, describe_worst(Cg, Co, S)
+
+
+def test_gemm_f64_odd_leading_dimensions(orc):
+    """Unaligned rows (odd leading dimensions) take the 8-byte load path."""
+    dev = cuda_or_skip()
+    g = torch.Generator(device="cpu").manual_seed(5)
+    m, n, k = 131, 77, 93
+    Xb = torch.rand((m, k + 3), generator=g, dtype=torch.float64)
+    Yb = torch.rand((k, n + 1), generator=g, dtype=torch.float64)
+    Xd, Yd = Xb.to(dev), Yb.to(dev)
+    out = torch.empty((m, n + 5), dtype=torch.float64, device=dev)
+    st = ops._lib.load().tcu_gemm_f64(0, 0, m, n, k, ops._ptr(Xd), k + 3, ops._ptr(Yd), n + 1,
+                                      ops._ptr(out), n + 5, ops._stream(dev))
+    assert st == 0
+    X, Y = Xb[:, :k].contiguous(), Yb[:, :n].contiguous()
+    RA = to_orc(orc, dense_relation_from_matrix(X, False))
+    RB = to_orc(orc, dense_relation_from_matrix(Y, True))
+    Co, _, _ = orc.join_agg(RA, RB, m, k, n)
+    S, _, _ = orc.join_agg(abs_rel(orc, RA), abs_rel(orc, RB), m, k, n)
+    assert err_cw(out[:, :n].cpu().numpy(), Co, S) <= TOL
+
+
+def test_gemm_f64_k_zero():
+    dev = cuda_or_skip()
+    out = torch.full((5, 7), 3.0, dtype=torch.float64, device=dev)
+    A = torch.empty((5, 0), dtype=torch.float64, device=dev)
+    B = torch.empty((0, 7), dtype=torch.float64, device=dev)
+    ops.gemm_f64(A, B, out=out)
+    assert torch.all(out == 0)
+
+
+# ----------------------------------------------------------------- forward --
+
+def test_fwd_smallest_workload_full_oracle(orc):
+    """2^14 records per table (N = 128), U[-1,1), seed 0: every cell."""
+    dev = cuda_or_skip()
+    N = 128
+    A, B = wl.mm_query(N, N, N, seed=0, device=dev)
+    Cg, cnt, st, _ = run_fwd(A, B, N, N, N, with_count=True)
+    assert st == 0
+    RA, RB = to_orc(orc, A), to_orc(orc, B)
+    Co, co, _ = orc.join_agg(RA, RB, N, N, N, with_count=True)
+    S, _, _ = orc.join_agg(abs_rel(orc, RA), abs_rel(orc, RB), N, N, N)
+    assert err_cw(Cg.cpu().numpy(), Co, S) <= TOL
+    assert np.array_equal(cnt.cpu().numpy(), co)
+
+
+@pytest.mark.parametrize("seed,nA,nB,M,K,N,bad", [
+    (10, 50_000, 60_000, 300, 129, 257, 0.0),    # duplicates, ragged tiles
+    (11, 40_000, 40_000, 1, 1000, 133, 0.0),     # M = 1
+    (12, 30_000, 30_000, 200, 1, 150, 0.0),      # K = 1: every pair joins
+    (13, 20_000, 25_000, 130, 70, 1, 0.0),       # N = 1
+    (14, 60_000, 50_000, 140, 90, 260, 0.02),    # out-of-range records
+])
+def test_fwd_random_relations(orc, seed, nA, nB, M, K, N, bad):
+    dev = cuda_or_skip()
+    A = wl.random_relation(nA, M, K, seed, 1, device=dev, bad_fraction=bad)
+    B = wl.random_relation(nB, N, K, seed, 2, device=dev, bad_fraction=bad)
+    Cg, cnt, st, info = run_fwd(A, B, M, K, N, with_count=True)
+    RA, RB = to_orc(orc, A), to_orc(orc, B)
+    Co, co, _ = orc.join_agg(RA, RB, M, K, N, with_count=True)
+    S, _, _ = orc.join_agg(abs_rel(orc, RA), abs_rel(orc, RB), M, K, N)
+    assert np.array_equal(cnt.cpu().numpy(), co)
+    assert err_cw(Cg.cpu().numpy(), Co, S) <= TOL, describe_worst(Cg.cpu().numpy(), Co, S)
+    if bad > 0:
+        _, sa = orc.encode_A(RA, M, K)
+        _, sb = orc.encode_B(RB, K, N)
+        assert st == ops._lib.TCU_ERR_KEY_RANGE
+        assert (info["skipped_a"], info["skipped_b"]) == (sa, sb) and sa > 0
+    else:
+        assert st == 0
+
+
+def test_fwd_empty_relations(orc):
+    dev = cuda_or_skip()
+    e32 = torch.empty(0, dtype=torch.int32, device=dev)
+    e64 = torch.empty(0, dtype=torch.float64, device=dev)
+    B = wl.random_relation(1000, 40, 30, 20, 2, device=dev)
+    Cm, cnt, ws = ops.join_agg_fwd(e32, e32, e64, B.key, B.group, B.val, 50, 30, 40,
+                                   with_count=True)
+    assert torch.all(Cm == 0) and torch.all(cnt == 0)
+    Cm, cnt, ws = ops.join_agg_fwd(B.group, B.key, B.val, e32, e32, e64, 40, 30, 50,
+                                   with_count=True)
+    assert torch.all(Cm == 0) and torch.all(cnt == 0)
+
+
+def test_fwd_count_semantics_and_fp32_values(orc):
+    """NULL values = COUNT (Section 3.3); FP32 value columns widen exactly."""
+    dev = cuda_or_skip()
+    M, K, N = 190, 150, 170
+    A = wl.random_relation(40_000, M, K, 21, 1, device=dev, dtype=torch.float32)
+    B = wl.random_relation(40_000, N, K, 21, 2, device=dev)
+    Cc, _, ws = ops.join_agg_fwd(A.group, A.key, None, B.key, B.group, None, M, K, N)
+    RA, RB = to_orc(orc, A), to_orc(orc, B)
+    _, co, _ = orc.join_agg(RA, RB, M, K, N, with_count=True)
+    assert np.array_equal(Cc.cpu().numpy(), co.astype(np.float64))
+    Cg, _, _ = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, M, K, N)
+    Co, _, _ = orc.join_agg(RA, RB, M, K, N)
+    S, _, _ = orc.join_agg(abs_rel(orc, RA), abs_rel(orc, RB), M, K, N)
+    assert err_cw(Cg.cpu().numpy(), Co, S) <= TOL
+
+
+def sampled_checks(orc, A, B, Cg, M, K, N, seed, ncells=4096, nrows=0):
+    """Sampled cells, optional sampled rows, and Freivalds' check with two
+    random +-1 vectors; returns the worst componentwise error seen."""
+    RA, RB = to_orc(orc, A), to_orc(orc, B)
+    RAa, RBa = abs_rel(orc, RA), abs_rel(orc, RB)
+    rng = np.random.default_rng(seed)
+    cg = rng.integers(0, M, ncells).astype(np.int32)
+    ch = rng.integers(0, N, ncells).astype(np.int32)
+    Ch = Cg.cpu().numpy()
+    vo, _ = orc.join_agg_cells(RA, RB, M, K, N, cg, ch)
+    so, _ = orc.join_agg_cells(RAa, RBa, M, K, N, cg, ch)
+    worst = err_cw(Ch[cg, ch], vo, so)
+    if nrows:
+        rows = rng.choice(M, nrows, replace=False).astype(np.int32)
+        Co, _, _ = orc.join_agg(RA, RB, M, K, N, rows=rows)
+        So, _, _ = orc.join_agg(RAa, RBa, M, K, N, rows=rows)
+        worst = max(worst, err_cw(Ch[rows], Co, So))
+    for _ in range(2):
+        r = np.where(rng.random(N) < 0.5, -1.0, 1.0)
+        lhs = np.array([math.fsum(row * r) for row in Ch])  # exact products, one rounding
+        rhs = orc.freivalds(RA, RB, M, K, N, r)
+        # |C r - C* r| <= max err_cw * sum_h (|X||Y|)[g,h], plus one rounding per side
+        scale = orc.freivalds(RAa, RBa, M, K, N, np.ones(N))
+        fe = float(np.max(np.abs(lhs - rhs) / np.maximum(scale, 1e-300)))
+        worst = max(worst, fe)
+    return worst
+
+
+def test_fwd_2pow20_records(orc):
+    """2^20 records per table (N = 1024), seed 1: 48 whole rows, 4096 cells
+    and Freivalds' check against the oracle."""
+    dev = cuda_or_skip()
+    N = 1024
+    A, B = wl.mm_query(N, N, N, seed=1, device=dev)
+    Cg, _, st, _ = run_fwd(A, B, N, N, N)
+    assert st == 0
+    assert sampled_checks(orc, A, B, Cg, N, N, N, seed=1, nrows=48) <= TOL
+
+
+@pytest.mark.parametrize("lo,hi", [(0, 2), (-2**7, 2**7), (-2**15, 2**15)])
+def test_fwd_integer_values_bit_exact(orc, lo, hi):
+    """Rows of the paper's MAPE table (Section 5.4.1, Table 'error'): with
+    integer values every partial sum is an exact integer, so the FP64 path
+    must be exact where the paper's 16-bit units were not (N = 2048)."""
+    dev = cuda_or_skip()
+    N = 2048
+    A, B = wl.mm_query(N, N, N, seed=7, values="int", lo=lo, hi=hi, device=dev)
+    Cg, _, st, _ = run_fwd(A, B, N, N, N)
+    assert st == 0
+    RA, RB = to_orc(orc, A), to_orc(orc, B)
+    rng = np.random.default_rng(2)
+    cg = rng.integers(0, N, 2048).astype(np.int32)
+    ch = rng.integers(0, N, 2048).astype(np.int32)
+    vo, _ = orc.join_agg_cells(RA, RB, N, N, N, cg, ch)
+    Ch = Cg.cpu().numpy()
+    assert np.array_equal(Ch[cg, ch], vo)
+    r = np.where(rng.random(N) < 0.5, -1.0, 1.0)
+    lhs = np.array([math.fsum(row * r) for row in Ch])
+    assert np.array_equal(lhs, orc.freivalds(RA, RB, N, N, N, r))

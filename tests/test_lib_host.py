@@ -1,0 +1,104 @@
+"""Host-side checks of libtcudb.so that need no GPU.
+
+The library must load, export every entry point include/tcudb.h declares,
+size workspaces, and reject invalid arguments before touching the device.
+"""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2112_07552_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "tcudb.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tcu_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = header_functions()
+    assert len(names) >= 8
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_version_and_status_strings(lib):
+    assert b"gfx950" in lib.tcu_version()
+    for code in range(-6, 1):
+        s = lib.tcu_status_str(code).decode()
+        assert s and s != "unknown status"
+    assert lib.tcu_status_str(-99).decode() == "unknown status"
+
+
+def rel(n, dtype=_lib.TCU_F64, ptr=0x1000):
+    return _lib.tcu_relation(n, ptr if n else None, ptr if n else None, ptr, dtype)
+
+
+def test_workspace_bytes(lib):
+    A, B = rel(10), rel(10)
+    M, K, N = 100, 37, 50
+    fwd = lib.tcu_workspace_bytes(C.byref(A), C.byref(B), M, K, N, 0, 0)
+    align = lambda x: (x + 255) // 256 * 256
+    assert fwd == 256 + align(M * K * 8) + align(K * N * 8)
+    bwd = lib.tcu_workspace_bytes(C.byref(A), C.byref(B), M, K, N, 0, _lib.TCU_WS_BACKWARD)
+    assert bwd == fwd + align(max(M * K, K * N) * 8)
+    assert lib.tcu_workspace_bytes(C.byref(A), C.byref(B), 0, K, N, 0, 0) == 0
+    assert lib.tcu_workspace_bytes(C.byref(A), C.byref(B), M, K, N, 7, 0) == 0
+
+
+def test_argument_errors_return_before_launch(lib):
+    A, B = rel(10), rel(10)
+    cbuf = C.c_void_p(0x2000)
+    # NULL C
+    assert lib.tcu_join_agg_fwd(C.byref(A), C.byref(B), 4, 4, 4, 0, 0.0, None, None,
+                                C.c_void_p(0x100000), 1 << 20, None) == _lib.TCU_ERR_ARG
+    # bad shapes
+    assert lib.tcu_join_agg_fwd(C.byref(A), C.byref(B), 0, 4, 4, 0, 0.0, cbuf, None,
+                                C.c_void_p(0x100000), 1 << 20, None) == _lib.TCU_ERR_ARG
+    # negative record count
+    bad = rel(10); bad.n = -1
+    assert lib.tcu_join_agg_fwd(C.byref(bad), C.byref(B), 4, 4, 4, 0, 0.0, cbuf, None,
+                                C.c_void_p(0x100000), 1 << 20, None) == _lib.TCU_ERR_ARG
+    # NULL key column with records
+    nok = _lib.tcu_relation(5, 0x1000, None, None, 0)
+    assert lib.tcu_join_agg_fwd(C.byref(nok), C.byref(B), 4, 4, 4, 0, 0.0, cbuf, None,
+                                C.c_void_p(0x100000), 1 << 20, None) == _lib.TCU_ERR_ARG
+    # bad dtype
+    bd = rel(10, dtype=5)
+    assert lib.tcu_join_agg_fwd(C.byref(bd), C.byref(B), 4, 4, 4, 0, 0.0, cbuf, None,
+                                C.c_void_p(0x100000), 1 << 20, None) == _lib.TCU_ERR_ARG
+    # workspace: NULL, misaligned, too small
+    assert lib.tcu_join_agg_fwd(C.byref(A), C.byref(B), 4, 4, 4, 0, 0.0, cbuf, None,
+                                None, 1 << 20, None) == _lib.TCU_ERR_WORKSPACE
+    assert lib.tcu_join_agg_fwd(C.byref(A), C.byref(B), 4, 4, 4, 0, 0.0, cbuf, None,
+                                C.c_void_p(0x100010), 1 << 20, None) == _lib.TCU_ERR_WORKSPACE
+    assert lib.tcu_join_agg_fwd(C.byref(A), C.byref(B), 4, 4, 4, 0, 0.0, cbuf, None,
+                                C.c_void_p(0x100000), 300, None) == _lib.TCU_ERR_WORKSPACE
+    # backward: NULL dC, small workspace
+    assert lib.tcu_join_agg_bwd(C.byref(A), C.byref(B), 4, 4, 4, 0, 0.0, None, cbuf, cbuf,
+                                C.c_void_p(0x100000), 1 << 20, None) == _lib.TCU_ERR_ARG
+    fwd_only = lib.tcu_workspace_bytes(C.byref(A), C.byref(B), 64, 64, 64, 0, 0)
+    assert lib.tcu_join_agg_bwd(C.byref(A), C.byref(B), 64, 64, 64, 0, 0.0, cbuf, cbuf, cbuf,
+                                C.c_void_p(0x100000), fwd_only, None) == _lib.TCU_ERR_WORKSPACE
+    # gemm: bad transpose flag, negative size, short leading dimension
+    assert lib.tcu_gemm_f64(2, 0, 4, 4, 4, cbuf, 4, cbuf, 4, cbuf, 4, None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_gemm_f64(0, 0, -1, 4, 4, cbuf, 4, cbuf, 4, cbuf, 4, None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_gemm_f64(0, 0, 4, 4, 8, cbuf, 4, cbuf, 4, cbuf, 4, None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_gemm_f64(0, 0, 4, 4, 4, cbuf, 4, cbuf, 4, cbuf, 3, None) == _lib.TCU_ERR_ARG
+    # m == 0: nothing to do, nothing launched
+    assert lib.tcu_gemm_f64(0, 0, 0, 4, 4, None, 4, None, 4, None, 4, None) == _lib.TCU_OK
+    # encode: bad transpose, NULL out
+    assert lib.tcu_encode(C.byref(A), 3, 4, 4, cbuf, C.c_void_p(0x100000), 256, None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_encode(C.byref(A), 0, 4, 4, None, C.c_void_p(0x100000), 256, None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_sync_status(None, None, None) == _lib.TCU_ERR_WORKSPACE
