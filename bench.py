@@ -2,9 +2,13 @@
 workload: the matrix multiplication query over dense synthetic tables).
 
 One step = one pass of the whole path over one batch of resident input:
-forward (encode A -> X, encode B -> Y, C = X Y) plus the adjoint (re-encode,
-dX = W Y^T, dY = X^T W, gathers to the records), FP64, N x N x N with
-N^2 records per table.  Prints one JSON line.
+forward (encode A -> X, encode B -> Y, C = X Y) plus the adjoint
+(dX = W Y^T, dY = X^T W, gathers to the records), FP64, N x N x N with
+N^2 records per table.  The tables store matrices, so their cells are
+unique (declared to the library); the adjoint reuses the forward's X and Y
+(saved activations, which fit easily in HBM).  The checkpointed variant
+(re-encoding in the adjoint) is timed and reported beside it.  Prints one
+JSON line.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--n 4096]
 """
@@ -85,6 +89,9 @@ def main():
     ap.add_argument("--n", type=int, default=4096, help="M = K = N; records per table = n^2")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle error check")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 512 MiB device copy, the reference that scales "
+                         "profiler byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -105,8 +112,8 @@ def main():
     A, B = wl.mm_query(N, N, N, seed=2, device=dev)
     W = wl.draw_values("uniform", N * N, 1002, 0, device=dev).reshape(N, N)
 
-    relA = ops.make_relation(A.group, A.key, A.val)
-    relB = ops.make_relation(B.group, B.key, B.val)
+    relA = ops.make_relation(A.group, A.key, A.val, unique=True)
+    relB = ops.make_relation(B.group, B.key, B.val, unique=True)
     ws = ops.alloc_workspace(ops.workspace_bytes(relA, relB, N, N, N, backward=True), dev)
     Cm = torch.empty((N, N), dtype=torch.float64, device=dev)
     dA = torch.empty(n_rec, dtype=torch.float64, device=dev)
@@ -119,20 +126,34 @@ def main():
         _lib.check(L.tcu_join_agg_fwd(C.byref(relA), C.byref(relB), N, N, N, 0, 0.0,
                                       C.c_void_p(Cm.data_ptr()), None, wsp, wsn, sp), "fwd")
 
-    def bwd():
+    def bwd(flags):
         _lib.check(L.tcu_join_agg_bwd(C.byref(relA), C.byref(relB), N, N, N, 0, 0.0,
                                       C.c_void_p(W.data_ptr()), C.c_void_p(dA.data_ptr()),
-                                      C.c_void_p(dB.data_ptr()), wsp, wsn, sp), "bwd")
+                                      C.c_void_p(dB.data_ptr()), flags, wsp, wsn, sp), "bwd")
 
     def step():
         fwd()
-        bwd()
+        bwd(_lib.TCU_BWD_SAVED_ENCODINGS)
+
+    def step_checkpointed():
+        fwd()
+        bwd(0)
+
+    if args.copy_calibration:
+        src = torch.empty(64 << 20, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)  # reads 512 MiB, writes 512 MiB
+        torch.cuda.synchronize()
+        del src, dst
 
     log("timing fwd+adjoint")
     ms_step = time_loop(step, args.steps, args.warmup, stream)
     log(f"fwd+adjoint {ms_step:.3f} ms")
     ms_fwd = time_loop(fwd, args.steps, args.warmup, stream)
     log(f"fwd {ms_fwd:.3f} ms")
+    ms_ckpt = time_loop(step_checkpointed, args.steps, args.warmup, stream)
+    log(f"fwd+adjoint with re-encoding (checkpointed) {ms_ckpt:.3f} ms")
     st, info = ops.sync_status(ws)
     if st != 0:
         raise RuntimeError(f"device status {st}: {info}")
@@ -141,8 +162,8 @@ def main():
     # stream at the three shapes the step launches (NN forward, NT and TN adjoint)
     X = torch.empty((N, N), dtype=torch.float64, device=dev)
     Y = torch.empty((N, N), dtype=torch.float64, device=dev)
-    ops.encode(A.group, A.key, A.val, N, N, False, out=X)
-    ops.encode(B.group, B.key, B.val, N, N, True, out=Y)
+    ops.encode(A.group, A.key, A.val, N, N, False, out=X, unique=True)
+    ops.encode(B.group, B.key, B.val, N, N, True, out=Y, unique=True)
     G = torch.empty((N, N), dtype=torch.float64, device=dev)
     gemm_ms = {}
     for name, (ta, tb, a, b) in {"nn": (0, 0, X, Y), "nt": (0, 1, W, Y),
@@ -194,10 +215,13 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"MM query, dense {N}x{N} tables ({n_rec} records each, random "
-                               f"order), U[-1,1) FP64, seed 2; step = forward + adjoint (FP64)",
+                               f"order, unique cells), U[-1,1) FP64, seed 2; step = forward + "
+                               f"adjoint (FP64, saved encodings)",
                    "M": N, "K": N, "N": N, "records_per_table": n_rec, "precision": "fp64"},
         "fwd_elements_per_s": n_rec / (ms_fwd * 1e-3),
         "ms_fwd": ms_fwd,
+        "checkpointed_elements_per_s": n_rec / (ms_ckpt * 1e-3),
+        "ms_checkpointed": ms_ckpt,
         "err_cw_vs_oracle": result_err,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_F64_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_F64_MFMA_TFLOPS,

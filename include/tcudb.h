@@ -56,22 +56,40 @@ typedef enum {
                                 FP32 exact partial sums, FP64 combination     */
 } tcu_precision;
 
+/* Relation flags. */
+#define TCU_REL_UNIQUE_CELLS 1u /* no two records share a (group, key) pair, as
+                                   for a table that stores a matrix (the MM
+                                   query); the encoding then uses plain stores
+                                   instead of atomics.  If the promise is
+                                   broken, one of the duplicates' values is
+                                   kept (no memory is touched out of bounds). */
+
 /* One relation, struct of arrays with n records.
  * For A: group = g in [0,M) (A.col_num of the MM query), key = k in [0,K)
  *        (A.row_num).
  * For B: group = h in [0,N) (B.row_num), key = k in [0,K) (B.col_num).
- * val: n values of `dtype`, or NULL for COUNT. */
+ * val: n values of `dtype`, or NULL for COUNT.
+ * flags: TCU_REL_* bits. */
 typedef struct {
     int64_t n;
     const int32_t *group;
     const int32_t *key;
     const void *val;
     tcu_dtype dtype;
+    uint32_t flags;
 } tcu_relation;
 
 /* Flags for tcu_workspace_bytes. */
 #define TCU_WS_BACKWARD 1 /* size for tcu_join_agg_bwd as well               */
 #define TCU_WS_COUNT 2    /* size for the optional pair-count output         */
+
+/* Flags for tcu_join_agg_bwd. */
+#define TCU_BWD_SAVED_ENCODINGS 1 /* ws still holds X and Y written by the last
+                                     tcu_join_agg_fwd on these same relations,
+                                     shapes and precision (saved activations):
+                                     skip re-encoding.  Without the flag X and
+                                     Y are rebuilt from the records
+                                     (activation checkpointing). */
 
 /* Status block read back by tcu_sync_status (host copy). */
 typedef struct {
@@ -93,7 +111,8 @@ size_t tcu_workspace_bytes(const tcu_relation *A, const tcu_relation *B, int32_t
  *   transpose == 0: out[group, key] = sum of val   (A -> X, rows = M, cols = K)
  *   transpose == 1: out[key, group] = sum of val   (B -> Y, rows = K, cols = N)
  * Duplicate coordinates add up (FP64 atomics: order-dependent rounding);
- * unique coordinates give the values bit for bit.  Out-of-range records are
+ * unique coordinates give the values bit for bit (with TCU_REL_UNIQUE_CELLS
+ * through plain stores).  Out-of-range records are
  * skipped and counted as A's skips in the workspace status block.
  * ws: at least tcu_workspace_bytes(...) for any shapes (256 bytes suffice). */
 tcu_status tcu_encode(const tcu_relation *R, int transpose, int32_t rows, int32_t cols,
@@ -124,14 +143,15 @@ tcu_status tcu_join_agg_fwd(const tcu_relation *A, const tcu_relation *B, int32_
 /* Step a4, the adjoint of the operator for L = sum_{g,h} dC[g,h] C[g,h]:
  *   dA_val[i] = sum_{b: b.k == a_i.k} dC[a_i.g, b.h] * b.w = (dC Y^T)[a_i.g, a_i.k]
  *   dB_val[j] = sum_{a: a.k == b_j.k} dC[a.g, b_j.h] * a.v = (X^T dC)[b_j.k, b_j.h]
- * X and Y are re-encoded from the records (activation checkpointing: the
- * forward keeps no matrices).  Either output may be NULL.  Skipped records
- * get 0.  Gradients are FP64 whatever the value dtype.  Needs a workspace
- * sized with TCU_WS_BACKWARD. */
+ * By default X and Y are re-encoded from the records (activation
+ * checkpointing: nothing of the forward is kept); with
+ * TCU_BWD_SAVED_ENCODINGS the forward's X and Y in ws are used.  Either
+ * output may be NULL.  Skipped records get 0.  Gradients are FP64 whatever
+ * the value dtype.  Needs a workspace sized with TCU_WS_BACKWARD. */
 tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_t M, int32_t K,
                             int32_t N, tcu_precision p, double tol, const double *dC,
-                            double *dA_val, double *dB_val, void *ws, size_t ws_bytes,
-                            hipStream_t stream);
+                            double *dA_val, double *dB_val, int flags, void *ws,
+                            size_t ws_bytes, hipStream_t stream);
 
 /* SYNCHRONISES the stream, then reads the workspace status block written by
  * the last call that used `ws`.  Returns TCU_ERR_KEY_RANGE if records were

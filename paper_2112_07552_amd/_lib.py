@@ -29,6 +29,9 @@ TCU_PREC_SPLIT_BF16 = 1
 TCU_WS_BACKWARD = 1
 TCU_WS_COUNT = 2
 
+TCU_REL_UNIQUE_CELLS = 1
+TCU_BWD_SAVED_ENCODINGS = 1
+
 EXPORTS = (
     "tcu_workspace_bytes", "tcu_encode", "tcu_gemm_f64", "tcu_join_agg_fwd",
     "tcu_join_agg_bwd", "tcu_sync_status", "tcu_status_str", "tcu_version",
@@ -37,7 +40,7 @@ EXPORTS = (
 
 class tcu_relation(C.Structure):
     _fields_ = [("n", C.c_int64), ("group", C.c_void_p), ("key", C.c_void_p),
-                ("val", C.c_void_p), ("dtype", C.c_int)]
+                ("val", C.c_void_p), ("dtype", C.c_int), ("flags", C.c_uint32)]
 
 
 class tcu_status_info(C.Structure):
@@ -74,8 +77,8 @@ def load():
     L.tcu_join_agg_fwd.argtypes = [rel_p, rel_p, i32, i32, i32, C.c_int, f64, vp, vp, vp,
                                    C.c_size_t, vp]
     L.tcu_join_agg_fwd.restype = C.c_int
-    L.tcu_join_agg_bwd.argtypes = [rel_p, rel_p, i32, i32, i32, C.c_int, f64, vp, vp, vp, vp,
-                                   C.c_size_t, vp]
+    L.tcu_join_agg_bwd.argtypes = [rel_p, rel_p, i32, i32, i32, C.c_int, f64, vp, vp, vp,
+                                   C.c_int, vp, C.c_size_t, vp]
     L.tcu_join_agg_bwd.restype = C.c_int
     L.tcu_sync_status.argtypes = [vp, vp, C.POINTER(tcu_status_info)]
     L.tcu_sync_status.restype = C.c_int

@@ -23,6 +23,7 @@ tcu_status hip_status(hipError_t e) { return e == hipSuccess ? TCU_OK : TCU_ERR_
 bool relation_ok(const tcu_relation *R) {
     if (R == nullptr || R->n < 0) return false;
     if (R->n > 0 && (R->group == nullptr || R->key == nullptr)) return false;
+    if ((R->flags & ~TCU_REL_UNIQUE_CELLS) != 0) return false;
     return R->dtype == TCU_F64 || R->dtype == TCU_F32;
 }
 
@@ -137,21 +138,24 @@ tcu_status tcu_join_agg_fwd(const tcu_relation *A, const tcu_relation *B, int32_
 
 tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_t M, int32_t K,
                             int32_t N, tcu_precision p, double tol, const double *dC,
-                            double *dA_val, double *dB_val, void *ws, size_t ws_bytes,
-                            hipStream_t stream) {
+                            double *dA_val, double *dB_val, int flags, void *ws,
+                            size_t ws_bytes, hipStream_t stream) {
     (void)tol;
     if (!relation_ok(A) || !relation_ok(B) || !shapes_ok(M, K, N) || dC == nullptr)
         return TCU_ERR_ARG;
+    if ((flags & ~TCU_BWD_SAVED_ENCODINGS) != 0) return TCU_ERR_ARG;
     if (p != TCU_PREC_FP64) return TCU_ERR_ARG;
     const Layout L = plan_layout(M, K, N, p, TCU_WS_BACKWARD);
     if (!ws_ok(ws, ws_bytes, L.total)) return TCU_ERR_WORKSPACE;
     StatusBlock *st = at<StatusBlock>(ws, 0);
     double *X = at<double>(ws, L.x), *Y = at<double>(ws, L.y), *G = at<double>(ws, L.g);
 
-    TCU_TRY(launch_clear_status(st, stream));
     if (dA_val == nullptr && dB_val == nullptr) return TCU_OK;
-    // activation checkpointing: the encodings are rebuilt from the records
-    TCU_TRY(encode_both(*A, *B, M, K, N, X, Y, st, false, stream));
+    if (!(flags & TCU_BWD_SAVED_ENCODINGS)) {
+        // activation checkpointing: the encodings are rebuilt from the records
+        TCU_TRY(launch_clear_status(st, stream));
+        TCU_TRY(encode_both(*A, *B, M, K, N, X, Y, st, false, stream));
+    }
     if (dA_val != nullptr) {
         // dX = dC * Y^T (M x K), then dA.val[i] = dX[g_i, k_i]
         TCU_TRY(launch_gemm_f64(0, 1, M, K, N, dC, N, Y, N, G, K, stream));

@@ -14,10 +14,11 @@
 //    stage s+1 are issued before the MFMAs of stage s and written to the other
 //    buffer afterwards, so one barrier per stage suffices.
 //  * Inside a stage, lane group j = lane/16 at k-step t (0..3) contracts
-//    k = 4j + t.  Any bijection of the 16 k values is a valid contraction
-//    order as long as A and B use the same one; this one lets a lane read its
-//    four k values of a contraction-contiguous operand with two 16-byte LDS
-//    reads.
+//    k = 4j + t (any bijection of the 16 k values is a valid contraction
+//    order as long as A and B use the same one).  Fragments are read from LDS
+//    one k-step at a time, which keeps the kernel within 128 VGPRs + 128
+//    AGPRs, so two workgroups (two waves per SIMD) share a CU and cover each
+//    other's barrier and load stalls.
 //  * Operands whose contraction index is contiguous in memory are staged as
 //    [outer][16 + 2] in LDS, the others as [16][128 + 2]; the pads spread rows
 //    over the LDS banks.  Global loads are 16-byte vectors when the leading
@@ -86,22 +87,16 @@ __device__ inline void store_tile(double *__restrict__ L, const double2 (&r)[4])
     }
 }
 
-// Fragments of one stage: f[block][t] for k-step t.
+// Fragments of k-step t of one stage: f[block] = the lane's element of
+// MFMA block `block` (row or column wbase + 16*block + lane%16, k = 4j + t).
 template <bool KC, int F>
-__device__ inline void read_frags(const double *__restrict__ L, int wbase, double (&f)[F][4]) {
+__device__ inline void read_frags(const double *__restrict__ L, int wbase, int t, double (&f)[F]) {
     const int lane = threadIdx.x & 63;
     const int j = lane >> 4, l16 = lane & 15;
 #pragma unroll
     for (int b = 0; b < F; ++b) {
         const int o = wbase + b * 16 + l16;
-        if (KC) {
-            const double2 lo = *reinterpret_cast<const double2 *>(L + o * KPAD + 4 * j);
-            const double2 hi = *reinterpret_cast<const double2 *>(L + o * KPAD + 4 * j + 2);
-            f[b][0] = lo.x; f[b][1] = lo.y; f[b][2] = hi.x; f[b][3] = hi.y;
-        } else {
-#pragma unroll
-            for (int t = 0; t < 4; ++t) f[b][t] = L[(4 * j + t) * OPAD + o];
-        }
+        f[b] = KC ? L[o * KPAD + 4 * j + t] : L[(4 * j + t) * OPAD + o];
     }
 }
 
@@ -122,7 +117,7 @@ __device__ inline void tile_coords(int tiles_m, int tiles_n, int &tm, int &tn) {
 // A_KC: op(A)'s contraction index is contiguous (trans_a == 0).
 // B_KC: op(B)'s contraction index is contiguous (trans_b == 1).
 template <bool A_KC, bool B_KC>
-__global__ void __launch_bounds__(THREADS)
+__global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
 gemm_f64_kernel(int m, int n, int k, const double *__restrict__ A, int64_t lda,
                 const double *__restrict__ B, int64_t ldb, double *__restrict__ C, int64_t ldc,
                 int vec_a, int vec_b) {
@@ -158,17 +153,18 @@ gemm_f64_kernel(int m, int n, int k, const double *__restrict__ A, int64_t lda,
             load_tile<A_KC>(A, lda, m0, (kt + 1) * BK, m, k, vec_a, ra);
             load_tile<B_KC>(B, ldb, n0, (kt + 1) * BK, n, k, vec_b, rb);
         }
-        double fa[FM][4], fb[FN][4];
-        read_frags<A_KC, FM>(lds_a[cur], wm * WM, fa);
-        read_frags<B_KC, FN>(lds_b[cur], wn * WN, fb);
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < 4; ++t) {
+            double fa[FM], fb[FN];
+            read_frags<A_KC, FM>(lds_a[cur], wm * WM, t, fa);
+            read_frags<B_KC, FN>(lds_b[cur], wn * WN, t, fb);
 #pragma unroll
             for (int a = 0; a < FM; ++a)
 #pragma unroll
                 for (int b = 0; b < FN; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a][t], fb[b][t], acc[a][b],
-                                                                     0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0,
+                                                                     0);
+        }
         if (more) {
             store_tile<A_KC>(lds_a[cur ^ 1], ra);
             store_tile<B_KC>(lds_b[cur ^ 1], rb);

@@ -39,8 +39,10 @@ def _need_cuda(t: torch.Tensor, name: str, dtypes) -> None:
         raise ValueError(f"{name} must be contiguous")
 
 
-def make_relation(group: torch.Tensor, key: torch.Tensor, val: Optional[torch.Tensor]):
-    """tcu_relation for one relation; returns (struct, tensors to keep alive)."""
+def make_relation(group: torch.Tensor, key: torch.Tensor, val: Optional[torch.Tensor],
+                  unique: bool = False):
+    """tcu_relation for one relation.  unique=True declares that no two
+    records share a (group, key) cell (a table storing a matrix)."""
     _need_cuda(group, "group", (torch.int32,))
     _need_cuda(key, "key", (torch.int32,))
     n = group.numel()
@@ -55,7 +57,8 @@ def make_relation(group: torch.Tensor, key: torch.Tensor, val: Optional[torch.Te
             raise ValueError("columns of a relation must be on one device")
         dtype = _lib.TCU_F32 if val.dtype == torch.float32 else _lib.TCU_F64
     rel = _lib.tcu_relation(n, group.data_ptr() if n else None, key.data_ptr() if n else None,
-                            val.data_ptr() if (val is not None and n) else None, dtype)
+                            val.data_ptr() if (val is not None and n) else None, dtype,
+                            _lib.TCU_REL_UNIQUE_CELLS if unique else 0)
     return rel
 
 
@@ -77,11 +80,12 @@ def alloc_workspace(nbytes: int, device) -> torch.Tensor:
 
 
 def encode(group, key, val, rows: int, cols: int, transpose: bool = False,
-           out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+           out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
+           unique: bool = False) -> torch.Tensor:
     """Step a1 (Sections 3.1/3.3): dense FP64 encoding of one relation.
 
     transpose=False: out[group, key] (A -> X);  True: out[key, group] (B -> Y)."""
-    rel = make_relation(group, key, val)
+    rel = make_relation(group, key, val, unique)
     dev = group.device
     if out is None:
         out = torch.empty((rows, cols), dtype=torch.float64, device=dev)
@@ -113,13 +117,17 @@ def gemm_f64(A: torch.Tensor, B: torch.Tensor, trans_a: bool = False, trans_b: b
 
 def join_agg_fwd(a_group, a_key, a_val, b_key, b_group, b_val, M: int, K: int, N: int,
                  precision: str = "fp64", tol: float = 0.0, with_count: bool = False,
-                 ws: Optional[torch.Tensor] = None
+                 ws: Optional[torch.Tensor] = None, unique: bool = False,
+                 for_backward: bool = False
                  ) -> Tuple[torch.Tensor, Optional[torch.Tensor], torch.Tensor]:
-    """Steps a1-a3: returns (C, count or None, workspace)."""
-    A = make_relation(a_group, a_key, a_val)
-    B = make_relation(b_group, b_key, b_val)
+    """Steps a1-a3: returns (C, count or None, workspace).
+
+    for_backward=True sizes the workspace so that join_agg_bwd can reuse the
+    encodings it holds (saved_encodings=True)."""
+    A = make_relation(a_group, a_key, a_val, unique)
+    B = make_relation(b_group, b_key, b_val, unique)
     dev = a_group.device
-    need = workspace_bytes(A, B, M, K, N, precision, count=with_count)
+    need = workspace_bytes(A, B, M, K, N, precision, count=with_count, backward=for_backward)
     if ws is None or ws.numel() < need:
         ws = alloc_workspace(need, dev)
     Cm = torch.empty((M, N), dtype=torch.float64, device=dev)
@@ -132,22 +140,29 @@ def join_agg_fwd(a_group, a_key, a_val, b_key, b_group, b_val, M: int, K: int, N
 
 def join_agg_bwd(a_group, a_key, a_val, b_key, b_group, b_val, M: int, K: int, N: int,
                  dC: torch.Tensor, need_a: bool = True, need_b: bool = True,
-                 precision: str = "fp64", tol: float = 0.0, ws: Optional[torch.Tensor] = None):
-    """Step a4: returns (dA_val or None, dB_val or None, workspace), FP64."""
-    A = make_relation(a_group, a_key, a_val)
-    B = make_relation(b_group, b_key, b_val)
+                 precision: str = "fp64", tol: float = 0.0, ws: Optional[torch.Tensor] = None,
+                 unique: bool = False, saved_encodings: bool = False):
+    """Step a4: returns (dA_val or None, dB_val or None, workspace), FP64.
+
+    saved_encodings=True: `ws` is the workspace of the forward on these same
+    inputs (sized with for_backward=True) and still holds X and Y."""
+    A = make_relation(a_group, a_key, a_val, unique)
+    B = make_relation(b_group, b_key, b_val, unique)
     dev = a_group.device
     _need_cuda(dC, "dC", (torch.float64,))
     if tuple(dC.shape) != (M, N):
         raise ValueError(f"dC must be {M} x {N}")
     need = workspace_bytes(A, B, M, K, N, precision, backward=True)
+    if saved_encodings and (ws is None or ws.numel() < need):
+        raise ValueError("saved_encodings needs the forward's workspace sized for backward")
     if ws is None or ws.numel() < need:
         ws = alloc_workspace(need, dev)
     dA = torch.empty(A.n, dtype=torch.float64, device=dev) if need_a else None
     dB = torch.empty(B.n, dtype=torch.float64, device=dev) if need_b else None
+    flags = _lib.TCU_BWD_SAVED_ENCODINGS if saved_encodings else 0
     check(_lib.load().tcu_join_agg_bwd(C.byref(A), C.byref(B), M, K, N, PRECISIONS[precision],
-                                       tol, _ptr(dC), _ptr(dA), _ptr(dB), _ptr(ws), ws.numel(),
-                                       _stream(dev)), "tcu_join_agg_bwd")
+                                       tol, _ptr(dC), _ptr(dA), _ptr(dB), flags, _ptr(ws),
+                                       ws.numel(), _stream(dev)), "tcu_join_agg_bwd")
     return dA, dB, ws
 
 
@@ -159,19 +174,33 @@ def sync_status(ws: torch.Tensor) -> Tuple[int, dict]:
                 "skipped_a": info.skipped_a, "skipped_b": info.skipped_b}
 
 
+def _checkpoint_needed(M: int, K: int, N: int, device) -> bool:
+    """Keep X and Y for backward unless they would take more than half of the
+    device memory that is free now."""
+    enc = 8 * (M * K + K * N + max(M * K, K * N))
+    free, _ = torch.cuda.mem_get_info(device)
+    return enc > free // 2
+
+
 class JoinAgg(torch.autograd.Function):
     """C = join-aggregate(A, B) with the hand-written adjoint as backward.
 
-    Only the record columns are saved (activation checkpointing): backward
-    re-encodes X and Y inside the library."""
+    checkpoint=None keeps the forward's encodings X and Y for backward when
+    they fit comfortably in HBM, and otherwise saves only the record columns
+    and re-encodes in backward (activation checkpointing); True / False force
+    one or the other."""
 
     @staticmethod
-    def forward(ctx, a_group, a_key, a_val, b_key, b_group, b_val, M, K, N, precision, tol):
-        Cm, _, _ = join_agg_fwd(a_group, a_key, a_val, b_key, b_group, b_val, M, K, N,
-                                precision, tol)
+    def forward(ctx, a_group, a_key, a_val, b_key, b_group, b_val, M, K, N, precision, tol,
+                unique, checkpoint):
+        if checkpoint is None:
+            checkpoint = _checkpoint_needed(M, K, N, a_group.device)
+        Cm, _, ws = join_agg_fwd(a_group, a_key, a_val, b_key, b_group, b_val, M, K, N,
+                                 precision, tol, unique=unique, for_backward=not checkpoint)
         ctx.save_for_backward(a_group, a_key, a_val, b_key, b_group, b_val)
         ctx.shape = (M, K, N)
-        ctx.precision, ctx.tol = precision, tol
+        ctx.precision, ctx.tol, ctx.unique = precision, tol, unique
+        ctx.ws = None if checkpoint else ws
         return Cm
 
     @staticmethod
@@ -184,15 +213,19 @@ class JoinAgg(torch.autograd.Function):
         if need_a or need_b:
             dA, dB, _ = join_agg_bwd(a_group, a_key, a_val, b_key, b_group, b_val, M, K, N,
                                      dC.contiguous().to(torch.float64), need_a, need_b,
-                                     ctx.precision, ctx.tol)
+                                     ctx.precision, ctx.tol, ws=ctx.ws, unique=ctx.unique,
+                                     saved_encodings=ctx.ws is not None)
+        ctx.ws = None
         if dA is not None:
             dA = dA.to(a_val.dtype)
         if dB is not None:
             dB = dB.to(b_val.dtype)
-        return None, None, dA, None, None, dB, None, None, None, None, None
+        return (None, None, dA, None, None, dB) + (None,) * 7
 
 
 def join_agg(a_group, a_key, a_val, b_key, b_group, b_val, M: int, K: int, N: int,
-             precision: str = "fp64", tol: float = 0.0) -> torch.Tensor:
+             precision: str = "fp64", tol: float = 0.0, unique: bool = False,
+             checkpoint: Optional[bool] = None) -> torch.Tensor:
     """Differentiable C = join-aggregate (gradients for the value columns)."""
-    return JoinAgg.apply(a_group, a_key, a_val, b_key, b_group, b_val, M, K, N, precision, tol)
+    return JoinAgg.apply(a_group, a_key, a_val, b_key, b_group, b_val, M, K, N, precision, tol,
+                         unique, checkpoint)

@@ -66,6 +66,37 @@ def test_bwd_one_side_only(orc):
     assert torch.equal(dA, dA3) and torch.equal(dB2, dB3)
 
 
+@pytest.mark.parametrize("unique", [False, True])
+def test_bwd_saved_encodings_match_checkpointing(unique):
+    """Reusing the forward's X and Y gives the same bits as re-encoding."""
+    dev = cuda_or_skip()
+    M, K, N = 300, 257, 200
+    A, B = wl.mm_query(M, K, N, seed=34, device=dev)
+    W = wl.draw_values("uniform", M * N, 34, 99, device=dev).reshape(M, N)
+    _, _, ws = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, M, K, N,
+                                unique=unique, for_backward=True)
+    dA1, dB1, _ = ops.join_agg_bwd(A.group, A.key, A.val, B.key, B.group, B.val, M, K, N, W,
+                                   ws=ws, unique=unique, saved_encodings=True)
+    dA2, dB2, _ = ops.join_agg_bwd(A.group, A.key, A.val, B.key, B.group, B.val, M, K, N, W,
+                                   unique=unique)
+    assert torch.equal(dA1, dA2) and torch.equal(dB1, dB2)
+
+
+@pytest.mark.parametrize("checkpoint", [True, False])
+def test_autograd_checkpoint_modes_agree(checkpoint):
+    dev = cuda_or_skip()
+    M, K, N = 130, 100, 120
+    A, B = wl.mm_query(M, K, N, seed=35, device=dev)
+    W = wl.draw_values("uniform", M * N, 35, 99, device=dev).reshape(M, N)
+    av = A.val.clone().requires_grad_(True)
+    bv = B.val.clone().requires_grad_(True)
+    Cm = ops.join_agg(A.group, A.key, av, B.key, B.group, bv, M, K, N, unique=True,
+                      checkpoint=checkpoint)
+    (Cm * W).sum().backward()
+    dA, dB, _ = ops.join_agg_bwd(A.group, A.key, A.val, B.key, B.group, B.val, M, K, N, W)
+    assert torch.equal(av.grad, dA) and torch.equal(bv.grad, dB)
+
+
 def test_fwd_bwd_2pow24_records(orc):
     """2^24 records per table (N = 4096), seed 2, W = U[-1,1) (seed 1002):
     sampled cells and Freivalds' check for C; oracle gradient on 4096 + 4096
@@ -74,11 +105,14 @@ def test_fwd_bwd_2pow24_records(orc):
     dev = cuda_or_skip()
     N = 4096
     A, B = wl.mm_query(N, N, N, seed=2, device=dev)
-    Cg, _, ws = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, N, N, N)
+    # the launch configuration the benchmark times: unique cells, saved encodings
+    Cg, _, ws = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, N, N, N,
+                                 unique=True, for_backward=True)
     assert ops.sync_status(ws)[0] == 0
     assert sampled_checks(orc, A, B, Cg, N, N, N, seed=2, ncells=4096) <= TOL
     W = wl.draw_values("uniform", N * N, 1002, 0, device=dev).reshape(N, N)
-    dA, dB, ws = ops.join_agg_bwd(A.group, A.key, A.val, B.key, B.group, B.val, N, N, N, W)
+    dA, dB, ws = ops.join_agg_bwd(A.group, A.key, A.val, B.key, B.group, B.val, N, N, N, W,
+                                  ws=ws, unique=True, saved_encodings=True)
     assert ops.sync_status(ws)[0] == 0
     rng = np.random.default_rng(1002)
     ia = rng.choice(A.n, 4096, replace=False).astype(np.int64)

@@ -42,6 +42,19 @@ def test_encode_dense_bit_exact(orc, n_side):
     assert np.array_equal(Y.cpu().numpy(), Yo)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_encode_unique_cells_plain_stores(orc, dtype):
+    """TCU_REL_UNIQUE_CELLS (plain stores) gives the same bits as the atomic
+    path and the oracle on tables with unique cells."""
+    dev = cuda_or_skip()
+    R = wl.dense_relation(300, 517, 8, 1, device=dev, dtype=dtype)
+    Xu = ops.encode(R.group, R.key, R.val, 517, 300, unique=True)
+    Xa = ops.encode(R.group, R.key, R.val, 517, 300, unique=False)
+    Xo, _ = orc.encode(R.group.cpu().numpy(), R.key.cpu().numpy(),
+                       R.val.cpu().to(torch.float64).numpy(), 517, 300)
+    assert torch.equal(Xu, Xa) and np.array_equal(Xu.cpu().numpy(), Xo)
+
+
 def test_encode_duplicates_integer_values_exact(orc):
     dev = cuda_or_skip()
     R = wl.random_relation(200_000, 300, 257, 3, 1, values="int", lo=-1000, hi=1000, device=dev)
@@ -162,6 +175,23 @@ def test_fwd_random_relations(orc, seed, nA, nB, M, K, N, bad):
         assert (info["skipped_a"], info["skipped_b"]) == (sa, sb) and sa > 0
     else:
         assert st == 0
+
+
+def test_fwd_unique_flag_matches(orc):
+    """The MM query's dense tables with the unique-cells flag: full oracle."""
+    dev = cuda_or_skip()
+    M, K, N = 257, 190, 131
+    A, B = wl.mm_query(M, K, N, seed=15, device=dev)
+    Cg, cnt, ws = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, M, K, N,
+                                   with_count=True, unique=True)
+    assert ops.sync_status(ws)[0] == 0
+    RA, RB = to_orc(orc, A), to_orc(orc, B)
+    Co, co, _ = orc.join_agg(RA, RB, M, K, N, with_count=True)
+    S, _, _ = orc.join_agg(abs_rel(orc, RA), abs_rel(orc, RB), M, K, N)
+    assert err_cw(Cg.cpu().numpy(), Co, S) <= TOL
+    assert np.array_equal(cnt.cpu().numpy(), co)
+    Cn, _, _ = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, M, K, N)
+    assert torch.equal(Cg, Cn)
 
 
 def test_fwd_empty_relations(orc):

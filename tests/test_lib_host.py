@@ -41,8 +41,8 @@ def test_version_and_status_strings(lib):
     assert lib.tcu_status_str(-99).decode() == "unknown status"
 
 
-def rel(n, dtype=_lib.TCU_F64, ptr=0x1000):
-    return _lib.tcu_relation(n, ptr if n else None, ptr if n else None, ptr, dtype)
+def rel(n, dtype=_lib.TCU_F64, ptr=0x1000, flags=0):
+    return _lib.tcu_relation(n, ptr if n else None, ptr if n else None, ptr, dtype, flags)
 
 
 def test_workspace_bytes(lib):
@@ -85,11 +85,17 @@ def test_argument_errors_return_before_launch(lib):
                                 C.c_void_p(0x100010), 1 << 20, None) == _lib.TCU_ERR_WORKSPACE
     assert lib.tcu_join_agg_fwd(C.byref(A), C.byref(B), 4, 4, 4, 0, 0.0, cbuf, None,
                                 C.c_void_p(0x100000), 300, None) == _lib.TCU_ERR_WORKSPACE
-    # backward: NULL dC, small workspace
-    assert lib.tcu_join_agg_bwd(C.byref(A), C.byref(B), 4, 4, 4, 0, 0.0, None, cbuf, cbuf,
+    # unknown relation flag
+    bf = rel(10, flags=4)
+    assert lib.tcu_join_agg_fwd(C.byref(bf), C.byref(B), 4, 4, 4, 0, 0.0, cbuf, None,
+                                C.c_void_p(0x100000), 1 << 20, None) == _lib.TCU_ERR_ARG
+    # backward: NULL dC, unknown flag, small workspace
+    assert lib.tcu_join_agg_bwd(C.byref(A), C.byref(B), 4, 4, 4, 0, 0.0, None, cbuf, cbuf, 0,
+                                C.c_void_p(0x100000), 1 << 20, None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_join_agg_bwd(C.byref(A), C.byref(B), 4, 4, 4, 0, 0.0, cbuf, cbuf, cbuf, 2,
                                 C.c_void_p(0x100000), 1 << 20, None) == _lib.TCU_ERR_ARG
     fwd_only = lib.tcu_workspace_bytes(C.byref(A), C.byref(B), 64, 64, 64, 0, 0)
-    assert lib.tcu_join_agg_bwd(C.byref(A), C.byref(B), 64, 64, 64, 0, 0.0, cbuf, cbuf, cbuf,
+    assert lib.tcu_join_agg_bwd(C.byref(A), C.byref(B), 64, 64, 64, 0, 0.0, cbuf, cbuf, cbuf, 0,
                                 C.c_void_p(0x100000), fwd_only, None) == _lib.TCU_ERR_WORKSPACE
     # gemm: bad transpose flag, negative size, short leading dimension
     assert lib.tcu_gemm_f64(2, 0, 4, 4, 4, cbuf, 4, cbuf, 4, cbuf, 4, None) == _lib.TCU_ERR_ARG
