@@ -52,9 +52,15 @@ typedef enum { TCU_F64 = 0, TCU_F32 = 1 } tcu_dtype;
 
 typedef enum {
     TCU_PREC_FP64 = 0,       /* FP64 encodings, FP64 matrix-core product       */
-    TCU_PREC_SPLIT_BF16 = 1  /* FP64 encodings split into BF16 integer slices,
-                                FP32 exact partial sums, FP64 combination     */
+    TCU_PREC_SPLIT_BF16 = 1, /* FP64 encodings cut into 7-bit integer digits
+                                held in BF16, BF16 matrix cores with exact
+                                FP32 partial sums, FP64 combination          */
+    TCU_PREC_SPLIT_I8 = 2    /* the same digits held in int8, int8 matrix
+                                cores with exact int32 partial sums          */
 } tcu_precision;
+
+/* Largest slice count of the mixed forms (8 digits of 7 bits). */
+#define TCU_MAX_SLICES 8
 
 /* Relation flags. */
 #define TCU_REL_UNIQUE_CELLS 1u /* no two records share a (group, key) pair, as
@@ -118,6 +124,34 @@ size_t tcu_workspace_bytes(const tcu_relation *A, const tcu_relation *B, int32_t
 tcu_status tcu_encode(const tcu_relation *R, int transpose, int32_t rows, int32_t cols,
                       double *out, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Step a0 host part, the mixed form's precision plan (the feasibility test of
+ * Section 4.2.1 retargeted): the smallest slice count S in [1, 8] whose
+ * a-priori bound meets `tol` for a contraction of length k,
+ *   4.04 (S+1) 2^(-7S) + 4.04 * 2^-53 * n_add(S, k) <= tol,
+ * the bound on |error| / (k * max|row of A| * max|column of B|) from the
+ * dropped digit pairs and the FP64 additions.  Returns S, or
+ * TCU_ERR_INFEASIBLE when even S = 8 misses `tol`, or TCU_ERR_ARG.  Host
+ * only: touches no device. */
+int tcu_split_slices(tcu_precision p, int32_t k, double tol);
+
+/* Step a0 device part alone: the per-line scale exponents and S digit slices
+ * of a dense FP64 matrix Z (rows x cols, leading dimension ld).
+ * axis == 0: lines are rows (length cols); 1: lines are columns (length rows).
+ * For a line with largest magnitude mx, e = the exponent with
+ * 2^(e-1) <= mx < 2^e (0 for an all-zero line), r_0 = z 2^-e and for
+ * p = 1..S: t = r_{p-1} 2^7, d_p = trunc(t), r_p = t - d_p.
+ * exps[line] = e (int32, `lines` entries); digits d_p are written as int8
+ * (TCU_PREC_SPLIT_I8) or BF16 (TCU_PREC_SPLIT_BF16) in the blocked layout
+ *   slices[p][t / KSTEP][line][t % KSTEP],  KSTEP = 32 (int8) or 16 (BF16),
+ * lines padded with zero digits to lines_pad (multiple of 128, >= lines) and
+ * positions t to len_pad (multiple of 64, >= line length); slice p starts at
+ * element p * lines_pad * len_pad.  NaN/Inf values give digits 0 and set
+ * TCU_ERR_NONFINITE in the status block.  ws: >= 256 + 8 * lines_pad bytes. */
+tcu_status tcu_split(const double *Z, int32_t rows, int32_t cols, int64_t ld, int axis,
+                     tcu_precision p, int32_t S, void *slices, int32_t lines_pad,
+                     int32_t len_pad, int32_t *exps, void *ws, size_t ws_bytes,
+                     hipStream_t stream);
+
 /* Step a2 alone, the contraction of Section 3.3: C = op(A) * op(B) in FP64 on
  * the matrix cores, op(A) m x k, op(B) k x n, C m x n (leading dimension ldc).
  * trans_a == 0: A is m x k row-major (lda >= k); 1: A is k x m (lda >= m).
@@ -131,11 +165,13 @@ tcu_status tcu_gemm_f64(int trans_a, int trans_b, int32_t m, int32_t n, int32_t 
  * rows g ascending, columns h ascending) = the join-aggregate above.
  * count (M x N int32, or NULL): exact number of joined pairs per (g,h); SQL's
  * result holds exactly the cells with count > 0 (a dense C shows 0 elsewhere).
- * p == TCU_PREC_SPLIT_BF16 runs the mixed form to componentwise accuracy
- * `tol` relative to K * max|X[g,:]| * max|Y[:,h]| (tol <= 0: 2^-52) and makes
- * one device-to-host synchronisation to read the encodings' exponent range.
- * Device-side conditions (out-of-range records) are reported by
- * tcu_sync_status. */
+ * The mixed forms (TCU_PREC_SPLIT_*) guarantee, cell by cell,
+ *   |C - exact| <= tol * K * max_k |X[g,k]| * max_k |Y[k,h]|
+ * with the slice count from tcu_split_slices (tol <= 0 means 1e-12), and
+ * return TCU_ERR_INFEASIBLE (launching nothing) when no slice count can; the
+ * count output is exact in every form.  No call synchronises the host.
+ * Device-side conditions (out-of-range records, NaN/Inf in the mixed forms)
+ * are reported by tcu_sync_status. */
 tcu_status tcu_join_agg_fwd(const tcu_relation *A, const tcu_relation *B, int32_t M, int32_t K,
                             int32_t N, tcu_precision p, double tol, double *C, int32_t *count,
                             void *ws, size_t ws_bytes, hipStream_t stream);
@@ -147,7 +183,9 @@ tcu_status tcu_join_agg_fwd(const tcu_relation *A, const tcu_relation *B, int32_
  * checkpointing: nothing of the forward is kept); with
  * TCU_BWD_SAVED_ENCODINGS the forward's X and Y in ws are used.  Either
  * output may be NULL.  Skipped records get 0.  Gradients are FP64 whatever
- * the value dtype.  Needs a workspace sized with TCU_WS_BACKWARD. */
+ * the value dtype.  In the mixed forms both products carry the forward's
+ * guarantee with their own contraction length (N for dX, M for dY).  Needs a
+ * workspace sized with TCU_WS_BACKWARD. */
 tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_t M, int32_t K,
                             int32_t N, tcu_precision p, double tol, const double *dC,
                             double *dA_val, double *dB_val, int flags, void *ws,

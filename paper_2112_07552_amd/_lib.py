@@ -25,6 +25,8 @@ TCU_F32 = 1
 
 TCU_PREC_FP64 = 0
 TCU_PREC_SPLIT_BF16 = 1
+TCU_PREC_SPLIT_I8 = 2
+TCU_MAX_SLICES = 8
 
 TCU_WS_BACKWARD = 1
 TCU_WS_COUNT = 2
@@ -33,8 +35,8 @@ TCU_REL_UNIQUE_CELLS = 1
 TCU_BWD_SAVED_ENCODINGS = 1
 
 EXPORTS = (
-    "tcu_workspace_bytes", "tcu_encode", "tcu_gemm_f64", "tcu_join_agg_fwd",
-    "tcu_join_agg_bwd", "tcu_sync_status", "tcu_status_str", "tcu_version",
+    "tcu_workspace_bytes", "tcu_split_slices", "tcu_split", "tcu_encode", "tcu_gemm_f64",
+    "tcu_join_agg_fwd", "tcu_join_agg_bwd", "tcu_sync_status", "tcu_status_str", "tcu_version",
 )
 
 
@@ -70,6 +72,11 @@ def load():
     vp, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     L.tcu_workspace_bytes.argtypes = [rel_p, rel_p, i32, i32, i32, C.c_int, C.c_int]
     L.tcu_workspace_bytes.restype = C.c_size_t
+    L.tcu_split_slices.argtypes = [C.c_int, i32, f64]
+    L.tcu_split_slices.restype = C.c_int
+    L.tcu_split.argtypes = [vp, i32, i32, i64, C.c_int, C.c_int, i32, vp, i32, i32, vp, vp,
+                            C.c_size_t, vp]
+    L.tcu_split.restype = C.c_int
     L.tcu_encode.argtypes = [rel_p, C.c_int, i32, i32, vp, vp, C.c_size_t, vp]
     L.tcu_encode.restype = C.c_int
     L.tcu_gemm_f64.argtypes = [C.c_int, C.c_int, i32, i32, i32, vp, i64, vp, i64, vp, i64, vp]

@@ -29,23 +29,54 @@ bool relation_ok(const tcu_relation *R) {
 
 bool shapes_ok(int32_t M, int32_t K, int32_t N) { return M >= 1 && K >= 1 && N >= 1; }
 
-// Workspace layout: [status block][X: M*K f64][Y: K*N f64][G: gradient]
+bool is_split(tcu_precision p) { return p == TCU_PREC_SPLIT_BF16 || p == TCU_PREC_SPLIT_I8; }
+bool precision_ok(tcu_precision p) { return p == TCU_PREC_FP64 || is_split(p); }
+
+size_t pad128(int64_t x) { return (size_t)((x + 127) / 128 * 128); }
+size_t pad64(int64_t x) { return (size_t)((x + 63) / 64 * 64); }
+size_t maxz(size_t a, size_t b) { return a > b ? a : b; }
+
+// Workspace layout:
+//   [status block][X: M*K f64][Y: K*N f64]
+//   [G: max(M*K, K*N) f64]                             (backward)
+//   [line maxima and exponents of operands A and B]     (mixed forms)
+//   [digit slices of operands A and B, TCU_MAX_SLICES each]
+// In the mixed forms "A" is the left operand of a product (X forward, W
+// for dX, X^T for dY) and "B" the right one (Y, Y^T, W).
 struct Layout {
-    size_t x = 0, y = 0, g = 0, total = 0;
+    size_t x = 0, y = 0, g = 0, mba = 0, mbb = 0, ea = 0, eb = 0, sa = 0, sb = 0, total = 0;
 };
 
 Layout plan_layout(int32_t M, int32_t K, int32_t N, tcu_precision p, int flags) {
-    (void)p;
     Layout L;
+    const bool bwd = (flags & TCU_WS_BACKWARD) != 0;
     size_t off = sizeof(StatusBlock);
     L.x = off;
     off += align_up((size_t)M * (size_t)K * sizeof(double));
     L.y = off;
     off += align_up((size_t)K * (size_t)N * sizeof(double));
-    if (flags & TCU_WS_BACKWARD) {
+    if (bwd) {
         L.g = off;
-        const size_t mk = (size_t)M * (size_t)K, kn = (size_t)K * (size_t)N;
-        off += align_up((mk > kn ? mk : kn) * sizeof(double));
+        off += align_up(maxz((size_t)M * K, (size_t)K * N) * sizeof(double));
+    }
+    if (is_split(p)) {
+        const size_t digit = p == TCU_PREC_SPLIT_I8 ? 1 : 2;
+        // (lines, length) of each operand: forward X (M, K) and Y (N, K);
+        // backward W (M, N) and Y^T (K, N) for dX, X^T (K, M) and W (N, M) for dY
+        size_t la = pad128(M), lb = pad128(N);
+        size_t za = pad128(M) * pad64(K), zb = pad128(N) * pad64(K);
+        if (bwd) {
+            la = maxz(la, pad128(K));
+            lb = maxz(lb, pad128(K));
+            za = maxz(za, maxz(pad128(M) * pad64(N), pad128(K) * pad64(M)));
+            zb = maxz(zb, maxz(pad128(K) * pad64(N), pad128(N) * pad64(M)));
+        }
+        L.mba = off; off += align_up(la * 8);
+        L.mbb = off; off += align_up(lb * 8);
+        L.ea = off; off += align_up(la * 4);
+        L.eb = off; off += align_up(lb * 4);
+        L.sa = off; off += align_up(TCU_MAX_SLICES * za * digit);
+        L.sb = off; off += align_up(TCU_MAX_SLICES * zb * digit);
     }
     L.total = off;
     return L;
@@ -73,6 +104,38 @@ hipError_t encode_both(const tcu_relation &A, const tcu_relation &B, int32_t M, 
     return e;
 }
 
+// Mixed-form product C (m x n, ldc) = opA * opB with contraction length k.
+// opA's lines are its m rows: Za with axis_a (0: Za is m x k, rows are
+// lines; 1: Za is k x m, columns are lines); likewise opB's n lines from Zb
+// with axis_b (0: Zb is n x k; 1: Zb is k x n).
+struct SplitOperand {
+    const double *Z;
+    int rows, cols;
+    int64_t ld;
+    int axis;
+};
+
+hipError_t split_product(const SplitOperand &a, const SplitOperand &b, int m, int n, int k,
+                         int S, tcu_precision p, void *ws, const Layout &L, StatusBlock *st,
+                         double *C, int64_t ldc, hipStream_t s) {
+    const int bf16 = p == TCU_PREC_SPLIT_BF16;
+    const int len_pad = (int)pad64(k);
+    const int la = (int)pad128(m), lb = (int)pad128(n);
+    auto *mba = at<unsigned long long>(ws, L.mba);
+    auto *mbb = at<unsigned long long>(ws, L.mbb);
+    int *ea = at<int>(ws, L.ea), *eb = at<int>(ws, L.eb);
+    void *sa = at<char>(ws, L.sa), *sb = at<char>(ws, L.sb);
+    hipError_t e = launch_line_max(a.Z, a.rows, a.cols, a.ld, a.axis, mba, st, s);
+    if (e == hipSuccess)
+        e = launch_split(a.Z, a.rows, a.cols, a.ld, a.axis, mba, S, bf16, sa, la, len_pad, ea, s);
+    if (e == hipSuccess) e = launch_line_max(b.Z, b.rows, b.cols, b.ld, b.axis, mbb, st, s);
+    if (e == hipSuccess)
+        e = launch_split(b.Z, b.rows, b.cols, b.ld, b.axis, mbb, S, bf16, sb, lb, len_pad, eb, s);
+    if (e == hipSuccess)
+        e = launch_gemm_split(m, n, k, S, bf16, sa, la, sb, lb, len_pad, ea, eb, C, ldc, s);
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -81,8 +144,43 @@ size_t tcu_workspace_bytes(const tcu_relation *A, const tcu_relation *B, int32_t
                            int32_t N, tcu_precision p, int flags) {
     (void)A; (void)B;
     if (!shapes_ok(M, K, N)) return 0;
-    if (p != TCU_PREC_FP64 && p != TCU_PREC_SPLIT_BF16) return 0;
+    if (!precision_ok(p)) return 0;
     return plan_layout(M, K, N, p, flags).total;
+}
+
+int tcu_split_slices(tcu_precision p, int32_t k, double tol) {
+    if (!is_split(p) || k < 1) return TCU_ERR_ARG;
+    if (!(tol > 0.0)) tol = 1e-12;
+    const int bf16 = p == TCU_PREC_SPLIT_BF16;
+    const int kstep = bf16 ? 16 : 32;
+    const int64_t nblk = (int64_t)pad64(k) / kstep;
+    for (int S = 1; S <= TCU_MAX_SLICES; ++S) {
+        const int64_t chunk = split_chunk_steps(S, bf16);
+        const int64_t n_add = (int64_t)S * ((nblk + chunk - 1) / chunk);
+        const double trunc_bound = 4.04 * (S + 1) * ldexp(1.0, -7 * S);
+        const double round_bound = 4.04 * (double)n_add * ldexp(1.0, -53);
+        if (trunc_bound + round_bound <= tol) return S;
+    }
+    return TCU_ERR_INFEASIBLE;
+}
+
+tcu_status tcu_split(const double *Z, int32_t rows, int32_t cols, int64_t ld, int axis,
+                     tcu_precision p, int32_t S, void *slices, int32_t lines_pad,
+                     int32_t len_pad, int32_t *exps, void *ws, size_t ws_bytes,
+                     hipStream_t stream) {
+    if (Z == nullptr || slices == nullptr || exps == nullptr) return TCU_ERR_ARG;
+    if (rows < 1 || cols < 1 || ld < cols || (axis != 0 && axis != 1)) return TCU_ERR_ARG;
+    if (!is_split(p) || S < 1 || S > TCU_MAX_SLICES) return TCU_ERR_ARG;
+    const int lines = axis == 0 ? rows : cols, len = axis == 0 ? cols : rows;
+    if (lines_pad < lines || lines_pad % 128 || len_pad < len || len_pad % 64) return TCU_ERR_ARG;
+    if (!ws_ok(ws, ws_bytes, sizeof(StatusBlock) + (size_t)lines_pad * 8)) return TCU_ERR_WORKSPACE;
+    StatusBlock *st = at<StatusBlock>(ws, 0);
+    auto *mb = at<unsigned long long>(ws, sizeof(StatusBlock));
+    TCU_TRY(launch_clear_status(st, stream, (uint32_t)S));
+    TCU_TRY(launch_line_max(Z, rows, cols, ld, axis, mb, st, stream));
+    TCU_TRY(launch_split(Z, rows, cols, ld, axis, mb, S, p == TCU_PREC_SPLIT_BF16, slices,
+                         lines_pad, len_pad, exps, stream));
+    return TCU_OK;
 }
 
 tcu_status tcu_encode(const tcu_relation *R, int transpose, int32_t rows, int32_t cols,
@@ -114,16 +212,20 @@ tcu_status tcu_gemm_f64(int trans_a, int trans_b, int32_t m, int32_t n, int32_t 
 tcu_status tcu_join_agg_fwd(const tcu_relation *A, const tcu_relation *B, int32_t M, int32_t K,
                             int32_t N, tcu_precision p, double tol, double *C, int32_t *count,
                             void *ws, size_t ws_bytes, hipStream_t stream) {
-    (void)tol;
     if (!relation_ok(A) || !relation_ok(B) || !shapes_ok(M, K, N) || C == nullptr)
         return TCU_ERR_ARG;
-    if (p != TCU_PREC_FP64) return TCU_ERR_ARG;
+    if (!precision_ok(p)) return TCU_ERR_ARG;
+    int S = 0;
+    if (is_split(p)) {
+        S = tcu_split_slices(p, K, tol);
+        if (S < 0) return (tcu_status)S;
+    }
     const Layout L = plan_layout(M, K, N, p, 0);
     if (!ws_ok(ws, ws_bytes, L.total)) return TCU_ERR_WORKSPACE;
     StatusBlock *st = at<StatusBlock>(ws, 0);
     double *X = at<double>(ws, L.x), *Y = at<double>(ws, L.y);
 
-    TCU_TRY(launch_clear_status(st, stream));
+    TCU_TRY(launch_clear_status(st, stream, (uint32_t)S));
     if (count != nullptr) {
         // exact pair counts: the 0/1 (multiplicity) encodings of Section 3.1,
         // multiplied in FP64 (integers below 2^53 are exact), C as scratch
@@ -132,7 +234,13 @@ tcu_status tcu_join_agg_fwd(const tcu_relation *A, const tcu_relation *B, int32_
         TCU_TRY(launch_f64_to_i32(C, count, (size_t)M * N, stream));
     }
     TCU_TRY(encode_both(*A, *B, M, K, N, X, Y, st, false, stream));
-    TCU_TRY(launch_gemm_f64(0, 0, M, N, K, X, K, Y, N, C, N, stream));
+    if (S == 0) {
+        TCU_TRY(launch_gemm_f64(0, 0, M, N, K, X, K, Y, N, C, N, stream));
+    } else {
+        // X: M lines (rows) of length K; Y: N lines (columns) of length K
+        const SplitOperand a{X, M, K, K, 0}, b{Y, K, N, N, 1};
+        TCU_TRY(split_product(a, b, M, N, K, S, p, ws, L, st, C, N, stream));
+    }
     return TCU_OK;
 }
 
@@ -140,11 +248,17 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
                             int32_t N, tcu_precision p, double tol, const double *dC,
                             double *dA_val, double *dB_val, int flags, void *ws,
                             size_t ws_bytes, hipStream_t stream) {
-    (void)tol;
     if (!relation_ok(A) || !relation_ok(B) || !shapes_ok(M, K, N) || dC == nullptr)
         return TCU_ERR_ARG;
     if ((flags & ~TCU_BWD_SAVED_ENCODINGS) != 0) return TCU_ERR_ARG;
-    if (p != TCU_PREC_FP64) return TCU_ERR_ARG;
+    if (!precision_ok(p)) return TCU_ERR_ARG;
+    int S1 = 0, S2 = 0;
+    if (is_split(p)) {
+        S1 = tcu_split_slices(p, N, tol);  // dX contracts over h
+        S2 = tcu_split_slices(p, M, tol);  // dY contracts over g
+        if (S1 < 0) return (tcu_status)S1;
+        if (S2 < 0) return (tcu_status)S2;
+    }
     const Layout L = plan_layout(M, K, N, p, TCU_WS_BACKWARD);
     if (!ws_ok(ws, ws_bytes, L.total)) return TCU_ERR_WORKSPACE;
     StatusBlock *st = at<StatusBlock>(ws, 0);
@@ -158,12 +272,24 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
     }
     if (dA_val != nullptr) {
         // dX = dC * Y^T (M x K), then dA.val[i] = dX[g_i, k_i]
-        TCU_TRY(launch_gemm_f64(0, 1, M, K, N, dC, N, Y, N, G, K, stream));
+        if (S1 == 0) {
+            TCU_TRY(launch_gemm_f64(0, 1, M, K, N, dC, N, Y, N, G, K, stream));
+        } else {
+            // dC: M lines (rows) of length N; Y^T: K lines = rows of Y, length N
+            const SplitOperand a{dC, M, N, N, 0}, b{Y, K, N, N, 0};
+            TCU_TRY(split_product(a, b, M, K, N, S1, p, ws, L, st, G, K, stream));
+        }
         TCU_TRY(launch_gather(*A, 0, M, K, G, dA_val, stream));
     }
     if (dB_val != nullptr) {
         // dY = X^T * dC (K x N), then dB.val[j] = dY[k_j, h_j]
-        TCU_TRY(launch_gemm_f64(1, 0, K, N, M, X, K, dC, N, G, N, stream));
+        if (S2 == 0) {
+            TCU_TRY(launch_gemm_f64(1, 0, K, N, M, X, K, dC, N, G, N, stream));
+        } else {
+            // X^T: K lines = columns of X, length M; dC: N lines = columns, length M
+            const SplitOperand a{X, M, K, K, 1}, b{dC, M, N, N, 1};
+            TCU_TRY(split_product(a, b, K, N, M, S2, p, ws, L, st, G, N, stream));
+        }
         TCU_TRY(launch_gather(*B, 1, K, N, G, dB_val, stream));
     }
     return TCU_OK;

@@ -30,9 +30,9 @@ __global__ void __launch_bounds__(kThreads) zero_f64_kernel(double *__restrict__
     }
 }
 
-__global__ void zero_status_kernel(StatusBlock *st) {
+__global__ void zero_status_kernel(StatusBlock *st, uint32_t slices) {
     uint32_t *w = reinterpret_cast<uint32_t *>(st);
-    w[threadIdx.x] = 0u;  // 64 threads x 4 bytes
+    w[threadIdx.x] = threadIdx.x == 1 ? slices : 0u;  // 64 threads x 4 bytes; word 1 = slices
 }
 
 // Counts this wave's invalid records and adds them to the status block once
@@ -111,8 +111,8 @@ hipError_t launch_zero_f64(double *p, size_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_clear_status(StatusBlock *st, hipStream_t s) {
-    zero_status_kernel<<<1, 64, 0, s>>>(st);
+hipError_t launch_clear_status(StatusBlock *st, hipStream_t s, uint32_t slices) {
+    zero_status_kernel<<<1, 64, 0, s>>>(st, slices);
     return hipGetLastError();
 }
 

@@ -1,0 +1,307 @@
+// gemm_split.hip -- step a2 in the mixed-precision form: the contraction
+// C = X * Y of TCUDB Section 3.3 from 7-bit digit slices on the narrow
+// matrix cores, exact integer partial sums, FP64 combination.
+//
+// With X[g,k] = 2^e_g sum_p dX_p[g,k] 2^(-7p) and Y[k,h] = 2^f_h sum_q
+// dY_q[k,h] 2^(-7q) (split.hip), the kernel evaluates
+//   C[g,h] = 2^(e_g + f_h) * sum_{t=2}^{S+1} 2^(-7t) * sum_{p+q=t} sum_k dX_p dY_q
+// i.e. all digit pairs on the first S anti-diagonals, each later diagonal a
+// correction of the previous ones 2^-7 times smaller.  Each inner sum of
+// digit products is an integer: every product is below 2^14 in magnitude,
+// so a diagonal with D pairs accumulated over L values of k stays exact in
+// the accumulator as long as D * L * 127^2 fits (2^31 for int32, 2^24 for
+// FP32).  BF16 accumulators are flushed into an FP64 sum held in registers
+// every 128 k (S = 7); int8 accumulators stay exact over 16384 k, so a
+// longer contraction is cut into launches of that length that add into C.
+//
+// Matrix-core instructions (gfx950), lane layouts measured on the device:
+//   v_mfma_i32_32x32x32_i8 / v_mfma_f32_32x32x16_bf16: A lane l holds row
+//   l%32, k in [KSTEP/2 * (l/32), +KSTEP/2); B lane l holds column l%32, the
+//   same k range; D lane l item i is row 8*(i/4) + 4*(l/32) + i%4, col l%32.
+// Both consume 16 bytes per lane per operand per k-step (KSTEP = 32 int8
+// digits or 16 BF16 digits).
+//
+// Tiling: 4 waves in a 2 x 2 grid; a wave owns 32 x 64 outputs (int8: two
+// 32 x 32 blocks, workgroup 64 x 128) or 32 x 32 (BF16, which also holds the
+// FP64 sum; workgroup 64 x 64).  One pipeline stage is one k-step of all S
+// slices of both operands in LDS, double-buffered; each wave holds one
+// accumulator per diagonal and block (S * WNB * 16 registers) and reads each
+// slice's fragment once per k-step, so the S(S+1)/2 digit products reuse
+// registers instead of LDS.
+#include <type_traits>
+
+#include "internal.h"
+
+namespace tcu {
+namespace {
+
+typedef int i4 __attribute__((ext_vector_type(4)));
+typedef int i16v __attribute__((ext_vector_type(16)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int THREADS = 256;
+constexpr int BM = 64;  // workgroup rows (2 waves of 32)
+constexpr int GROUP_M = 8;
+constexpr int NUM_XCD = 8;
+
+template <typename T> struct Mfma;
+template <> struct Mfma<int8_t> {
+    using acc_t = i16v;
+    static constexpr long kExactLimit = 2147483647L;  // int32
+    static constexpr int kWNB = 2;                    // 32 x 32 blocks per wave along n
+    static constexpr bool kSum = false;               // one exact chunk per launch
+    __device__ static inline acc_t step(i4 a, i4 b, acc_t c) {
+        return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mfma<uint16_t> {
+    using acc_t = f16v;
+    static constexpr long kExactLimit = 16777216L;  // integers exact in FP32
+    static constexpr int kWNB = 1;
+    static constexpr bool kSum = true;              // FP64 sum over short exact chunks
+    __device__ static inline acc_t step(i4 a, i4 b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, a),
+                                                       __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+    }
+};
+
+// k-steps per exact chunk: the largest power of two with S * L * 127^2 exact
+template <typename T>
+inline int flush_steps(int S) {
+    const int kstep = 32 / (int)sizeof(T);
+    const long L = Mfma<T>::kExactLimit / ((long)S * 16129L) / kstep;
+    int f = 1;
+    while ((long)f * 2 <= L && f < (1 << 20)) f *= 2;
+    return f;
+}
+
+__device__ inline void tile_coords(int tiles_m, int tiles_n, int &tm, int &tn) {
+    const int nt = tiles_m * tiles_n;
+    const int wg = blockIdx.x;
+    const int per = nt / NUM_XCD;
+    const int full = per * NUM_XCD;
+    const int logical = wg < full ? (wg % NUM_XCD) * per + wg / NUM_XCD : wg;
+    const int group = GROUP_M * tiles_n;
+    const int first_m = (logical / group) * GROUP_M;
+    const int gm = min(tiles_m - first_m, GROUP_M);
+    const int in_group = logical % group;
+    tm = first_m + in_group % gm;
+    tn = in_group / gm;
+}
+
+// LDS per buffer: X [S][2 halves][BM rows][16 B], then Y [S][2][BN][16 B].
+template <int S, int BN>
+struct Stage {
+    static constexpr int x_chunks = S * 2 * BM;
+    static constexpr int y_chunks = S * 2 * BN;
+    static constexpr int chunks = x_chunks + y_chunks;
+    static constexpr int per_thread = (chunks + THREADS - 1) / THREADS;
+};
+
+// Chunk c of the stage at k-step kb -> global source and LDS index.  Slices
+// are [p][kb][line][32 B], so chunk (p, line, half) of one k-step is at
+// ((p * nblk + kb) * lines_pad + line) * 32 + half * 16 bytes.
+template <int S, int BN>
+__device__ inline int chunk_dst(int c) {
+    if (c < Stage<S, BN>::x_chunks) {
+        const int p = c / (2 * BM), rem = c % (2 * BM);
+        return (p * 2 + (rem & 1)) * BM + (rem >> 1);
+    }
+    const int cc = c - Stage<S, BN>::x_chunks;
+    const int p = cc / (2 * BN), rem = cc % (2 * BN);
+    return Stage<S, BN>::x_chunks + (p * 2 + (rem & 1)) * BN + (rem >> 1);
+}
+
+template <int S, int BN>
+__device__ inline const char *chunk_src(int c, int kb, int nblk, const char *xs,
+                                        int x_lines_pad, int m0, const char *ys,
+                                        int y_lines_pad, int n0) {
+    if (c < Stage<S, BN>::x_chunks) {
+        const int p = c / (2 * BM), rem = c % (2 * BM);
+        return xs + (((int64_t)p * nblk + kb) * x_lines_pad + m0 + (rem >> 1)) * 32 +
+               (rem & 1) * 16;
+    }
+    const int cc = c - Stage<S, BN>::x_chunks;
+    const int p = cc / (2 * BN), rem = cc % (2 * BN);
+    return ys + (((int64_t)p * nblk + kb) * y_lines_pad + n0 + (rem >> 1)) * 32 +
+           (rem & 1) * 16;
+}
+
+// k-steps [kb0, kb1) of the product; accumulate != 0 adds to C.
+template <typename T, int S>
+__global__ void __launch_bounds__(THREADS)
+gemm_split_kernel(int m, int n, int nblk, int kb0, int kb1, int flush, int accumulate,
+                  const char *__restrict__ xs, int x_lines_pad, const char *__restrict__ ys,
+                  int y_lines_pad, const int *__restrict__ ex, const int *__restrict__ ey,
+                  double *__restrict__ C, int64_t ldc) {
+    using M = Mfma<T>;
+    using acc_t = typename M::acc_t;
+    constexpr int WNB = M::kWNB;
+    constexpr int BN = 64 * WNB;
+    using St = Stage<S, BN>;
+    __shared__ __attribute__((aligned(16))) i4 lds[2][St::chunks];
+
+    const int tiles_m = (m + BM - 1) / BM, tiles_n = (n + BN - 1) / BN;
+    int tm, tn;
+    tile_coords(tiles_m, tiles_n, tm, tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int l32 = lane & 31, half = lane >> 5;
+
+    acc_t acc[S][WNB];
+    double sum[M::kSum ? WNB : 1][M::kSum ? 16 : 1];
+#pragma unroll
+    for (int d = 0; d < S; ++d)
+#pragma unroll
+        for (int b = 0; b < WNB; ++b) acc[d][b] = acc_t{};
+    if constexpr (M::kSum) {
+#pragma unroll
+        for (int b = 0; b < WNB; ++b)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) sum[b][i] = 0.0;
+    }
+
+    i4 pre[St::per_thread];
+    auto load_stage = [&](int kb) {
+#pragma unroll
+        for (int i = 0; i < St::per_thread; ++i) {
+            const int c = threadIdx.x + THREADS * i;
+            if (c < St::chunks)
+                pre[i] = *reinterpret_cast<const i4 *>(
+                    chunk_src<S, BN>(c, kb, nblk, xs, x_lines_pad, m0, ys, y_lines_pad, n0));
+        }
+    };
+    auto store_stage = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < St::per_thread; ++i) {
+            const int c = threadIdx.x + THREADS * i;
+            if (c < St::chunks) lds[buf][chunk_dst<S, BN>(c)] = pre[i];
+        }
+    };
+
+    load_stage(kb0);
+    store_stage(0);
+    __syncthreads();
+    for (int kb = kb0; kb < kb1; ++kb) {
+        const int cur = (kb - kb0) & 1;
+        const bool more = kb + 1 < kb1;
+        if (more) load_stage(kb + 1);
+        i4 fx[S], fy[S][WNB];
+#pragma unroll
+        for (int p = 0; p < S; ++p) {
+            fx[p] = lds[cur][(p * 2 + half) * BM + wm * 32 + l32];
+#pragma unroll
+            for (int b = 0; b < WNB; ++b)
+                fy[p][b] = lds[cur][St::x_chunks + (p * 2 + half) * BN + wn * 32 * WNB +
+                                    b * 32 + l32];
+        }
+#pragma unroll
+        for (int p = 0; p < S; ++p)
+#pragma unroll
+            for (int q = 0; q + p < S; ++q)
+#pragma unroll
+                for (int b = 0; b < WNB; ++b)
+                    acc[p + q][b] = M::step(fx[p], fy[q][b], acc[p + q][b]);
+        if constexpr (M::kSum) {
+            if ((kb - kb0 + 1) % flush == 0 || !more) {
+#pragma unroll
+                for (int d = 0; d < S; ++d)
+#pragma unroll
+                    for (int b = 0; b < WNB; ++b) {
+#pragma unroll
+                        for (int i = 0; i < 16; ++i)
+                            sum[b][i] += ldexp((double)acc[d][b][i], -7 * (d + 2));
+                        acc[d][b] = acc_t{};
+                    }
+            }
+        }
+        if (more) store_stage(cur ^ 1);
+        __syncthreads();
+    }
+
+    // epilogue: C (+)= 2^(e_g + f_h) * sum_t 2^(-7t) S_t
+#pragma unroll
+    for (int b = 0; b < WNB; ++b) {
+        const int col = n0 + wn * 32 * WNB + b * 32 + l32;
+        if (col >= n) continue;
+        const int fcol = ey[col];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int row = m0 + wm * 32 + 8 * (i >> 2) + 4 * half + (i & 3);
+            if (row >= m) continue;
+            double v;
+            if constexpr (M::kSum) {
+                v = sum[b][i];
+            } else {
+                v = 0.0;
+#pragma unroll
+                for (int d = S - 1; d >= 0; --d) v += ldexp((double)acc[d][b][i], -7 * (d + 2));
+            }
+            v = ldexp(v, ex[row] + fcol);
+            double *dst = C + (int64_t)row * ldc + col;
+            *dst = accumulate ? *dst + v : v;
+        }
+    }
+}
+
+template <typename T, int S>
+hipError_t launch_s(int m, int n, int nblk, const void *xs, int x_lines_pad, const void *ys,
+                    int y_lines_pad, const int *ex, const int *ey, double *C, int64_t ldc,
+                    hipStream_t s) {
+    constexpr int BN = 64 * Mfma<T>::kWNB;
+    const int tiles = ((m + BM - 1) / BM) * ((n + BN - 1) / BN);
+    const int flush = flush_steps<T>(S);
+    // int8: one launch per exact chunk (no FP64 sum held in registers);
+    // BF16: one launch, flushing into the FP64 sum every `flush` k-steps
+    const int chunk = Mfma<T>::kSum ? nblk : flush;
+    for (int kb0 = 0; kb0 < nblk; kb0 += chunk) {
+        const int kb1 = kb0 + chunk < nblk ? kb0 + chunk : nblk;
+        gemm_split_kernel<T, S><<<tiles, THREADS, 0, s>>>(
+            m, n, nblk, kb0, kb1, flush, kb0 > 0, static_cast<const char *>(xs), x_lines_pad,
+            static_cast<const char *>(ys), y_lines_pad, ex, ey, C, ldc);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_t(int m, int n, int nblk, int S, const void *xs, int x_lines_pad,
+                    const void *ys, int y_lines_pad, const int *ex, const int *ey, double *C,
+                    int64_t ldc, hipStream_t s) {
+    switch (S) {
+#define TCU_GS_CASE(v) \
+    case v: return launch_s<T, v>(m, n, nblk, xs, x_lines_pad, ys, y_lines_pad, ex, ey, C, ldc, s);
+        TCU_GS_CASE(1) TCU_GS_CASE(2) TCU_GS_CASE(3) TCU_GS_CASE(4)
+        TCU_GS_CASE(5) TCU_GS_CASE(6) TCU_GS_CASE(7) TCU_GS_CASE(8)
+#undef TCU_GS_CASE
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+int split_chunk_steps(int S, int digit_bf16) {
+    return digit_bf16 ? flush_steps<uint16_t>(S) : flush_steps<int8_t>(S);
+}
+
+hipError_t launch_gemm_split(int m, int n, int k, int S, int digit_bf16, const void *xs,
+                             int x_lines_pad, const void *ys, int y_lines_pad, int len_pad,
+                             const int *ex, const int *ey, double *C, int64_t ldc,
+                             hipStream_t s) {
+    if (m == 0 || n == 0) return hipSuccess;
+    if (x_lines_pad % 128 || y_lines_pad % 128 || len_pad % 64 || len_pad < k)
+        return hipErrorInvalidValue;
+    if (x_lines_pad < m || y_lines_pad < n) return hipErrorInvalidValue;
+    const int kstep = digit_bf16 ? 16 : 32;
+    const int nblk = len_pad / kstep;
+    if (nblk == 0) return hipErrorInvalidValue;
+    if (digit_bf16)
+        return launch_t<uint16_t>(m, n, nblk, S, xs, x_lines_pad, ys, y_lines_pad, ex, ey, C,
+                                  ldc, s);
+    return launch_t<int8_t>(m, n, nblk, S, xs, x_lines_pad, ys, y_lines_pad, ex, ey, C, ldc, s);
+}
+
+}  // namespace tcu

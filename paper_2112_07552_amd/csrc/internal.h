@@ -29,12 +29,33 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // encode.hip
 hipError_t launch_zero_f64(double *p, size_t n, hipStream_t s);
-hipError_t launch_clear_status(StatusBlock *st, hipStream_t s);
+hipError_t launch_clear_status(StatusBlock *st, hipStream_t s, uint32_t slices = 0);
 hipError_t launch_encode(const tcu_relation &R, int transpose, int rows, int cols, double *out,
                          StatusBlock *st, int which, hipStream_t s);
 hipError_t launch_gather(const tcu_relation &R, int transpose, int rows, int cols,
                          const double *src, double *dst, hipStream_t s);
 hipError_t launch_f64_to_i32(const double *src, int32_t *dst, size_t n, hipStream_t s);
+
+// split.hip: per-line max |z| (axis 0: rows, 1: columns) into maxbits (bit
+// patterns of non-negative doubles), and the digit slices of Z.
+hipError_t launch_line_max(const double *Z, int rows, int cols, int64_t ld, int axis,
+                           unsigned long long *maxbits, StatusBlock *st, hipStream_t s);
+// Lines are rows (axis 0, lines_pad >= rows, len_pad >= cols) or columns
+// (axis 1, lines_pad >= cols, len_pad >= rows); lines_pad % 128 == 0,
+// len_pad % 64 == 0.  Layout: slices[p][t / KSTEP][line][t % KSTEP].
+hipError_t launch_split(const double *Z, int rows, int cols, int64_t ld, int axis,
+                        const unsigned long long *maxbits, int S, int digit_bf16, void *out,
+                        int lines_pad, int len_pad, int *exps, hipStream_t s);
+
+// gemm_split.hip: C (m x n, ldc) = 2^(ex[g] + ey[h]) * sum over digit pairs
+// (p, q) with p + q <= S + 1 of 2^(-7(p+q)) X_p Y_q, digits from launch_split
+// (X lines = rows of op(A), Y lines = columns of op(B), both of length k).
+hipError_t launch_gemm_split(int m, int n, int k, int S, int digit_bf16, const void *xs,
+                             int x_lines_pad, const void *ys, int y_lines_pad, int len_pad,
+                             const int *ex, const int *ey, double *C, int64_t ldc,
+                             hipStream_t s);
+// k-steps per exact integer chunk of the split GEMM (host side of its plan).
+int split_chunk_steps(int S, int digit_bf16);
 
 // gemm_f64.hip: C (m x n, ldc) = op(A) * op(B), FP64 matrix cores.
 hipError_t launch_gemm_f64(int trans_a, int trans_b, int m, int n, int k, const double *A,

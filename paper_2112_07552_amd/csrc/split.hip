@@ -1,0 +1,272 @@
+// split.hip -- step a0 of the mixed-precision form: per-line statistics and
+// the fixed-point slicing of an FP64 encoding into narrow integer digits.
+//
+// TCUDB's feasibility test (Section 4.2.1) reads per-column min/max metadata
+// to pick the narrowest matrix-unit type that still gives acceptable results,
+// or refuses.  The mixed form generalises it: every line (row of X, column of
+// Y) gets a power-of-two scale from its largest magnitude, and the scaled
+// values are cut into S digits of 7 bits that the matrix units multiply
+// exactly:
+//   mx   = max |z| over the line,  e = exponent with 2^(e-1) <= mx < 2^e
+//          (e = 0 for an all-zero line),
+//   r_0  = z * 2^-e,  t = r_{p-1} * 2^7,  d_p = trunc(t),  r_p = t - d_p,
+// so z = 2^e (sum_p d_p 2^(-7p) + r_S 2^(-7S)) exactly, |d_p| <= 127, and
+// every step is exact in FP64 (power-of-two scalings, removal of an
+// integer part).  Digits are stored as int8 or as BF16 (|d| <= 127 has at
+// most 7 significant bits, exact in BF16).
+//
+// Output layout, blocked for the split GEMM's loads: the position t along a
+// line is cut into blocks of 32 bytes of digits (KSTEP = 32 int8 or 16 BF16
+// digits, one matrix-core k-step), and
+//   slices[p][t / KSTEP][line][t % KSTEP]
+// so one k-step of 64 or 128 consecutive lines is one contiguous run.  Lines
+// are padded with zero digits to `lines_pad` (a multiple of 128) and t to
+// `len_pad` (a multiple of 64); slice p starts at p * lines_pad * len_pad.
+// Lines are rows of the input (no transpose) or its columns (transposed
+// through LDS).
+//
+// Both kernels are HBM-bound: the statistics read 8 B per element, the split
+// reads 8 B and writes S * sizeof(digit) B per element.
+#include "internal.h"
+
+namespace tcu {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kDigitBits = 7;
+
+__device__ inline unsigned long long abs_bits(double z) {
+    return (unsigned long long)__double_as_longlong(fabs(z));
+}
+
+// Max |z| per row: one wave per row.
+__global__ void __launch_bounds__(kThreads)
+row_max_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
+               unsigned long long *__restrict__ maxbits, StatusBlock *st) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = blockIdx.x * (kThreads / 64) + wave;
+    if (row >= rows) return;
+    const double *z = Z + (int64_t)row * ld;
+    double mx = 0.0;
+    bool bad = false;
+    for (int c = lane; c < cols; c += 64) {
+        const double v = z[c];
+        if (!isfinite(v)) bad = true;
+        else mx = fmax(mx, fabs(v));
+    }
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    const unsigned long long anybad = __ballot(bad);
+    if (lane == 0) {
+        maxbits[row] = abs_bits(mx);
+        if (anybad) atomicOr(&st->flags, kFlagNonFinite);
+    }
+}
+
+// Max |z| per column: threads own columns, blocks own chunks of rows, and the
+// partial maxima meet in an atomic max on the (monotone) bit patterns of the
+// non-negative doubles.  maxbits must be zero beforehand.
+constexpr int kColChunk = 256;
+
+__global__ void __launch_bounds__(kThreads)
+col_max_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
+               unsigned long long *__restrict__ maxbits, StatusBlock *st) {
+    const int col = blockIdx.x * kThreads + threadIdx.x;
+    const int r0 = blockIdx.y * kColChunk;
+    const int r1 = min(rows, r0 + kColChunk);
+    double mx = 0.0;
+    bool bad = false;
+    if (col < cols) {
+        for (int r = r0; r < r1; ++r) {
+            const double v = Z[(int64_t)r * ld + col];
+            if (!isfinite(v)) bad = true;
+            else mx = fmax(mx, fabs(v));
+        }
+        atomicMax(maxbits + col, abs_bits(mx));
+    }
+    const unsigned long long anybad = __ballot(bad);
+    if (anybad && (threadIdx.x & 63) == 0) atomicOr(&st->flags, kFlagNonFinite);
+}
+
+__device__ inline int line_exponent(unsigned long long bits) {
+    const double mx = __longlong_as_double((long long)bits);
+    int e = 0;
+    if (mx > 0.0) frexp(mx, &e);
+    return e;
+}
+
+template <typename T> __device__ inline T to_digit(double d);
+template <> __device__ inline int8_t to_digit<int8_t>(double d) { return (int8_t)(int)d; }
+template <> __device__ inline uint16_t to_digit<uint16_t>(double d) {
+    // |d| <= 127 is exact in FP32 and its low 16 mantissa bits are zero
+    return (uint16_t)(__float_as_uint((float)d) >> 16);
+}
+
+// One vector store of 8 digits (8 B of int8 or 16 B of BF16); the slice
+// layout keeps every group of 8 aligned.
+__device__ inline void store8(int8_t *dst, const int8_t (&d)[8]) {
+    uint2 v;
+    v.x = (uint32_t)(uint8_t)d[0] | ((uint32_t)(uint8_t)d[1] << 8) |
+          ((uint32_t)(uint8_t)d[2] << 16) | ((uint32_t)(uint8_t)d[3] << 24);
+    v.y = (uint32_t)(uint8_t)d[4] | ((uint32_t)(uint8_t)d[5] << 8) |
+          ((uint32_t)(uint8_t)d[6] << 16) | ((uint32_t)(uint8_t)d[7] << 24);
+    *reinterpret_cast<uint2 *>(dst) = v;
+}
+__device__ inline void store8(uint16_t *dst, const uint16_t (&d)[8]) {
+    uint4 v;
+    v.x = (uint32_t)d[0] | ((uint32_t)d[1] << 16);
+    v.y = (uint32_t)d[2] | ((uint32_t)d[3] << 16);
+    v.z = (uint32_t)d[4] | ((uint32_t)d[5] << 16);
+    v.w = (uint32_t)d[6] | ((uint32_t)d[7] << 16);
+    *reinterpret_cast<uint4 *>(dst) = v;
+}
+
+template <typename T>
+__device__ inline int64_t slice_offset(int line, int t, int lines_pad) {
+    constexpr int kstep = 32 / (int)sizeof(T);
+    return ((int64_t)(t / kstep) * lines_pad + line) * kstep + (t % kstep);
+}
+
+// Lines are rows: each thread handles 8 consecutive elements of one row and
+// writes 8 digits per slice; padding rows and columns get zero digits.
+template <typename T, int S>
+__global__ void __launch_bounds__(kThreads)
+split_rows_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
+                  const unsigned long long *__restrict__ maxbits, T *__restrict__ out,
+                  int lines_pad, int len_pad, int *__restrict__ exps) {
+    const int groups = len_pad / 8;
+    const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (gid >= (int64_t)lines_pad * groups) return;
+    const int row = (int)(gid / groups);
+    const int c0 = (int)(gid % groups) * 8;
+    const bool live = row < rows;
+    const int e = live ? line_exponent(maxbits[row]) : 0;
+    if (live && c0 == 0) exps[row] = e;
+    T dig[S][8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int c = c0 + j;
+        double z = (live && c < cols) ? Z[(int64_t)row * ld + c] : 0.0;
+        if (!isfinite(z)) z = 0.0;
+        double r = ldexp(z, -e);
+#pragma unroll
+        for (int p = 0; p < S; ++p) {
+            const double t = ldexp(r, kDigitBits);
+            const double d = trunc(t);
+            dig[p][j] = to_digit<T>(d);
+            r = t - d;
+        }
+    }
+    const int64_t slice_stride = (int64_t)lines_pad * len_pad;
+    T *o = out + slice_offset<T>(row, c0, lines_pad);
+#pragma unroll
+    for (int p = 0; p < S; ++p) store8(o + (int64_t)p * slice_stride, dig[p]);
+}
+
+// Lines are columns: a block turns a 64 x 64 tile of Z into S tiles of
+// digits transposed through LDS, so both the FP64 reads and the digit
+// writes are contiguous.  Rows in [rows, out_ld) get zero digits.
+constexpr int kTile = 64;
+
+template <typename T, int S>
+__global__ void __launch_bounds__(kThreads)
+split_cols_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
+                  const unsigned long long *__restrict__ maxbits, T *__restrict__ out,
+                  int lines_pad, int len_pad, int *__restrict__ exps) {
+    __shared__ T tile[S][kTile][kTile + 4];  // [p][col][row]
+    const int r0 = blockIdx.x * kTile, c0 = blockIdx.y * kTile;
+    const int tc = threadIdx.x & 63, tr = threadIdx.x >> 6;  // 4 row lanes
+    const int col = c0 + tc;
+    const int e = col < cols ? line_exponent(maxbits[col]) : 0;
+    if (blockIdx.x == 0 && tr == 0 && col < cols) exps[col] = e;
+    for (int rr = tr; rr < kTile; rr += 4) {
+        const int row = r0 + rr;
+        double z = (row < rows && col < cols) ? Z[(int64_t)row * ld + col] : 0.0;
+        if (!isfinite(z)) z = 0.0;
+        double r = ldexp(z, -e);
+#pragma unroll
+        for (int p = 0; p < S; ++p) {
+            const double t = ldexp(r, kDigitBits);
+            const double d = trunc(t);
+            tile[p][tc][rr] = to_digit<T>(d);
+            r = t - d;
+        }
+    }
+    __syncthreads();
+    // write: thread -> (column, 16 consecutive rows) of each slice; the 16
+    // rows lie inside one k-step block (KSTEP is 16 or 32)
+    const int wc = threadIdx.x >> 2, wr = (threadIdx.x & 3) * 16;
+    const int ocol = c0 + wc;
+    const int64_t slice_stride = (int64_t)lines_pad * len_pad;
+#pragma unroll
+    for (int p = 0; p < S; ++p) {
+        T *dst = out + (int64_t)p * slice_stride + slice_offset<T>(ocol, r0 + wr, lines_pad);
+        T v0[8], v1[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) { v0[j] = tile[p][wc][wr + j]; v1[j] = tile[p][wc][wr + 8 + j]; }
+        store8(dst, v0);
+        store8(dst + 8, v1);
+    }
+}
+
+template <typename T, int S>
+hipError_t launch_split_s(const double *Z, int rows, int cols, int64_t ld, int axis,
+                          const unsigned long long *maxbits, T *out, int lines_pad, int len_pad,
+                          int *exps, hipStream_t s) {
+    if (axis == 0) {
+        const int64_t work = (int64_t)lines_pad * (len_pad / 8);
+        const unsigned grid = (unsigned)((work + kThreads - 1) / kThreads);
+        split_rows_kernel<T, S><<<grid, kThreads, 0, s>>>(Z, rows, cols, ld, maxbits, out,
+                                                          lines_pad, len_pad, exps);
+    } else {
+        dim3 grid(len_pad / kTile, lines_pad / kTile);
+        split_cols_kernel<T, S><<<grid, kThreads, 0, s>>>(Z, rows, cols, ld, maxbits, out,
+                                                          lines_pad, len_pad, exps);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_split_t(const double *Z, int rows, int cols, int64_t ld, int axis,
+                          const unsigned long long *maxbits, int S, T *out, int lines_pad,
+                          int len_pad, int *exps, hipStream_t s) {
+    switch (S) {
+#define TCU_SPLIT_CASE(n) \
+    case n: return launch_split_s<T, n>(Z, rows, cols, ld, axis, maxbits, out, lines_pad, len_pad, exps, s);
+        TCU_SPLIT_CASE(1) TCU_SPLIT_CASE(2) TCU_SPLIT_CASE(3) TCU_SPLIT_CASE(4)
+        TCU_SPLIT_CASE(5) TCU_SPLIT_CASE(6) TCU_SPLIT_CASE(7) TCU_SPLIT_CASE(8)
+#undef TCU_SPLIT_CASE
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_line_max(const double *Z, int rows, int cols, int64_t ld, int axis,
+                           unsigned long long *maxbits, StatusBlock *st, hipStream_t s) {
+    if (rows == 0 || cols == 0) return hipSuccess;
+    if (axis == 0) {
+        const unsigned grid = (unsigned)((rows + 3) / 4);
+        row_max_kernel<<<grid, kThreads, 0, s>>>(Z, rows, cols, ld, maxbits, st);
+    } else {
+        // zero the maxima with a kernel (the bit pattern of +0.0 is all zeros)
+        hipError_t e = launch_zero_f64(reinterpret_cast<double *>(maxbits), (size_t)cols, s);
+        if (e != hipSuccess) return e;
+        dim3 grid((cols + kThreads - 1) / kThreads, (rows + kColChunk - 1) / kColChunk);
+        col_max_kernel<<<grid, kThreads, 0, s>>>(Z, rows, cols, ld, maxbits, st);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_split(const double *Z, int rows, int cols, int64_t ld, int axis,
+                        const unsigned long long *maxbits, int S, int digit_bf16, void *out,
+                        int lines_pad, int len_pad, int *exps, hipStream_t s) {
+    if (lines_pad % 128 != 0 || len_pad % 64 != 0) return hipErrorInvalidValue;
+    if (digit_bf16)
+        return launch_split_t<uint16_t>(Z, rows, cols, ld, axis, maxbits, S,
+                                        static_cast<uint16_t *>(out), lines_pad, len_pad, exps,
+                                        s);
+    return launch_split_t<int8_t>(Z, rows, cols, ld, axis, maxbits, S,
+                                  static_cast<int8_t *>(out), lines_pad, len_pad, exps, s);
+}
+
+}  // namespace tcu

@@ -19,7 +19,8 @@ import torch
 from . import _lib
 from ._lib import TcuError, check
 
-PRECISIONS = {"fp64": _lib.TCU_PREC_FP64, "split": _lib.TCU_PREC_SPLIT_BF16}
+PRECISIONS = {"fp64": _lib.TCU_PREC_FP64, "split_bf16": _lib.TCU_PREC_SPLIT_BF16,
+              "split_i8": _lib.TCU_PREC_SPLIT_I8}
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -77,6 +78,48 @@ def alloc_workspace(nbytes: int, device) -> torch.Tensor:
     if ws.data_ptr() % 256:
         raise RuntimeError("torch returned a workspace that is not 256-byte aligned")
     return ws
+
+
+def split_slices(precision: str, k: int, tol: float) -> int:
+    """Step a0 host plan: slice count for a contraction of length k (raises
+    TcuError with TCU_ERR_INFEASIBLE when no slice count meets tol)."""
+    S = _lib.load().tcu_split_slices(PRECISIONS[precision], int(k), float(tol))
+    if S < 0:
+        raise TcuError(S, "tcu_split_slices")
+    return S
+
+
+def _pad(x: int, m: int) -> int:
+    return (x + m - 1) // m * m
+
+
+def split(Z: torch.Tensor, axis: int, precision: str, S: int, ws: Optional[torch.Tensor] = None):
+    """Step a0 device part: (exps int32 [lines], slices [S, lines_pad, len_pad]
+    in the library's blocked layout, raw dtype int8 or int16 (BF16 bits))."""
+    _need_cuda(Z, "Z", (torch.float64,))
+    rows, cols = Z.shape
+    lines, length = (rows, cols) if axis == 0 else (cols, rows)
+    lines_pad, len_pad = _pad(lines, 128), _pad(length, 64)
+    dt = torch.int8 if precision == "split_i8" else torch.int16
+    slices = torch.empty((S, lines_pad * len_pad), dtype=dt, device=Z.device)
+    exps = torch.empty(lines, dtype=torch.int32, device=Z.device)
+    need = 256 + 8 * lines_pad
+    if ws is None or ws.numel() < need:
+        ws = alloc_workspace(need, Z.device)
+    check(_lib.load().tcu_split(_ptr(Z), rows, cols, Z.shape[1], axis, PRECISIONS[precision], S,
+                                _ptr(slices), lines_pad, len_pad, _ptr(exps), _ptr(ws),
+                                ws.numel(), _stream(Z.device)), "tcu_split")
+    return exps, slices, (lines_pad, len_pad), ws
+
+
+def unblock_slices(slices: torch.Tensor, lines: int, length: int, lines_pad: int, len_pad: int,
+                   precision: str) -> torch.Tensor:
+    """Reorder the blocked layout [S][t / KSTEP][line][t % KSTEP] to
+    [S][line][t] (index bookkeeping only)."""
+    kstep = 32 if precision == "split_i8" else 16
+    S = slices.shape[0]
+    v = slices.reshape(S, len_pad // kstep, lines_pad, kstep).permute(0, 2, 1, 3)
+    return v.reshape(S, lines_pad, len_pad)[:, :lines, :length]
 
 
 def encode(group, key, val, rows: int, cols: int, transpose: bool = False,

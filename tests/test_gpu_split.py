@@ -1,0 +1,189 @@
+"""GPU parity of the mixed-precision form (steps a0 and the split a2).
+
+a0: the digit slices and line exponents are integer codes, so they must match
+the oracle's slicing bit for bit.  a2: the product must meet the guaranteed
+bound |C - C*| <= tol * K * max|X[g,:]| * max|Y[:,h]| against the oracle's
+C*, cell by cell; integer-valued inputs and 0/1 encodings must be exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2112_07552_amd import ops
+from paper_2112_07552_amd import workloads as wl
+
+from .gpu_util import abs_rel, cuda_or_skip, err_cw, to_orc
+
+pytestmark = pytest.mark.gpu
+
+FORMS = ["split_i8", "split_bf16"]
+
+
+def special_matrix(R, L, seed, kind="uniform"):
+    Z = wl.draw_values(kind, R * L, seed, 0, lo=-2**15, hi=2**15).reshape(R, L).clone()
+    Z[min(3, R - 1), :] = 0.0                 # an all-zero row
+    Z[0, min(2, L - 1)] = 2.0 ** -1070         # a subnormal
+    Z[R // 2, L // 2] = -3.5e300               # a huge magnitude in one line
+    return Z
+
+
+@pytest.mark.parametrize("precision", FORMS)
+@pytest.mark.parametrize("axis", [0, 1])
+@pytest.mark.parametrize("R,L,S", [(130, 77, 7), (64, 200, 3), (1, 1, 8), (257, 129, 5)])
+def test_split_bit_exact(orc, precision, axis, R, L, S):
+    dev = cuda_or_skip()
+    Z = special_matrix(R, L, R * 31 + L + S, "loguniform")
+    exps, sl, (lp, lnp), ws = ops.split(Z.to(dev), axis, precision, S)
+    assert ops.sync_status(ws)[0] == 0
+    lines, length = (R, L) if axis == 0 else (L, R)
+    got = ops.unblock_slices(sl, lines, length, lp, lnp, precision).cpu()
+    if precision == "split_bf16":  # BF16 bits -> values
+        got = (got.to(torch.int32) << 16).view(torch.float32).to(torch.float64)
+    else:
+        got = got.to(torch.float64)
+    oe, osl = orc.split(Z.numpy(), axis, S, 7)
+    if axis == 1:
+        osl = osl.transpose(0, 2, 1)  # oracle is [p][row][col]; lines are columns
+    assert np.array_equal(exps.cpu().numpy(), oe)
+    assert np.array_equal(got.numpy(), osl)
+    # padding is zero
+    full = ops.unblock_slices(sl, lp, lnp, lp, lnp, precision).cpu()
+    assert torch.all(full[:, lines:, :] == 0) and torch.all(full[:, :, length:] == 0)
+
+
+@pytest.mark.parametrize("precision", FORMS)
+def test_split_flags_non_finite(precision):
+    dev = cuda_or_skip()
+    Z = torch.ones((70, 90), dtype=torch.float64)
+    Z[5, 7] = float("nan")
+    Z[60, 1] = float("inf")
+    for axis in (0, 1):
+        _, _, _, ws = ops.split(Z.to(dev), axis, precision, 3)
+        assert ops.sync_status(ws)[0] == ops._lib.TCU_ERR_NONFINITE
+
+
+def bound_check(orc, A, B, M, K, N, Cg, tol):
+    """|C - C*| <= tol * K * rowmax|X| * colmax|Y| in every cell."""
+    RA, RB = to_orc(orc, A), to_orc(orc, B)
+    Co, _, _ = orc.join_agg(RA, RB, M, K, N)
+    X, _ = orc.encode_A(RA, M, K)
+    Y, _ = orc.encode_B(RB, K, N)
+    mu = np.abs(X).max(axis=1)
+    nu = np.abs(Y).max(axis=0)
+    bound = tol * K * np.outer(mu, nu)
+    diff = np.abs(Cg - Co)
+    assert np.all(diff <= bound), float(np.max(diff / np.maximum(bound, 1e-300)))
+    S, _, _ = orc.join_agg(abs_rel(orc, RA), abs_rel(orc, RB), M, K, N)
+    return err_cw(Cg, Co, S)
+
+
+@pytest.mark.parametrize("precision", FORMS)
+@pytest.mark.parametrize("tol", [1e-6, 1e-9, 1e-12])
+@pytest.mark.parametrize("seed,nA,nB,M,K,N,kind", [
+    (50, 40_000, 50_000, 200, 129, 257, "uniform"),
+    (51, 30_000, 30_000, 130, 70, 65, "loguniform"),
+    (52, 20_000, 30_000, 1, 300, 140, "uniform"),
+])
+def test_split_forward_within_bound(orc, precision, tol, seed, nA, nB, M, K, N, kind):
+    dev = cuda_or_skip()
+    A = wl.random_relation(nA, M, K, seed, 1, device=dev, values=kind)
+    B = wl.random_relation(nB, N, K, seed, 2, device=dev, values=kind)
+    Cg, _, ws = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, M, K, N,
+                                 precision=precision, tol=tol)
+    st, info = ops.sync_status(ws)
+    assert st == 0 and info["slices"] == ops.split_slices(precision, K, tol)
+    bound_check(orc, A, B, M, K, N, Cg.cpu().numpy(), tol)
+
+
+@pytest.mark.parametrize("precision", FORMS)
+def test_split_dense_workload_2pow20(orc, precision):
+    """2^20 records per table, U[-1,1): bound on sampled cells, and the
+    measured componentwise error against |X||Y| stays far below 1e-12."""
+    from .test_gpu_parity import sampled_checks
+    dev = cuda_or_skip()
+    N = 1024
+    A, B = wl.mm_query(N, N, N, seed=1, device=dev)
+    Cg, _, ws = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, N, N, N,
+                                 precision=precision, tol=1e-12, unique=True)
+    assert ops.sync_status(ws)[0] == 0
+    assert sampled_checks(orc, A, B, Cg, N, N, N, seed=5, ncells=2048) <= 1e-12
+
+
+@pytest.mark.parametrize("precision", FORMS)
+@pytest.mark.parametrize("lo,hi", [(0, 2), (-2**15, 2**15)])
+def test_split_integer_values_exact(orc, precision, lo, hi):
+    """Integer inputs below 2^15 need at most 3 digits; with 7 slices every
+    nonzero digit pair is kept and all sums are exact integers, so C is
+    exact (the rows of the paper's MAPE table, Section 5.4.1)."""
+    dev = cuda_or_skip()
+    N = 512
+    A, B = wl.mm_query(N, N, N, seed=8, values="int", lo=lo, hi=hi, device=dev)
+    Cg, _, _ = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, N, N, N,
+                                precision=precision, tol=1e-12)
+    RA, RB = to_orc(orc, A), to_orc(orc, B)
+    rows = np.arange(0, N, 7, dtype=np.int32)
+    Co, _, _ = orc.join_agg(RA, RB, N, N, N, rows=rows)
+    assert np.array_equal(Cg.cpu().numpy()[rows], Co)
+
+
+def test_split_i8_long_contraction_chunks(orc):
+    """K above the int8 exact-chunk length (16384 at S = 7): launches add
+    their chunks into C."""
+    dev = cuda_or_skip()
+    M, K, N = 70, 20_000, 90
+    A = wl.random_relation(200_000, M, K, 53, 1, device=dev)
+    B = wl.random_relation(200_000, N, K, 53, 2, device=dev)
+    Cg, _, ws = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, M, K, N,
+                                 precision="split_i8", tol=1e-12)
+    assert ops.sync_status(ws)[0] == 0
+    bound_check(orc, A, B, M, K, N, Cg.cpu().numpy(), 1e-12)
+
+
+@pytest.mark.parametrize("precision", FORMS)
+def test_split_infeasible_tolerance(precision):
+    dev = cuda_or_skip()
+    A = wl.random_relation(100, 10, 10, 54, 1, device=dev)
+    B = wl.random_relation(100, 10, 10, 54, 2, device=dev)
+    with pytest.raises(ops.TcuError) as ei:
+        ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, 10, 10, 10,
+                         precision=precision, tol=1e-18)
+    assert ei.value.status == ops._lib.TCU_ERR_INFEASIBLE
+
+
+@pytest.mark.parametrize("precision", FORMS)
+def test_split_non_finite_reported(precision):
+    dev = cuda_or_skip()
+    A = wl.random_relation(2000, 30, 20, 55, 1, device=dev)
+    B = wl.random_relation(2000, 40, 20, 55, 2, device=dev)
+    A.val[17] = float("nan")
+    _, _, ws = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, 30, 20, 40,
+                                precision=precision, tol=1e-9)
+    assert ops.sync_status(ws)[0] == ops._lib.TCU_ERR_NONFINITE
+
+
+@pytest.mark.parametrize("precision", FORMS)
+def test_split_adjoint_within_bound(orc, precision):
+    """Both adjoint products carry the same guarantee with their contraction
+    lengths: |dA - dA*| <= tol * N * max|W[g,:]| * max|Y[k,:]| and
+    |dB - dB*| <= tol * M * max|X[:,k]| * max|W[:,h]|."""
+    dev = cuda_or_skip()
+    M, K, N = 150, 110, 170
+    tol = 1e-12
+    A = wl.random_relation(30_000, M, K, 56, 1, device=dev)
+    B = wl.random_relation(30_000, N, K, 56, 2, device=dev)
+    W = wl.draw_values("uniform", M * N, 56, 99, device=dev).reshape(M, N)
+    dA, dB, ws = ops.join_agg_bwd(A.group, A.key, A.val, B.key, B.group, B.val, M, K, N, W,
+                                  precision=precision, tol=tol)
+    assert ops.sync_status(ws)[0] == 0
+    RA, RB = to_orc(orc, A), to_orc(orc, B)
+    Wn = W.cpu().numpy()
+    X, _ = orc.encode_A(RA, M, K)
+    Y, _ = orc.encode_B(RB, K, N)
+    ga = orc.grad(RA, RB, M, K, N, Wn, "A")
+    gb = orc.grad(RA, RB, M, K, N, Wn, "B")
+    gA, kA = A.group.cpu().numpy(), A.key.cpu().numpy()
+    kB, hB = B.key.cpu().numpy(), B.group.cpu().numpy()
+    bA = tol * N * np.abs(Wn).max(axis=1)[gA] * np.abs(Y).max(axis=1)[kA]
+    bB = tol * M * np.abs(X).max(axis=0)[kB] * np.abs(Wn).max(axis=0)[hB]
+    assert np.all(np.abs(dA.cpu().numpy() - ga) <= bA)
+    assert np.all(np.abs(dB.cpu().numpy() - gb) <= bB)

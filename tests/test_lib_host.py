@@ -108,3 +108,46 @@ def test_argument_errors_return_before_launch(lib):
     assert lib.tcu_encode(C.byref(A), 3, 4, 4, cbuf, C.c_void_p(0x100000), 256, None) == _lib.TCU_ERR_ARG
     assert lib.tcu_encode(C.byref(A), 0, 4, 4, None, C.c_void_p(0x100000), 256, None) == _lib.TCU_ERR_ARG
     assert lib.tcu_sync_status(None, None, None) == _lib.TCU_ERR_WORKSPACE
+
+
+def test_split_plan_host_only(lib):
+    """The precision plan (feasibility test retargeted) needs no device."""
+    for p in (_lib.TCU_PREC_SPLIT_BF16, _lib.TCU_PREC_SPLIT_I8):
+        prev = 0
+        for tol in (1e-3, 1e-6, 1e-9, 1e-12):
+            S = lib.tcu_split_slices(p, 4096, tol)
+            assert 1 <= S <= _lib.TCU_MAX_SLICES and S >= prev
+            prev = S
+        # the bound's truncation part alone: 4.04 (S+1) 2^-7S must not exceed tol
+        S = lib.tcu_split_slices(p, 4096, 1e-12)
+        assert 4.04 * (S + 1) * 2.0 ** (-7 * S) <= 1e-12
+        assert 4.04 * S * 2.0 ** (-7 * (S - 1)) > 1e-12  # S - 1 slices would not do
+        assert lib.tcu_split_slices(p, 4096, 1e-18) == _lib.TCU_ERR_INFEASIBLE
+        assert lib.tcu_split_slices(p, 0, 1e-9) == _lib.TCU_ERR_ARG
+        assert lib.tcu_split_slices(p, 64, 0.0) == lib.tcu_split_slices(p, 64, 1e-12)
+    assert lib.tcu_split_slices(_lib.TCU_PREC_FP64, 64, 1e-9) == _lib.TCU_ERR_ARG
+
+
+def test_split_argument_errors(lib):
+    buf = C.c_void_p(0x100000)
+    # bad axis, S out of range, padding not a multiple of 128 / 64, FP64 precision
+    assert lib.tcu_split(buf, 10, 10, 10, 2, 2, 3, buf, 128, 64, buf, buf, 1 << 20, None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_split(buf, 10, 10, 10, 0, 2, 9, buf, 128, 64, buf, buf, 1 << 20, None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_split(buf, 10, 10, 10, 0, 2, 3, buf, 100, 64, buf, buf, 1 << 20, None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_split(buf, 10, 10, 10, 0, 2, 3, buf, 128, 60, buf, buf, 1 << 20, None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_split(buf, 10, 10, 10, 0, 0, 3, buf, 128, 64, buf, buf, 1 << 20, None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_split(buf, 10, 10, 5, 0, 2, 3, buf, 128, 64, buf, buf, 1 << 20, None) == _lib.TCU_ERR_ARG
+    # workspace too small for the line maxima
+    assert lib.tcu_split(buf, 10, 10, 10, 0, 2, 3, buf, 128, 64, buf, buf, 300, None) == _lib.TCU_ERR_WORKSPACE
+
+
+def test_mixed_forms_workspace_and_infeasible(lib):
+    A, B = rel(10), rel(10)
+    fp64 = lib.tcu_workspace_bytes(C.byref(A), C.byref(B), 300, 200, 100, 0, 0)
+    i8 = lib.tcu_workspace_bytes(C.byref(A), C.byref(B), 300, 200, 100, 2, 0)
+    bf = lib.tcu_workspace_bytes(C.byref(A), C.byref(B), 300, 200, 100, 1, 0)
+    assert fp64 < i8 < bf
+    # an unreachable tolerance is refused before any launch
+    cbuf = C.c_void_p(0x2000)
+    assert lib.tcu_join_agg_fwd(C.byref(A), C.byref(B), 4, 4, 4, 2, 1e-18, cbuf, None,
+                                C.c_void_p(0x100000), 1 << 30, None) == _lib.TCU_ERR_INFEASIBLE
