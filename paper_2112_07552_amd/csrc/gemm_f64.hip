@@ -50,10 +50,29 @@ struct Tile {
 // Global -> registers: 4 chunks of 2 doubles per thread.
 // KC:  element (o, kk) of the tile is P[(o0 + o) * ld + k0 + kk]
 // !KC: element (o, kk) of the tile is P[(k0 + kk) * ld + o0 + o]
+// `fast` (uniform across the workgroup) says the whole 128 x 16 tile lies
+// inside the operand and 16-byte loads are aligned: then the loads carry no
+// per-element guard, so the compiler emits straight-line dwordx4 loads that
+// stay in flight across the MFMAs of the current stage.  Edge tiles take the
+// guarded path.
 template <bool KC>
 __device__ inline void load_tile(const double *__restrict__ P, int64_t ld, int o0, int k0,
                                  int oext, int kext, bool vec, double2 (&r)[4]) {
     const int tid = threadIdx.x;
+    const bool fast = vec && o0 + 128 <= oext && k0 + BK <= kext;
+    if (fast) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int c = tid + THREADS * i;
+            int o, kk;
+            if (KC) { o = c >> 3; kk = (c & 7) * 2; }
+            else    { kk = c >> 6; o = (c & 63) * 2; }
+            const int64_t base = KC ? (int64_t)(o0 + o) * ld + k0 + kk
+                                    : (int64_t)(k0 + kk) * ld + o0 + o;
+            r[i] = *reinterpret_cast<const double2 *>(P + base);
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int c = tid + THREADS * i;
