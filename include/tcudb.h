@@ -142,7 +142,8 @@ int tcu_split_slices(tcu_precision p, int32_t k, double tol);
  * p = 1..S: t = r_{p-1} 2^7, d_p = trunc(t), r_p = t - d_p.
  * exps[line] = e (int32, `lines` entries); digits d_p are written as int8
  * (TCU_PREC_SPLIT_I8) or BF16 (TCU_PREC_SPLIT_BF16) in the blocked layout
- *   slices[p][t / KSTEP][line][t % KSTEP],  KSTEP = 32 (int8) or 16 (BF16),
+ *   slices[p][t / KSTEP][(t % KSTEP) / HALF][line][t % HALF],
+ *   KSTEP = 32 (int8) or 16 (BF16) digits, HALF = KSTEP / 2,
  * lines padded with zero digits to lines_pad (multiple of 128, >= lines) and
  * positions t to len_pad (multiple of 64, >= line length); slice p starts at
  * element p * lines_pad * len_pad.  NaN/Inf values give digits 0 and set

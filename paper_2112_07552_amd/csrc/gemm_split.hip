@@ -24,7 +24,9 @@
 // Tiling: 4 waves in a 2 x 2 grid; a wave owns 32 x 64 outputs (int8: two
 // 32 x 32 blocks, workgroup 64 x 128) or 32 x 32 (BF16, which also holds the
 // FP64 sum; workgroup 64 x 64).  One pipeline stage is one k-step of all S
-// slices of both operands in LDS, double-buffered; each wave holds one
+// slices of both operands, moved global -> LDS by direct-to-LDS loads (no
+// register staging) into three rotating buffers, so the loads of a k-step
+// are issued two k-steps before it is multiplied.  Each wave holds one
 // accumulator per diagonal and block (S * WNB * 16 registers) and reads each
 // slice's fragment once per k-step, so the S(S+1)/2 digit products reuse
 // registers instead of LDS.
@@ -90,42 +92,72 @@ __device__ inline void tile_coords(int tiles_m, int tiles_n, int &tm, int &tn) {
     tn = in_group / gm;
 }
 
-// LDS per buffer: X [S][2 halves][BM rows][16 B], then Y [S][2][BN][16 B].
+// One pipeline stage = one k-step of all S slices of both operands:
+// X planes [S][2 halves][BM rows][16 B], then Y planes [S][2][BN rows][16 B].
+// Each (slice, half, 64-row block) plane is one 1 KB run in global memory
+// (split.hip's layout) and one wave instruction, global_load_lds_dwordx4,
+// moves it straight into LDS: lane l's 16 bytes land at plane base + 16 l.
 template <int S, int BN>
 struct Stage {
-    static constexpr int x_chunks = S * 2 * BM;
-    static constexpr int y_chunks = S * 2 * BN;
-    static constexpr int chunks = x_chunks + y_chunks;
-    static constexpr int per_thread = (chunks + THREADS - 1) / THREADS;
+    static constexpr int xi = S * 2;                // X planes (BM = 64 rows)
+    static constexpr int yi = S * 2 * (BN / 64);    // Y planes
+    static constexpr int planes = xi + yi;
+    static constexpr int per_wave = (planes + 3) / 4;
+    static constexpr int chunks = planes * 64 + 64; // + one scratch plane
+    static constexpr int x_chunks = xi * 64;
 };
 
-// Chunk c of the stage at k-step kb -> global source and LDS index.  Slices
-// are [p][kb][line][32 B], so chunk (p, line, half) of one k-step is at
-// ((p * nblk + kb) * lines_pad + line) * 32 + half * 16 bytes.
-template <int S, int BN>
-__device__ inline int chunk_dst(int c) {
-    if (c < Stage<S, BN>::x_chunks) {
-        const int p = c / (2 * BM), rem = c % (2 * BM);
-        return (p * 2 + (rem & 1)) * BM + (rem >> 1);
-    }
-    const int cc = c - Stage<S, BN>::x_chunks;
-    const int p = cc / (2 * BN), rem = cc % (2 * BN);
-    return Stage<S, BN>::x_chunks + (p * 2 + (rem & 1)) * BN + (rem >> 1);
+constexpr int NSTAGE = 3;  // LDS buffers: loads run two k-steps ahead
+
+// s_waitcnt with only the vector-memory counter constrained (gfx9 encoding:
+// vmcnt bits [3:0] and [15:14], expcnt [6:4], lgkmcnt [11:8]).
+template <int V>
+__device__ inline void wait_vmcnt() {
+    static_assert(V >= 0 && V < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((V & 15) | ((V >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
+// Workgroup barrier without the memory fence __syncthreads() implies: that
+// fence makes the compiler wait for every outstanding load, including the
+// direct-to-LDS loads of later k-steps.  Completion of this wave's LDS-bound
+// loads is waited for explicitly (wait_vmcnt), LDS reads complete before
+// their MFMAs use them, and the "memory" clobber keeps the compiler from
+// moving LDS accesses across the barrier.
+__device__ inline void barrier_no_fence() { asm volatile("s_barrier" ::: "memory"); }
+
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) const void global_cvoid;
+
+// Issue this wave's share of the loads of k-step kb into LDS buffer `buf`.
+// Plane q (wave-uniform) goes to wave q % 4; waves with fewer real planes
+// load a valid dummy run into the scratch plane, so every wave issues exactly
+// per_wave instructions and its vmcnt bookkeeping is a constant.
 template <int S, int BN>
-__device__ inline const char *chunk_src(int c, int kb, int nblk, const char *xs,
-                                        int x_lines_pad, int m0, const char *ys,
-                                        int y_lines_pad, int n0) {
-    if (c < Stage<S, BN>::x_chunks) {
-        const int p = c / (2 * BM), rem = c % (2 * BM);
-        return xs + (((int64_t)p * nblk + kb) * x_lines_pad + m0 + (rem >> 1)) * 32 +
-               (rem & 1) * 16;
+__device__ inline void issue_stage(i4 *buf, int kb, int nblk, const char *xs, int x_lines_pad,
+                                   int m0, const char *ys, int y_lines_pad, int n0, int wave,
+                                   int lane) {
+    using St = Stage<S, BN>;
+#pragma unroll
+    for (int j = 0; j < St::per_wave; ++j) {
+        const int q = wave + 4 * j;
+        const char *src;
+        int dst;
+        if (q < St::xi) {
+            const int p = q >> 1, h = q & 1;
+            src = xs + ((((int64_t)p * nblk + kb) * 2 + h) * x_lines_pad + m0 + lane) * 16;
+            dst = q * 64;
+        } else if (q < St::planes) {
+            const int qq = q - St::xi;
+            const int rb = qq % (BN / 64), ph = qq / (BN / 64);
+            const int p = ph >> 1, h = ph & 1;
+            src = ys + ((((int64_t)p * nblk + kb) * 2 + h) * y_lines_pad + n0 + rb * 64 + lane) * 16;
+            dst = q * 64;
+        } else {
+            src = xs + lane * 16;
+            dst = St::planes * 64;
+        }
+        __builtin_amdgcn_global_load_lds((global_cvoid *)src, (lds_void *)(buf + dst), 16, 0, 0);
     }
-    const int cc = c - Stage<S, BN>::x_chunks;
-    const int p = cc / (2 * BN), rem = cc % (2 * BN);
-    return ys + (((int64_t)p * nblk + kb) * y_lines_pad + n0 + (rem >> 1)) * 32 +
-           (rem & 1) * 16;
 }
 
 // k-steps [kb0, kb1) of the product; accumulate != 0 adds to C.
@@ -140,7 +172,7 @@ gemm_split_kernel(int m, int n, int nblk, int kb0, int kb1, int flush, int accum
     constexpr int WNB = M::kWNB;
     constexpr int BN = 64 * WNB;
     using St = Stage<S, BN>;
-    __shared__ __attribute__((aligned(16))) i4 lds[2][St::chunks];
+    __shared__ __attribute__((aligned(16))) i4 lds[NSTAGE][St::chunks];
 
     const int tiles_m = (m + BM - 1) / BM, tiles_n = (n + BN - 1) / BN;
     int tm, tn;
@@ -163,31 +195,25 @@ gemm_split_kernel(int m, int n, int nblk, int kb0, int kb1, int flush, int accum
             for (int i = 0; i < 16; ++i) sum[b][i] = 0.0;
     }
 
-    i4 pre[St::per_thread];
-    auto load_stage = [&](int kb) {
+    // prologue: k-steps kb0 and kb0 + 1 in flight
 #pragma unroll
-        for (int i = 0; i < St::per_thread; ++i) {
-            const int c = threadIdx.x + THREADS * i;
-            if (c < St::chunks)
-                pre[i] = *reinterpret_cast<const i4 *>(
-                    chunk_src<S, BN>(c, kb, nblk, xs, x_lines_pad, m0, ys, y_lines_pad, n0));
-        }
-    };
-    auto store_stage = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < St::per_thread; ++i) {
-            const int c = threadIdx.x + THREADS * i;
-            if (c < St::chunks) lds[buf][chunk_dst<S, BN>(c)] = pre[i];
-        }
-    };
+    for (int st = 0; st < NSTAGE - 1; ++st)
+        if (kb0 + st < kb1)
+            issue_stage<S, BN>(lds[st], kb0 + st, nblk, xs, x_lines_pad, m0, ys, y_lines_pad,
+                               n0, wave, lane);
 
-    load_stage(kb0);
-    store_stage(0);
-    __syncthreads();
     for (int kb = kb0; kb < kb1; ++kb) {
-        const int cur = (kb - kb0) & 1;
-        const bool more = kb + 1 < kb1;
-        if (more) load_stage(kb + 1);
+        const int it = kb - kb0;
+        // this wave's loads of k-step kb are done once at most the later
+        // k-step already issued is outstanding; the barrier then publishes
+        // every wave's loads and retires all reads of the buffer reused below
+        if (kb + 1 < kb1) wait_vmcnt<St::per_wave>();
+        else wait_vmcnt<0>();
+        barrier_no_fence();
+        if (kb + NSTAGE - 1 < kb1)
+            issue_stage<S, BN>(lds[(it + NSTAGE - 1) % NSTAGE], kb + NSTAGE - 1, nblk, xs,
+                               x_lines_pad, m0, ys, y_lines_pad, n0, wave, lane);
+        const int cur = it % NSTAGE;
         i4 fx[S], fy[S][WNB];
 #pragma unroll
         for (int p = 0; p < S; ++p) {
@@ -205,7 +231,7 @@ gemm_split_kernel(int m, int n, int nblk, int kb0, int kb1, int flush, int accum
                 for (int b = 0; b < WNB; ++b)
                     acc[p + q][b] = M::step(fx[p], fy[q][b], acc[p + q][b]);
         if constexpr (M::kSum) {
-            if ((kb - kb0 + 1) % flush == 0 || !more) {
+            if ((it + 1) % flush == 0 || kb + 1 == kb1) {
 #pragma unroll
                 for (int d = 0; d < S; ++d)
 #pragma unroll
@@ -217,8 +243,6 @@ gemm_split_kernel(int m, int n, int nblk, int kb0, int kb1, int flush, int accum
                     }
             }
         }
-        if (more) store_stage(cur ^ 1);
-        __syncthreads();
     }
 
     // epilogue: C (+)= 2^(e_g + f_h) * sum_t 2^(-7t) S_t

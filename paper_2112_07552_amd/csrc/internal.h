@@ -42,7 +42,8 @@ hipError_t launch_line_max(const double *Z, int rows, int cols, int64_t ld, int 
                            unsigned long long *maxbits, StatusBlock *st, hipStream_t s);
 // Lines are rows (axis 0, lines_pad >= rows, len_pad >= cols) or columns
 // (axis 1, lines_pad >= cols, len_pad >= rows); lines_pad % 128 == 0,
-// len_pad % 64 == 0.  Layout: slices[p][t / KSTEP][line][t % KSTEP].
+// len_pad % 64 == 0.  Layout: slices[p][t / KSTEP][(t % KSTEP) / HALF][line][t % HALF]
+// with KSTEP = 32 / sizeof(digit), HALF = KSTEP / 2.
 hipError_t launch_split(const double *Z, int rows, int cols, int64_t ld, int axis,
                         const unsigned long long *maxbits, int S, int digit_bf16, void *out,
                         int lines_pad, int len_pad, int *exps, hipStream_t s);

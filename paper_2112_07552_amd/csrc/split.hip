@@ -16,12 +16,15 @@
 // most 7 significant bits, exact in BF16).
 //
 // Output layout, blocked for the split GEMM's loads: the position t along a
-// line is cut into blocks of 32 bytes of digits (KSTEP = 32 int8 or 16 BF16
-// digits, one matrix-core k-step), and
-//   slices[p][t / KSTEP][line][t % KSTEP]
-// so one k-step of 64 or 128 consecutive lines is one contiguous run.  Lines
-// are padded with zero digits to `lines_pad` (a multiple of 128) and t to
-// `len_pad` (a multiple of 64); slice p starts at p * lines_pad * len_pad.
+// line is cut into k-steps of 32 bytes of digits (KSTEP = 32 int8 or 16 BF16
+// digits, one matrix-core k-step), each k-step into two 16-byte halves
+// (HALF = KSTEP / 2 digits, the slice of k one lane feeds the matrix core),
+// and
+//   slices[p][t / KSTEP][(t % KSTEP) / HALF][line][t % HALF]
+// so the 16-byte halves of 64 consecutive lines are one contiguous 1 KB run,
+// which one wave loads straight into LDS.  Lines are padded with zero digits
+// to `lines_pad` (a multiple of 128) and t to `len_pad` (a multiple of 64);
+// slice p starts at p * lines_pad * len_pad.
 // Lines are rows of the input (no transpose) or its columns (transposed
 // through LDS).
 //
@@ -65,7 +68,7 @@ row_max_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
 // Max |z| per column: threads own columns, blocks own chunks of rows, and the
 // partial maxima meet in an atomic max on the (monotone) bit patterns of the
 // non-negative doubles.  maxbits must be zero beforehand.
-constexpr int kColChunk = 256;
+constexpr int kColChunk = 64;
 
 __global__ void __launch_bounds__(kThreads)
 col_max_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
@@ -122,8 +125,9 @@ __device__ inline void store8(uint16_t *dst, const uint16_t (&d)[8]) {
 
 template <typename T>
 __device__ inline int64_t slice_offset(int line, int t, int lines_pad) {
-    constexpr int kstep = 32 / (int)sizeof(T);
-    return ((int64_t)(t / kstep) * lines_pad + line) * kstep + (t % kstep);
+    constexpr int kstep = 32 / (int)sizeof(T), half = kstep / 2;
+    const int kb = t / kstep, h = (t % kstep) / half;
+    return (((int64_t)kb * 2 + h) * lines_pad + line) * half + (t % half);
 }
 
 // Lines are rows: each thread handles 8 consecutive elements of one row and
@@ -192,19 +196,19 @@ split_cols_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
         }
     }
     __syncthreads();
-    // write: thread -> (column, 16 consecutive rows) of each slice; the 16
-    // rows lie inside one k-step block (KSTEP is 16 or 32)
+    // write: thread -> (column, 16 consecutive rows) of each slice, as two
+    // groups of 8 rows (each group lies inside one 16-byte half)
     const int wc = threadIdx.x >> 2, wr = (threadIdx.x & 3) * 16;
     const int ocol = c0 + wc;
     const int64_t slice_stride = (int64_t)lines_pad * len_pad;
 #pragma unroll
     for (int p = 0; p < S; ++p) {
-        T *dst = out + (int64_t)p * slice_stride + slice_offset<T>(ocol, r0 + wr, lines_pad);
+        T *base = out + (int64_t)p * slice_stride;
         T v0[8], v1[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) { v0[j] = tile[p][wc][wr + j]; v1[j] = tile[p][wc][wr + 8 + j]; }
-        store8(dst, v0);
-        store8(dst + 8, v1);
+        store8(base + slice_offset<T>(ocol, r0 + wr, lines_pad), v0);
+        store8(base + slice_offset<T>(ocol, r0 + wr + 8, lines_pad), v1);
     }
 }
 

@@ -114,11 +114,12 @@ def split(Z: torch.Tensor, axis: int, precision: str, S: int, ws: Optional[torch
 
 def unblock_slices(slices: torch.Tensor, lines: int, length: int, lines_pad: int, len_pad: int,
                    precision: str) -> torch.Tensor:
-    """Reorder the blocked layout [S][t / KSTEP][line][t % KSTEP] to
-    [S][line][t] (index bookkeeping only)."""
+    """Reorder the blocked layout [S][t / KSTEP][(t % KSTEP) / HALF][line][t % HALF]
+    to [S][line][t] (index bookkeeping only)."""
     kstep = 32 if precision == "split_i8" else 16
+    half = kstep // 2
     S = slices.shape[0]
-    v = slices.reshape(S, len_pad // kstep, lines_pad, kstep).permute(0, 2, 1, 3)
+    v = slices.reshape(S, len_pad // kstep, 2, lines_pad, half).permute(0, 3, 1, 2, 4)
     return v.reshape(S, lines_pad, len_pad)[:, :lines, :length]
 
 
