@@ -254,40 +254,60 @@ int orc_join_agg_cells(int64_t nA, const int32_t *ag, const int32_t *ak, const d
 
 /*
  * Right-hand side of Freivalds' check: out[g] = sum_h C[g,h] r[h], evaluated
- * from the records in O(nA + nB) by regrouping the defining double sum:
+ * from the records in O(nA + nB) by regrouping the defining double sum
+ * (distributivity):
  *   t[k]   = sum_{b: b.key == k} b.val * r[b.group]
  *   out[g] = sum_{a: a.group == g} a.val * t[a.key]
  * (R. Freivalds, "Probabilistic machines can use less running time", IFIP 1977.)
+ * Both sums stream over the records: a fixed number of record chunks keep
+ * Dot2 partial sums per key (per group), which are then combined in chunk
+ * order with TwoSum, so the result does not depend on the thread count and
+ * no relation-sized buffer is allocated.
  */
+#define ORC_CHUNKS 64
+
+static int stream_dot2(int64_t n, const int32_t *idx, int32_t nidx, const int32_t *other,
+                       int32_t nother, const double *val, const double *factor_by_other,
+                       const int32_t *factor_index, double *out) {
+    /* out[idx[i]] = sum_i val[i] * factor_by_other[factor_index[i]] over valid i */
+    acc2 *part = (acc2 *)calloc((size_t)ORC_CHUNKS * (size_t)nidx, sizeof(acc2));
+    if (!part) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int c = 0; c < ORC_CHUNKS; ++c) {
+        const int64_t i0 = n * c / ORC_CHUNKS, i1 = n * (c + 1) / ORC_CHUNKS;
+        acc2 *pc = part + (size_t)c * nidx;
+        for (int64_t i = i0; i < i1; ++i) {
+            if (!in_range(idx[i], nidx) || !in_range(other[i], nother)) continue;
+            acc2_add(&pc[idx[i]], value_of(val, i), factor_by_other[factor_index[i]]);
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (int32_t j = 0; j < nidx; ++j) {
+        acc2 tot = {0.0, 0.0};
+        for (int c = 0; c < ORC_CHUNKS; ++c) {
+            const acc2 pc = part[(size_t)c * nidx + j];
+            double s, e;
+            two_sum(tot.hi, pc.hi, &s, &e);
+            tot.hi = s;
+            tot.lo += e + pc.lo;
+        }
+        out[j] = acc2_value(tot);
+    }
+    free(part);
+    return 0;
+}
+
 int orc_freivalds(int64_t nA, const int32_t *ag, const int32_t *ak, const double *av,
                   int64_t nB, const int32_t *bk, const int32_t *bh, const double *bw,
                   int32_t M, int32_t K, int32_t N, const double *r, double *out, int nthreads) {
     int used = set_threads(nthreads);
-    int64_t *boff, *border, *aoff, *aorder;
-    if (bucket_records(nB, bk, K, bh, N, 0, &boff, &border)) return -1;
-    if (bucket_records(nA, ag, M, ak, K, 0, &aoff, &aorder)) { free(boff); free(border); return -1; }
     double *t = (double *)malloc((size_t)K * sizeof(double));
-    if (!t) { free(boff); free(border); free(aoff); free(aorder); return -1; }
-#pragma omp parallel for schedule(dynamic, 64)
-    for (int32_t k = 0; k < K; ++k) {
-        acc2 acc = {0.0, 0.0};
-        for (int64_t u = boff[k]; u < boff[k + 1]; ++u) {
-            int64_t j = border[u];
-            acc2_add(&acc, value_of(bw, j), r[bh[j]]);
-        }
-        t[k] = acc2_value(acc);
-    }
-#pragma omp parallel for schedule(dynamic, 64)
-    for (int32_t g = 0; g < M; ++g) {
-        acc2 acc = {0.0, 0.0};
-        for (int64_t u = aoff[g]; u < aoff[g + 1]; ++u) {
-            int64_t i = aorder[u];
-            acc2_add(&acc, value_of(av, i), t[ak[i]]);
-        }
-        out[g] = acc2_value(acc);
-    }
-    free(t); free(boff); free(border); free(aoff); free(aorder);
-    return used;
+    if (!t) return -1;
+    /* t[k] over B: index = key, factor r[group]; out[g] over A: index = group, factor t[key] */
+    int bad = stream_dot2(nB, bk, K, bh, N, bw, r, bh, t);
+    if (!bad) bad = stream_dot2(nA, ag, M, ak, K, av, t, ak, out);
+    free(t);
+    return bad ? -1 : used;
 }
 
 /* ------------------------------------------------------------ gradient --- */
