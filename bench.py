@@ -182,6 +182,88 @@ def bench_mixed(N, args, stream, log):
     return out
 
 
+def bench_large(stream, log, N=32768):
+    """2^30 records per table (N = 32768, the paper's largest MM query), FP32
+    values N(0,1) with 5% x1e3 outliers (seed 4).  One forward and one
+    forward + adjoint with checkpointing (the adjoint re-encodes) in the mixed
+    int8 form at tol = 1e-12 and in the FP64 form, each timed once after one
+    untimed run; errors on a 64 x 64 block of C against the oracle."""
+    import numpy as np
+    import torch
+    from oracle import oracle as orc
+    from paper_2112_07552_amd import _lib, ops
+    from paper_2112_07552_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    log(f"large: generating 2 x {N * N} records")
+    A, B = wl.mm_query(N, N, N, seed=4, values="mixture", dtype=torch.float32, device=dev)
+    W = wl.draw_values("uniform", N * N, 1004, 0, device=dev).reshape(N, N)
+    relA = ops.make_relation(A.group, A.key, A.val, unique=True)
+    relB = ops.make_relation(B.group, B.key, B.val, unique=True)
+    L = _lib.load()
+    sp = C.c_void_p(stream.cuda_stream)
+    Cm = torch.empty((N, N), dtype=torch.float64, device=dev)
+    dA = torch.empty(N * N, dtype=torch.float64, device=dev)
+    dB = torch.empty(N * N, dtype=torch.float64, device=dev)
+    out = {"workload": f"MM query, dense {N}x{N} tables ({N * N} records each), FP32 values "
+                       f"N(0,1) with 5% x1e3 outliers, seed 4; adjoint with checkpointing "
+                       f"(re-encoding)", "records_per_table": N * N}
+    rng = np.random.default_rng(4)
+    rows = np.sort(rng.choice(N, 64, replace=False))
+    cols = np.sort(rng.choice(N, 64, replace=False))
+    ag, ak = A.group.cpu().numpy(), A.key.cpu().numpy()
+    av = A.val.cpu().numpy().astype(np.float64)
+    bk, bh = B.key.cpu().numpy(), B.group.cpu().numpy()
+    bw = B.val.cpu().numpy().astype(np.float64)
+    lut_a = np.full(N, -1); lut_a[rows] = np.arange(64)
+    lut_b = np.full(N, -1); lut_b[cols] = np.arange(64)
+    ga, hb = lut_a[ag], lut_b[bh]
+    ma, mb = ga >= 0, hb >= 0
+    Af = orc.Rel(ga[ma].astype(np.int32), ak[ma], av[ma])
+    Bf = orc.Rel(hb[mb].astype(np.int32), bk[mb], bw[mb])
+    Co, _, _ = orc.join_agg(Af, Bf, 64, N, 64)
+    So, _, _ = orc.join_agg(orc.Rel(Af.group, Af.key, np.abs(Af.val)),
+                            orc.Rel(Bf.group, Bf.key, np.abs(Bf.val)), 64, N, 64)
+    del ag, ak, av, bk, bh, bw, ga, hb
+    tr, tc = torch.as_tensor(rows, device=dev), torch.as_tensor(cols, device=dev)
+    for precision in ("fp64", "split_i8"):
+        prec = ops.PRECISIONS[precision]
+        ws = ops.alloc_workspace(ops.workspace_bytes(relA, relB, N, N, N, precision,
+                                                     backward=True), dev)
+
+        def fwd():
+            _lib.check(L.tcu_join_agg_fwd(C.byref(relA), C.byref(relB), N, N, N, prec, 1e-12,
+                                          C.c_void_p(Cm.data_ptr()), None,
+                                          C.c_void_p(ws.data_ptr()), ws.numel(), sp), "fwd")
+
+        def step():
+            fwd()
+            _lib.check(L.tcu_join_agg_bwd(C.byref(relA), C.byref(relB), N, N, N, prec, 1e-12,
+                                          C.c_void_p(W.data_ptr()), C.c_void_p(dA.data_ptr()),
+                                          C.c_void_p(dB.data_ptr()), 0,
+                                          C.c_void_p(ws.data_ptr()), ws.numel(), sp), "bwd")
+
+        t_fwd = time_loop(fwd, 1, 1, stream)
+        t_step = time_loop(step, 1, 1, stream)
+        fwd()
+        st, info = ops.sync_status(ws)
+        if st != 0:
+            raise RuntimeError(f"large {precision}: status {st}")
+        blk = Cm[tr][:, tc].cpu().numpy()
+        err = float(np.max(np.abs(blk - Co) / So))
+        log(f"large {precision}: fwd {t_fwd:.1f} ms, fwd+adj {t_step:.1f} ms, err {err:.2e}")
+        out[precision] = {"ms_fwd": t_fwd, "ms_fwd_adjoint_checkpointed": t_step,
+                          "err_cw_block": err, "slices": info["slices"],
+                          "fwd_elements_per_s": N * N / (t_fwd * 1e-3),
+                          "fwd_adjoint_elements_per_s": N * N / (t_step * 1e-3)}
+        del ws
+        torch.cuda.empty_cache()
+    out["speedup_fwd"] = out["fp64"]["ms_fwd"] / out["split_i8"]["ms_fwd"]
+    out["speedup_fwd_adjoint"] = (out["fp64"]["ms_fwd_adjoint_checkpointed"] /
+                                  out["split_i8"]["ms_fwd_adjoint_checkpointed"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,6 +273,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle error check")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
+    ap.add_argument("--large", action="store_true",
+                    help="also time the largest workload: 2^30 records per table, FP32 "
+                         "mixture values, mixed int8 form vs FP64 form, forward + adjoint "
+                         "with checkpointing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 512 MiB device copy, the reference that scales "
                          "profiler byte counters")
@@ -300,6 +386,9 @@ def main():
     mixed = None
     if not args.no_mixed:
         mixed = bench_mixed(N, args, stream, log)
+    large = None
+    if args.large:
+        large = bench_large(stream, log)
 
     cpu = None
     if not args.no_cpu:
@@ -335,6 +424,7 @@ def main():
                      "kernel_ms": gemm_ms},
         "cpu_baseline": cpu,
         "mixed": mixed,
+        "large": large,
     }
     print(json.dumps(out), flush=True)
 

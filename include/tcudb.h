@@ -192,6 +192,37 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
                             double *dA_val, double *dB_val, int flags, void *ws,
                             size_t ws_bytes, hipStream_t stream);
 
+/* Dictionary encoding for the encodings of Section 3.1: dom(ID) is the union
+ * of two columns' values, with k distinct values v_1 < ... < v_k (sorted,
+ * signed 64-bit).  codes_a[i] = the rank of a[i] in that list (0-based), and
+ * likewise codes_b; dict (capacity n_a + n_b) receives v_1..v_k and *k (a
+ * host pointer) receives k.  Codes are independent of record order.  The
+ * call SYNCHRONISES the stream once (to size the sort of the distinct
+ * values).  n_a + n_b must not exceed 2^31 - 1.  ws: at least
+ * tcu_dict_workspace_bytes(n_a + n_b) bytes, 256-byte aligned (about 24
+ * bytes per value); errors are returned, not recorded in ws. */
+size_t tcu_dict_workspace_bytes(int64_t n);
+tcu_status tcu_dict_encode(const int64_t *a, int64_t n_a, const int64_t *b, int64_t n_b,
+                           int32_t *codes_a, int32_t *codes_b, int64_t *dict, int64_t *k,
+                           void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Queries Q3 and Q4 of Section 3.3 in re-associated form: A forms a single
+ * group (Lemma Q3's 1^{1 x n} factor: A's group column is ignored), so
+ *   c[h] = sum over joined pairs (a, b) with b.group == h of a.val * b.val
+ *        = sum_{b: b.group == h} hA[b.key] * b.val,  hA[k] = sum_{a: a.key == k} a.val,
+ * computed from the records in two streaming passes without forming X or Y.
+ * count (N entries, or NULL) receives the exact number of joined pairs per
+ * group, so SUM / COUNT is the AVG of Section 3.3.  N = 1 with every B record
+ * in group 0 is Q4.  c is FP64 (N entries).  Records with a key outside
+ * [0,K) (or a B group outside [0,N)) are skipped and counted in the status
+ * block at the start of ws (tcu_sync_status).  Floating-point sums use
+ * atomics (order-dependent last bits); counts are exact.  ws: at least
+ * tcu_join_agg_row_workspace_bytes(K, N) bytes, 256-byte aligned. */
+size_t tcu_join_agg_row_workspace_bytes(int32_t K, int32_t N);
+tcu_status tcu_join_agg_row(const tcu_relation *A, const tcu_relation *B, int32_t K, int32_t N,
+                            double *c, uint64_t *count, void *ws, size_t ws_bytes,
+                            hipStream_t stream);
+
 /* SYNCHRONISES the stream, then reads the workspace status block written by
  * the last call that used `ws`.  Returns TCU_ERR_KEY_RANGE if records were
  * skipped, TCU_ERR_NONFINITE if the mixed form met NaN/Inf, else TCU_OK.

@@ -413,3 +413,41 @@ int64_t orc_split(int32_t R, int32_t L, const double *X, int axis, int nslices, 
     }
     return bad;
 }
+
+/* ---------------------------------------------------------- dictionary --- */
+
+static int cmp_i64(const void *x, const void *y) {
+    const int64_t a = *(const int64_t *)x, b = *(const int64_t *)y;
+    return (a > b) - (a < b);
+}
+
+static int32_t rank_of(const int64_t *dict, int64_t k, int64_t v) {
+    int64_t lo = 0, hi = k;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (dict[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return (int32_t)lo;
+}
+
+/*
+ * dom(ID) of Section 3.1: the union of two columns' values, sorted, with
+ * duplicates removed (dict[0..k)); every value's code is its 0-based rank.
+ * Returns k, or -1 on allocation failure.
+ */
+int64_t orc_dict(int64_t na, const int64_t *a, int64_t nb, const int64_t *b, int32_t *ca,
+                 int32_t *cb, int64_t *dict) {
+    int64_t n = na + nb;
+    int64_t *all = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!all) return -1;
+    memcpy(all, a, (size_t)na * sizeof(int64_t));
+    memcpy(all + na, b, (size_t)nb * sizeof(int64_t));
+    qsort(all, (size_t)n, sizeof(int64_t), cmp_i64);
+    int64_t k = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (k == 0 || all[i] != dict[k - 1]) dict[k++] = all[i];
+    free(all);
+    for (int64_t i = 0; i < na; ++i) ca[i] = rank_of(dict, k, a[i]);
+    for (int64_t i = 0; i < nb; ++i) cb[i] = rank_of(dict, k, b[i]);
+    return k;
+}

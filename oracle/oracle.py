@@ -66,6 +66,8 @@ def lib():
         L.orc_split.argtypes = [C.c_int32, C.c_int32, _f64p, C.c_int, C.c_int, C.c_int,
                                 _i32p, _f64p]
         L.orc_split.restype = C.c_int64
+        L.orc_dict.argtypes = [C.c_int64, _i64p, C.c_int64, _i64p, _i32p, _i32p, _i64p]
+        L.orc_dict.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -199,3 +201,18 @@ def split(X, axis: int, nslices: int, bits: int = 8):
     if bad:
         raise FloatingPointError(f"oracle.split: non-finite value in line {bad - 1}")
     return exps, sl
+
+
+def dictionary(a, b):
+    """dom(ID) of Section 3.1 for two int64 columns: (dict sorted distinct
+    values, codes of a, codes of b), codes = ranks in dict."""
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    b = np.ascontiguousarray(b, dtype=np.int64)
+    ca = np.empty(a.shape[0], dtype=np.int32)
+    cb = np.empty(b.shape[0], dtype=np.int32)
+    d = np.empty(max(1, a.shape[0] + b.shape[0]), dtype=np.int64)
+    k = lib().orc_dict(a.shape[0], _p(a, _i64p), b.shape[0], _p(b, _i64p), _p(ca, _i32p),
+                       _p(cb, _i32p), _p(d, _i64p))
+    if k < 0:
+        raise MemoryError("oracle: allocation failed")
+    return d[:k].copy(), ca, cb

@@ -295,6 +295,40 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
     return TCU_OK;
 }
 
+size_t tcu_dict_workspace_bytes(int64_t n) {
+    if (n < 0 || n > 0x7fffffffLL) return 0;
+    return dict_workspace_bytes(n);
+}
+
+tcu_status tcu_dict_encode(const int64_t *a, int64_t n_a, const int64_t *b, int64_t n_b,
+                           int32_t *codes_a, int32_t *codes_b, int64_t *dict, int64_t *k,
+                           void *ws, size_t ws_bytes, hipStream_t stream) {
+    if (n_a < 0 || n_b < 0 || n_a + n_b > 0x7fffffffLL || k == nullptr) return TCU_ERR_ARG;
+    if ((n_a > 0 && (a == nullptr || codes_a == nullptr)) ||
+        (n_b > 0 && (b == nullptr || codes_b == nullptr)) || (n_a + n_b > 0 && dict == nullptr))
+        return TCU_ERR_ARG;
+    if (!ws_ok(ws, ws_bytes, dict_workspace_bytes(n_a + n_b))) return TCU_ERR_WORKSPACE;
+    return hip_status(run_dict_encode(reinterpret_cast<const long long *>(a), n_a,
+                                      reinterpret_cast<const long long *>(b), n_b, codes_a,
+                                      codes_b, reinterpret_cast<long long *>(dict), k, ws,
+                                      stream));
+}
+
+size_t tcu_join_agg_row_workspace_bytes(int32_t K, int32_t N) {
+    if (K < 1 || N < 1) return 0;
+    return row_workspace_bytes(K, N);
+}
+
+tcu_status tcu_join_agg_row(const tcu_relation *A, const tcu_relation *B, int32_t K, int32_t N,
+                            double *c, uint64_t *count, void *ws, size_t ws_bytes,
+                            hipStream_t stream) {
+    if (!relation_ok(A) || !relation_ok(B) || K < 1 || N < 1 || c == nullptr) return TCU_ERR_ARG;
+    if (!ws_ok(ws, ws_bytes, row_workspace_bytes(K, N))) return TCU_ERR_WORKSPACE;
+    return hip_status(run_join_agg_row(*A, *B, K, N, c,
+                                       reinterpret_cast<unsigned long long *>(count), ws,
+                                       stream));
+}
+
 tcu_status tcu_sync_status(void *ws, hipStream_t stream, tcu_status_info *info) {
     if (ws == nullptr || ((uintptr_t)ws % kAlign) != 0) return TCU_ERR_WORKSPACE;
     StatusBlock host;

@@ -63,4 +63,16 @@ hipError_t launch_gemm_f64(int trans_a, int trans_b, int m, int n, int k, const 
                            int64_t lda, const double *B, int64_t ldb, double *C, int64_t ldc,
                            hipStream_t s);
 
+// dict.hip: dictionary encoding (ranks in the sorted union of two columns).
+size_t dict_workspace_bytes(int64_t n);
+hipError_t run_dict_encode(const long long *a, int64_t n_a, const long long *b, int64_t n_b,
+                           int *codes_a, int *codes_b, long long *dict, int64_t *k_out,
+                           void *ws, hipStream_t s);
+
+// reassoc.hip: Q3/Q4 in re-associated form (histogram of A by key, then one
+// pass over B grouped by B's group column).
+size_t row_workspace_bytes(int K, int N);
+hipError_t run_join_agg_row(const tcu_relation &A, const tcu_relation &B, int K, int N,
+                            double *c, unsigned long long *count, void *ws, hipStream_t s);
+
 }  // namespace tcu

@@ -226,6 +226,40 @@ def _checkpoint_needed(M: int, K: int, N: int, device) -> bool:
     return enc > free // 2
 
 
+def dict_encode(a: torch.Tensor, b: torch.Tensor):
+    """dom(ID) of Section 3.1 for two int64 columns on the GPU: returns
+    (dict: sorted distinct values, codes_a int32, codes_b int32)."""
+    _need_cuda(a, "a", (torch.int64,))
+    _need_cuda(b, "b", (torch.int64,))
+    dev = a.device
+    n = a.numel() + b.numel()
+    ws = alloc_workspace(int(_lib.load().tcu_dict_workspace_bytes(n)), dev)
+    ca = torch.empty(a.numel(), dtype=torch.int32, device=dev)
+    cb = torch.empty(b.numel(), dtype=torch.int32, device=dev)
+    d = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+    k = C.c_int64(0)
+    check(_lib.load().tcu_dict_encode(_ptr(a) if a.numel() else None, a.numel(),
+                                      _ptr(b) if b.numel() else None, b.numel(),
+                                      _ptr(ca) if a.numel() else None,
+                                      _ptr(cb) if b.numel() else None, _ptr(d), C.byref(k),
+                                      _ptr(ws), ws.numel(), _stream(dev)), "tcu_dict_encode")
+    return d[:k.value], ca, cb
+
+
+def join_agg_row(a_key, a_val, b_key, b_group, b_val, K: int, N: int, with_count: bool = False):
+    """Q3 / Q4 of Section 3.3 in re-associated form (A is one group):
+    returns (c [N] FP64, count [N] int64 or None, workspace)."""
+    dev = a_key.device
+    A = make_relation(a_key, a_key, a_val)  # the group column is not read
+    B = make_relation(b_group, b_key, b_val)
+    ws = alloc_workspace(int(_lib.load().tcu_join_agg_row_workspace_bytes(K, N)), dev)
+    c = torch.empty(N, dtype=torch.float64, device=dev)
+    cnt = torch.empty(N, dtype=torch.int64, device=dev) if with_count else None
+    check(_lib.load().tcu_join_agg_row(C.byref(A), C.byref(B), K, N, _ptr(c), _ptr(cnt),
+                                       _ptr(ws), ws.numel(), _stream(dev)), "tcu_join_agg_row")
+    return c, cnt, ws
+
+
 class JoinAgg(torch.autograd.Function):
     """C = join-aggregate(A, B) with the hand-written adjoint as backward.
 

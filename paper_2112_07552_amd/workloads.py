@@ -194,3 +194,15 @@ def random_relation(n: int, groups: int, keys: int, seed: int, tag: int,
         k = torch.where(bad & (which >= 0.75), torch.full_like(k, keys + 3), k)
     val = draw_values(values, n, seed, 8000 + tag, device=device, lo=lo, hi=hi, dtype=dtype)
     return Relation(g.to(torch.int32), k.to(torch.int32), val)
+
+
+def id_column(n: int, distinct: int, seed: int, tag: int, device="cpu") -> torch.Tensor:
+    """n int64 IDs drawn uniformly from a pool of `distinct` random 64-bit
+    values.  The pool depends on the seed only, so two columns with the same
+    seed and different tags share one domain (a join attribute, Section 3.1);
+    the choice of pool member per record depends on the tag."""
+    pool = hash_counter(stream_key(seed, 0), torch.arange(max(distinct, 1), dtype=torch.int64,
+                                                          device=device))
+    u = uniform01(stream_key(seed, 100 + tag), torch.arange(n, dtype=torch.int64, device=device))
+    return pool[torch.floor(u * distinct).to(torch.int64)]
+

@@ -288,3 +288,19 @@ def test_encode_dense_is_bit_exact_placement(orc):
     ref = np.full((M, K), np.nan)
     ref[A.group.numpy(), A.key.numpy()] = A.val.numpy()
     assert np.array_equal(X, ref)
+
+
+def test_dictionary_matches_library_unique(orc):
+    """dom(ID) of Section 3.1: numpy's unique (sort + dedup) is an
+    independent route to the sorted distinct values and the ranks."""
+    rng = np.random.default_rng(7)
+    a = rng.integers(-50, 50, 300).astype(np.int64)
+    b = np.concatenate([rng.integers(-2**63, 2**63 - 1, 200, dtype=np.int64),
+                        np.array([np.iinfo(np.int64).min, np.iinfo(np.int64).max, 0, 0],
+                                 dtype=np.int64)])
+    d, ca, cb = orc.dictionary(a, b)
+    ref, inv = np.unique(np.concatenate([a, b]), return_inverse=True)
+    assert np.array_equal(d, ref)
+    assert np.array_equal(np.concatenate([ca, cb]), inv.astype(np.int32))
+    d, ca, cb = orc.dictionary(a[:0], b[:3])
+    assert np.array_equal(d, np.unique(b[:3])) and ca.shape == (0,)
