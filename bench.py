@@ -32,6 +32,30 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_gemm_f64_mm_query_4096.md")
+GEMM_SOURCE = os.path.join(ROOT, "paper_2112_07552_amd", "csrc", "gemm_f64.hip")
+
+
+def counter_traffic():
+    """HBM bytes per NN launch from the committed counter summary, or None.
+
+    The summary records FETCH_SIZE and WRITE_SIZE per dispatch, already
+    scaled by the plain-copy calibration, and the SHA-256 of the kernel
+    source they were taken with; a changed source makes the figure stale, so
+    it is not reported."""
+    import hashlib
+    import re
+    try:
+        text = open(COUNTERS_FILE).read()
+        src = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"traffic: nn_bytes=(\d+) source_sha256=([0-9a-f]{64})", text)
+    if not m or m.group(2) != src:
+        return None
+    return int(m.group(1))
+
+
 def time_loop(fn, steps, warmup, stream):
     import torch
     for _ in range(warmup):
@@ -47,7 +71,7 @@ def time_loop(fn, steps, warmup, stream):
     return start.elapsed_time(end) / steps  # ms
 
 
-def cpu_baseline(A, B, N, W, target_s=15.0):
+def cpu_baseline(A, B, N, W, target_s=20.0):
     """The FP64 oracle (as it stands) on a bounded sample of the same step:
     forward rows of C for S groups, and the adjoint for the S*N records of A
     in those groups plus S*N records of B.  Elements/s = S*N / time."""
@@ -71,9 +95,10 @@ def cpu_baseline(A, B, N, W, target_s=15.0):
 
     S = 4
     t, used = run(S)
-    S2 = int(min(N, max(S, S * target_s / max(t, 1e-3))))
-    if S2 > S:
-        S = S2
+    for _ in range(3):  # rescale until the sample takes about target_s
+        if t >= 0.6 * target_s or S >= N:
+            break
+        S = int(min(N, max(S + 1, S * target_s / max(t, 1e-3))))
         t, used = run(S)
     return {"value": S * N / t, "unit": "elements/s", "cores": int(used), "kind": "oracle",
             "sample": f"forward rows g<{S} of C plus the value gradient of the {S * N} A "
@@ -182,6 +207,124 @@ def bench_mixed(N, args, stream, log):
     return out
 
 
+def bench_queries(stream, log, steps, warmup):
+    """Q1, Q3 and Q4 of Section 3 end to end from raw int64 ID columns
+    (dictionary encoding of the join and group columns, then the operator),
+    at the microbenchmark shapes of Section 5.2: n records per table with k
+    distinct join values, (n, k) = (32768, 32) and (4096, 4096), plus
+    (2^24, 32) for the re-associated forms.  B.Val has 32 distinct values.
+    Q1 returns the n x n pair-count matrix; Q3 is timed in the
+    re-associated form and as the literal product 1^T (mat(A) mat(B)^T)."""
+    import torch
+    from paper_2112_07552_amd import ops
+    from paper_2112_07552_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    out = {}
+    for n, k in ((32768, 32), (4096, 4096), (1 << 24, 32)):
+        ida = wl.id_column(n, k, 70, 1, device=dev)
+        idb = wl.id_column(n, k, 70, 2, device=dev)
+        bval = wl.id_column(n, 32, 71, 7, device=dev)
+        av = wl.draw_values("uniform", n, 70, 3, device=dev)
+        bw = wl.draw_values("uniform", n, 70, 4, device=dev)
+        tuples = torch.arange(n, dtype=torch.int32, device=dev)
+        ones = torch.ones((1, n), dtype=torch.float64, device=dev)
+        none = ida[:0]
+        _, ka, kb = ops.dict_encode(ida, idb)
+        K = int(max(ka.max(), kb.max())) + 1
+        r = {}
+
+        def dict_only():
+            ops.dict_encode(ida, idb)
+
+        def q3():
+            _, a_k, b_k = ops.dict_encode(ida, idb)
+            _, g, _ = ops.dict_encode(bval, none)
+            ops.join_agg_row(a_k, av, b_k, g, None, K, 32, with_count=True)
+
+        def q4():
+            _, a_k, b_k = ops.dict_encode(ida, idb)
+            ops.join_agg_row(a_k, av, b_k, tuples[:0].new_zeros(n), bw, K, 1)
+
+        r["ms_dict"] = time_loop(dict_only, steps, warmup, stream)
+        r["ms_q3_reassociated"] = time_loop(q3, steps, warmup, stream)
+        r["ms_q4_reassociated"] = time_loop(q4, steps, warmup, stream)
+        if n <= 32768:
+            _, g, _ = ops.dict_encode(bval, none)
+
+            def q1():
+                _, a_k, b_k = ops.dict_encode(ida, idb)
+                ops.join_agg_fwd(tuples, a_k, None, b_k, tuples, None, n, K, n, unique=True)
+
+            def q3_literal():
+                _, a_k, b_k = ops.dict_encode(ida, idb)
+                _, gg, _ = ops.dict_encode(bval, none)
+                Cf, _, _ = ops.join_agg_fwd(tuples, a_k, av, b_k, gg, None, n, K, 32)
+                ops.gemm_f64(ones, Cf)
+
+            r["ms_q1_count_matrix"] = time_loop(q1, max(2, steps // 4), 1, stream)
+            r["ms_q3_literal"] = time_loop(q3_literal, steps, warmup, stream)
+        r["records_per_s_q3"] = 2 * n / (r["ms_q3_reassociated"] * 1e-3)
+        log(f"queries n={n} k={k}: " + ", ".join(f"{a} {b:.3g}" for a, b in r.items()))
+        out[f"n{n}_k{k}"] = r
+        del ida, idb, bval, av, bw, tuples, ones, ka, kb
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_bsr(stream, log, steps, warmup):
+    """The block-sparse form (16 x 16 tiles, empty tiles skipped) against
+    the dense form on Q1 pair counts with one record per tuple (Section 5.2,
+    many distinct join values): (n tuples, k distinct IDs) = (4096, 4096),
+    where both run, and (16384, 2^20), where the dense product would take
+    2 n^2 K flops (its time is the model 2 n^2 K / (measured dense FP64
+    rate)); plus a road-network-like graph (2^16 nodes, 2 edges per node,
+    neighbours within +-40) times a 64-column node-feature relation."""
+    import torch
+    from paper_2112_07552_amd import ops
+    from paper_2112_07552_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    out = {}
+    dense_rate = None
+    for n, k in ((4096, 4096), (16384, 1 << 20)):
+        ida = wl.id_column(n, k, 72, 1, device=dev)
+        idb = wl.id_column(n, k, 72, 2, device=dev)
+        _, ka, kb = ops.dict_encode(ida, idb)
+        K = int(max(ka.max(), kb.max())) + 1
+        t = torch.arange(n, dtype=torch.int32, device=dev)
+        r = {"K": K}
+
+        def bsr():
+            ops.join_agg_bsr(t, ka, None, kb, t, None, n, K, n, unique=True)
+
+        r["ms_bsr"] = time_loop(bsr, steps, warmup, stream)
+        flops = 2.0 * n * n * K
+        if n * n * K <= 1 << 40:
+            def dense():
+                ops.join_agg_fwd(t, ka, None, kb, t, None, n, K, n, unique=True)
+            r["ms_dense"] = time_loop(dense, max(2, steps // 4), 1, stream)
+            dense_rate = flops / (r["ms_dense"] * 1e-3)
+        elif dense_rate is not None:
+            r["ms_dense_model"] = flops / dense_rate * 1e3
+        log(f"bsr q1 n={n} k={k}: " + ", ".join(f"{a} {b:.4g}" for a, b in r.items()))
+        out[f"q1_n{n}_k{k}"] = r
+        del ida, idb, ka, kb, t
+        torch.cuda.empty_cache()
+    nodes = 1 << 16
+    E = wl.local_edges(2 * nodes, nodes, 40, 73, 1, device=dev)
+    F = wl.random_relation(4 * nodes, 64, nodes, 73, 2, device=dev)
+
+    def graph():
+        ops.join_agg_bsr(E.group, E.key, E.val, F.key, F.group, F.val, nodes, nodes, 64)
+
+    r = {"ms_bsr": time_loop(graph, steps, warmup, stream),
+         "dense_flops": 2.0 * nodes * nodes * 64}
+    log(f"bsr graph 2^16 nodes: {r['ms_bsr']:.3f} ms")
+    out["graph_65536_nodes"] = r
+    return out
+
+
 def bench_large(stream, log, N=32768):
     """2^30 records per table (N = 32768, the paper's largest MM query), FP32
     values N(0,1) with 5% x1e3 outliers (seed 4).  One forward and one
@@ -273,6 +416,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle error check")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
+    ap.add_argument("--no-queries", action="store_true",
+                    help="skip the Q1/Q3/Q4 microbenchmark leg")
     ap.add_argument("--large", action="store_true",
                     help="also time the largest workload: 2^30 records per table, FP32 "
                          "mixture values, mixed int8 form vs FP64 form, forward + adjoint "
@@ -386,6 +531,10 @@ def main():
     mixed = None
     if not args.no_mixed:
         mixed = bench_mixed(N, args, stream, log)
+    queries = None
+    if not args.no_queries:
+        queries = bench_queries(stream, log, args.steps, args.warmup)
+        queries["block_sparse"] = bench_bsr(stream, log, args.steps, args.warmup)
     large = None
     if args.large:
         large = bench_large(stream, log)
@@ -420,10 +569,12 @@ def main():
         "err_cw_vs_oracle": result_err,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_F64_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_F64_MFMA_TFLOPS,
-                     "traffic": None, "kernel": "gemm_f64_kernel<true,false> (NN, forward)",
+                     "traffic": counter_traffic(),
+                     "kernel": "gemm_f64_kernel<true,false> (NN, forward)",
                      "kernel_ms": gemm_ms},
         "cpu_baseline": cpu,
         "mixed": mixed,
+        "queries": queries,
         "large": large,
     }
     print(json.dumps(out), flush=True)

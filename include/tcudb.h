@@ -223,6 +223,52 @@ tcu_status tcu_join_agg_row(const tcu_relation *A, const tcu_relation *B, int32_
                             double *c, uint64_t *count, void *ws, size_t ws_bytes,
                             hipStream_t stream);
 
+/* ---- Block-sparse form (Section 4.2.4: TCU-SpMM) ------------------------
+ *
+ * The operator of tcu_join_agg_fwd (same relations, same C) evaluated on
+ * 16 x 16 block-sparse encodings: X and Y are cut into 16 x 16 tiles, tiles
+ * holding no record are neither stored nor multiplied, and every pair of
+ * stored tiles that meet on a key tile runs on the FP64 matrix cores.  Meant
+ * for large, sparse key domains (K much larger than the keys any group
+ * touches), where the dense product would multiply mostly zeros.
+ *
+ * C: [M*N] FP64 row-major, every cell written (exactly 0 where no pair
+ *    joins).  With A->val == NULL and B->val == NULL, C is the pair count.
+ * Cost: building the tiles makes ONE host synchronisation per relation (to
+ *    size the sort of its distinct tile keys), so the call blocks until the
+ *    stream has reached that point.
+ * Records out of range are skipped and counted (tcu_sync_status).
+ * Duplicate cells add up (FP64 atomics) unless TCU_REL_UNIQUE_CELLS is set.
+ * Workspace: tcu_join_agg_bsr_workspace_bytes(); it bounds the tile storage
+ *    by 2 KB per record (at most one new tile per record), capped by the
+ *    number of tiles of the M x K and K x N grids. */
+size_t tcu_join_agg_bsr_workspace_bytes(const tcu_relation *A, const tcu_relation *B,
+                                        int32_t M, int32_t K, int32_t N);
+tcu_status tcu_join_agg_bsr(const tcu_relation *A, const tcu_relation *B, int32_t M, int32_t K,
+                            int32_t N, double *C, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---- Matrix-to-table conversion (Section 3.2: multi-way joins) ----------
+ *
+ * nonzero(M): the cells (i, j) of a dense rows x cols FP64 matrix (leading
+ * dimension ld >= cols) with M[i,j] != 0, in row-major order, i.e. the
+ * tuple pairs that survive a join, ready to be re-encoded for the next join
+ * of a multi-way join.
+ * out_row, out_col: [capacity] int32; entries beyond *count or capacity are
+ *    not written.  If *count > capacity, only the first `capacity` pairs
+ *    are written: call again with a larger output.
+ * col_map, out_key: both NULL, or col_map [cols] int32 and out_key
+ *    [capacity] int32 with out_key[p] = col_map[out_col[p]] (the join key of
+ *    the next join, e.g. the code of B.ID2 for B tuple out_col[p]).
+ * count: host pointer; receives the number of nonzero cells.  The call
+ *    SYNCHRONISES the stream to read it.
+ * rows, cols < 2^31; M may be NULL only if rows * cols == 0.
+ * Workspace: tcu_nonzero_workspace_bytes(rows, cols), 256-byte aligned. */
+size_t tcu_nonzero_workspace_bytes(int64_t rows, int64_t cols);
+tcu_status tcu_nonzero(const double *M, int64_t rows, int64_t cols, int64_t ld, int32_t *out_row,
+                       int32_t *out_col, const int32_t *col_map, int32_t *out_key,
+                       int64_t capacity, int64_t *count, void *ws, size_t ws_bytes,
+                       hipStream_t stream);
+
 /* SYNCHRONISES the stream, then reads the workspace status block written by
  * the last call that used `ws`.  Returns TCU_ERR_KEY_RANGE if records were
  * skipped, TCU_ERR_NONFINITE if the mixed form met NaN/Inf, else TCU_OK.

@@ -216,3 +216,39 @@ def dictionary(a, b):
     if k < 0:
         raise MemoryError("oracle: allocation failed")
     return d[:k].copy(), ca, cb
+
+
+def join3(a_id1, b_id1, b_id2, c_id2):
+    """Query Q2 of Section 3.2 by its definition: every (a, b, c) with
+    A[a].ID1 = B[b].ID1 and B[b].ID2 = C[c].ID2.  Returns an int64 array of
+    shape (t, 3), rows sorted lexicographically.
+
+    For each B tuple, the matching A tuples and C tuples are found by sorting
+    A on ID1 and C on ID2 and taking equal ranges (library sort and binary
+    search as steps); the output is their product, per B tuple."""
+    a = np.ascontiguousarray(a_id1, dtype=np.int64)
+    b1 = np.ascontiguousarray(b_id1, dtype=np.int64)
+    b2 = np.ascontiguousarray(b_id2, dtype=np.int64)
+    c = np.ascontiguousarray(c_id2, dtype=np.int64)
+    oa = np.argsort(a, kind="stable")
+    oc = np.argsort(c, kind="stable")
+    sa, sc = a[oa], c[oc]
+    a_lo, a_hi = np.searchsorted(sa, b1, "left"), np.searchsorted(sa, b1, "right")
+    c_lo, c_hi = np.searchsorted(sc, b2, "left"), np.searchsorted(sc, b2, "right")
+    out = []
+    for b in range(b1.shape[0]):
+        na, nc = a_hi[b] - a_lo[b], c_hi[b] - c_lo[b]
+        if na == 0 or nc == 0:
+            continue
+        aa = oa[a_lo[b]:a_hi[b]]
+        cc = oc[c_lo[b]:c_hi[b]]
+        t = np.empty((na * nc, 3), dtype=np.int64)
+        t[:, 0] = np.repeat(aa, nc)
+        t[:, 1] = b
+        t[:, 2] = np.tile(cc, na)
+        out.append(t)
+    if not out:
+        return np.empty((0, 3), dtype=np.int64)
+    t = np.concatenate(out)
+    return t[np.lexsort((t[:, 2], t[:, 1], t[:, 0]))]
+

@@ -329,6 +329,41 @@ tcu_status tcu_join_agg_row(const tcu_relation *A, const tcu_relation *B, int32_
                                        stream));
 }
 
+size_t tcu_join_agg_bsr_workspace_bytes(const tcu_relation *A, const tcu_relation *B,
+                                        int32_t M, int32_t K, int32_t N) {
+    if (!relation_ok(A) || !relation_ok(B) || !shapes_ok(M, K, N)) return 0;
+    return bsr_workspace_bytes(A->n, B->n, M, K, N);
+}
+
+tcu_status tcu_join_agg_bsr(const tcu_relation *A, const tcu_relation *B, int32_t M, int32_t K,
+                            int32_t N, double *C, void *ws, size_t ws_bytes, hipStream_t stream) {
+    if (!relation_ok(A) || !relation_ok(B) || !shapes_ok(M, K, N) || C == nullptr)
+        return TCU_ERR_ARG;
+    if (A->n > 0x7fffffffLL || B->n > 0x7fffffffLL) return TCU_ERR_ARG;
+    if (!ws_ok(ws, ws_bytes, bsr_workspace_bytes(A->n, B->n, M, K, N))) return TCU_ERR_WORKSPACE;
+    return hip_status(run_join_agg_bsr(*A, *B, M, K, N, C, ws, stream));
+}
+
+size_t tcu_nonzero_workspace_bytes(int64_t rows, int64_t cols) {
+    if (rows < 0 || cols < 0 || rows > 0x7fffffffLL || cols > 0x7fffffffLL) return 0;
+    return nonzero_workspace_bytes(rows, cols);
+}
+
+tcu_status tcu_nonzero(const double *M, int64_t rows, int64_t cols, int64_t ld, int32_t *out_row,
+                       int32_t *out_col, const int32_t *col_map, int32_t *out_key,
+                       int64_t capacity, int64_t *count, void *ws, size_t ws_bytes,
+                       hipStream_t stream) {
+    if (rows < 0 || cols < 0 || rows > 0x7fffffffLL || cols > 0x7fffffffLL || ld < cols ||
+        capacity < 0 || count == nullptr)
+        return TCU_ERR_ARG;
+    if (rows * cols > 0 && M == nullptr) return TCU_ERR_ARG;
+    if (capacity > 0 && (out_row == nullptr || out_col == nullptr)) return TCU_ERR_ARG;
+    if ((col_map == nullptr) != (out_key == nullptr)) return TCU_ERR_ARG;
+    if (!ws_ok(ws, ws_bytes, nonzero_workspace_bytes(rows, cols))) return TCU_ERR_WORKSPACE;
+    return hip_status(run_nonzero(M, rows, cols, ld, out_row, out_col, col_map, out_key, capacity,
+                                  count, ws, stream));
+}
+
 tcu_status tcu_sync_status(void *ws, hipStream_t stream, tcu_status_info *info) {
     if (ws == nullptr || ((uintptr_t)ws % kAlign) != 0) return TCU_ERR_WORKSPACE;
     StatusBlock host;

@@ -55,24 +55,11 @@ struct Tile {
 // per-element guard, so the compiler emits straight-line dwordx4 loads that
 // stay in flight across the MFMAs of the current stage.  Edge tiles take the
 // guarded path.
-template <bool KC>
+template <bool KC, bool FULL>
 __device__ inline void load_tile(const double *__restrict__ P, int64_t ld, int o0, int k0,
                                  int oext, int kext, bool vec, double2 (&r)[4]) {
     const int tid = threadIdx.x;
-    const bool fast = vec && o0 + 128 <= oext && k0 + BK <= kext;
-    if (fast) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int c = tid + THREADS * i;
-            int o, kk;
-            if (KC) { o = c >> 3; kk = (c & 7) * 2; }
-            else    { kk = c >> 6; o = (c & 63) * 2; }
-            const int64_t base = KC ? (int64_t)(o0 + o) * ld + k0 + kk
-                                    : (int64_t)(k0 + kk) * ld + o0 + o;
-            r[i] = *reinterpret_cast<const double2 *>(P + base);
-        }
-        return;
-    }
+    const bool fast = FULL || (vec && o0 + 128 <= oext && k0 + BK <= kext);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int c = tid + THREADS * i;
@@ -82,13 +69,17 @@ __device__ inline void load_tile(const double *__restrict__ P, int64_t ld, int o
         const int go = o0 + o, gk = k0 + kk;
         // the two elements of the chunk run along the contiguous index
         const int64_t base = KC ? (int64_t)go * ld + gk : (int64_t)gk * ld + go;
-        const bool in0 = KC ? (go < oext && gk < kext) : (gk < kext && go < oext);
-        const bool in1 = KC ? (go < oext && gk + 1 < kext) : (gk < kext && go + 1 < oext);
-        if (vec && in1) {
+        if (fast) {
             r[i] = *reinterpret_cast<const double2 *>(P + base);
         } else {
-            r[i].x = in0 ? P[base] : 0.0;
-            r[i].y = in1 ? P[base + 1] : 0.0;
+            const bool in0 = go < oext && gk < kext;
+            const bool in1 = KC ? (go < oext && gk + 1 < kext) : (gk < kext && go + 1 < oext);
+            if (vec && in1) {
+                r[i] = *reinterpret_cast<const double2 *>(P + base);
+            } else {
+                r[i].x = in0 ? P[base] : 0.0;
+                r[i].y = in1 ? P[base + 1] : 0.0;
+            }
         }
     }
 }
@@ -135,7 +126,9 @@ __device__ inline void tile_coords(int tiles_m, int tiles_n, int &tm, int &tn) {
 
 // A_KC: op(A)'s contraction index is contiguous (trans_a == 0).
 // B_KC: op(B)'s contraction index is contiguous (trans_b == 1).
-template <bool A_KC, bool B_KC>
+// FULL: every tile is whole (m, n multiples of 128, k of 16) and both
+// operands allow 16-byte loads; the loads and stores then carry no guards.
+template <bool A_KC, bool B_KC, bool FULL>
 __global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
 gemm_f64_kernel(int m, int n, int k, const double *__restrict__ A, int64_t lda,
                 const double *__restrict__ B, int64_t ldb, double *__restrict__ C, int64_t ldc,
@@ -159,8 +152,8 @@ gemm_f64_kernel(int m, int n, int k, const double *__restrict__ A, int64_t lda,
 
     const int nk = (k + BK - 1) / BK;
     double2 ra[4], rb[4];
-    load_tile<A_KC>(A, lda, m0, 0, m, k, vec_a, ra);
-    load_tile<B_KC>(B, ldb, n0, 0, n, k, vec_b, rb);
+    load_tile<A_KC, FULL>(A, lda, m0, 0, m, k, vec_a, ra);
+    load_tile<B_KC, FULL>(B, ldb, n0, 0, n, k, vec_b, rb);
     store_tile<A_KC>(lds_a[0], ra);
     store_tile<B_KC>(lds_b[0], rb);
     __syncthreads();
@@ -168,10 +161,15 @@ gemm_f64_kernel(int m, int n, int k, const double *__restrict__ A, int64_t lda,
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
         const bool more = kt + 1 < nk;
-        if (more) {
-            load_tile<A_KC>(A, lda, m0, (kt + 1) * BK, m, k, vec_a, ra);
-            load_tile<B_KC>(B, ldb, n0, (kt + 1) * BK, n, k, vec_b, rb);
-        }
+        // The last stage reloads its own (in-bounds) tile and stores it to
+        // the idle buffer, which no wave reads any more: loads and stores are
+        // unconditional, so the compiler neither sinks the loads behind the
+        // MFMAs nor keeps the staging registers in scratch.  The scheduling
+        // barrier pins the loads ahead of the stage's MFMAs.
+        const int knext = (more ? kt + 1 : kt) * BK;
+        load_tile<A_KC, FULL>(A, lda, m0, knext, m, k, vec_a, ra);
+        load_tile<B_KC, FULL>(B, ldb, n0, knext, n, k, vec_b, rb);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             double fa[FM], fb[FN];
@@ -184,10 +182,8 @@ gemm_f64_kernel(int m, int n, int k, const double *__restrict__ A, int64_t lda,
                     acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0,
                                                                      0);
         }
-        if (more) {
-            store_tile<A_KC>(lds_a[cur ^ 1], ra);
-            store_tile<B_KC>(lds_b[cur ^ 1], rb);
-        }
+        store_tile<A_KC>(lds_a[cur ^ 1], ra);
+        store_tile<B_KC>(lds_b[cur ^ 1], rb);
         __syncthreads();
     }
 
@@ -201,7 +197,7 @@ gemm_f64_kernel(int m, int n, int k, const double *__restrict__ A, int64_t lda,
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int row = m0 + wm * WM + a * 16 + j + 4 * i;
-                if (row < m && col < n) C[(int64_t)row * ldc + col] = acc[a][b][i];
+                if (FULL || (row < m && col < n)) C[(int64_t)row * ldc + col] = acc[a][b][i];
             }
         }
     }
@@ -213,8 +209,13 @@ hipError_t launch(int m, int n, int k, const double *A, int64_t lda, const doubl
     const int tiles = ((m + BM - 1) / BM) * ((n + BN - 1) / BN);
     const int vec_a = (lda % 2 == 0) && (((uintptr_t)A & 15) == 0);
     const int vec_b = (ldb % 2 == 0) && (((uintptr_t)B & 15) == 0);
-    gemm_f64_kernel<A_KC, B_KC><<<tiles, THREADS, 0, s>>>(m, n, k, A, lda, B, ldb, C, ldc, vec_a,
-                                                          vec_b);
+    const bool full = vec_a && vec_b && m % BM == 0 && n % BN == 0 && k % BK == 0 && k > 0;
+    if (full)
+        gemm_f64_kernel<A_KC, B_KC, true><<<tiles, THREADS, 0, s>>>(m, n, k, A, lda, B, ldb, C,
+                                                                    ldc, vec_a, vec_b);
+    else
+        gemm_f64_kernel<A_KC, B_KC, false><<<tiles, THREADS, 0, s>>>(m, n, k, A, lda, B, ldb, C,
+                                                                     ldc, vec_a, vec_b);
     return hipGetLastError();
 }
 

@@ -42,7 +42,6 @@ typedef int i16v __attribute__((ext_vector_type(16)));
 typedef float f16v __attribute__((ext_vector_type(16)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-constexpr int THREADS = 256;
 constexpr int BM = 64;  // workgroup rows (2 waves of 32)
 constexpr int GROUP_M = 8;
 constexpr int NUM_XCD = 8;
@@ -51,7 +50,8 @@ template <typename T> struct Mfma;
 template <> struct Mfma<int8_t> {
     using acc_t = i16v;
     static constexpr long kExactLimit = 2147483647L;  // int32
-    static constexpr int kWNB = 2;                    // 32 x 32 blocks per wave along n
+    static constexpr int kWNB = 1;                    // 32 x 32 blocks per wave along n
+    static constexpr int kWavesN = 4;                 // waves along n (8 per workgroup)
     static constexpr bool kSum = false;               // one exact chunk per launch
     __device__ static inline acc_t step(i4 a, i4 b, acc_t c) {
         return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
@@ -61,6 +61,7 @@ template <> struct Mfma<uint16_t> {
     using acc_t = f16v;
     static constexpr long kExactLimit = 16777216L;  // integers exact in FP32
     static constexpr int kWNB = 1;
+    static constexpr int kWavesN = 2;
     static constexpr bool kSum = true;              // FP64 sum over short exact chunks
     __device__ static inline acc_t step(i4 a, i4 b, acc_t c) {
         return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, a),
@@ -97,17 +98,17 @@ __device__ inline void tile_coords(int tiles_m, int tiles_n, int &tm, int &tn) {
 // Each (slice, half, 64-row block) plane is one 1 KB run in global memory
 // (split.hip's layout) and one wave instruction, global_load_lds_dwordx4,
 // moves it straight into LDS: lane l's 16 bytes land at plane base + 16 l.
-template <int S, int BN>
+template <int S, int BN, int NW>
 struct Stage {
     static constexpr int xi = S * 2;                // X planes (BM = 64 rows)
     static constexpr int yi = S * 2 * (BN / 64);    // Y planes
     static constexpr int planes = xi + yi;
-    static constexpr int per_wave = (planes + 3) / 4;
+    static constexpr int per_wave = (planes + NW - 1) / NW;
     static constexpr int chunks = planes * 64 + 64; // + one scratch plane
     static constexpr int x_chunks = xi * 64;
 };
 
-constexpr int NSTAGE = 3;  // LDS buffers: loads run two k-steps ahead
+constexpr int NSTAGE = 3;  // LDS buffers: loads run two k-steps ahead of the fragment reads
 
 // s_waitcnt with only the vector-memory counter constrained (gfx9 encoding:
 // vmcnt bits [3:0] and [15:14], expcnt [6:4], lgkmcnt [11:8]).
@@ -129,17 +130,17 @@ typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(1))) const void global_cvoid;
 
 // Issue this wave's share of the loads of k-step kb into LDS buffer `buf`.
-// Plane q (wave-uniform) goes to wave q % 4; waves with fewer real planes
+// Plane q (wave-uniform) goes to wave q % NW; waves with fewer real planes
 // load a valid dummy run into the scratch plane, so every wave issues exactly
 // per_wave instructions and its vmcnt bookkeeping is a constant.
-template <int S, int BN>
+template <int S, int BN, int NW>
 __device__ inline void issue_stage(i4 *buf, int kb, int nblk, const char *xs, int x_lines_pad,
                                    int m0, const char *ys, int y_lines_pad, int n0, int wave,
                                    int lane) {
-    using St = Stage<S, BN>;
+    using St = Stage<S, BN, NW>;
 #pragma unroll
     for (int j = 0; j < St::per_wave; ++j) {
-        const int q = wave + 4 * j;
+        const int q = wave + NW * j;
         const char *src;
         int dst;
         if (q < St::xi) {
@@ -160,9 +161,36 @@ __device__ inline void issue_stage(i4 *buf, int kb, int nblk, const char *xs, in
     }
 }
 
+// Digit products of slices p in [P0, P1) with every q on the kept diagonals.
+template <typename T, int S, int WNB, int P0, int P1>
+__device__ inline void mfma_range(const i4 (&fx)[S], const i4 (&fy)[S][WNB],
+                                  typename Mfma<T>::acc_t (&acc)[S][WNB]) {
+#pragma unroll
+    for (int p = P0; p < P1; ++p)
+#pragma unroll
+        for (int q = 0; q + p < S; ++q)
+#pragma unroll
+            for (int b = 0; b < WNB; ++b) acc[p + q][b] = Mfma<T>::step(fx[p], fy[q][b], acc[p + q][b]);
+}
+
 // k-steps [kb0, kb1) of the product; accumulate != 0 adds to C.
+//
+// Software pipeline, per k-step kb (fragments of kb already in registers):
+//   1. the MFMAs of the first slices of X;
+//   2. wait for this wave's loads of k-step kb+1, barrier (every wave's
+//      loads of kb+1 have landed, and every wave has consumed its fragments
+//      of kb, so kb's LDS buffer is free);
+//   3. issue the direct-to-LDS loads of k-step kb+3 into that buffer;
+//   4. read the fragments of kb+1 from LDS while
+//   5. the MFMAs of the remaining slices of X run.
+// The LDS read latency and the barrier then overlap matrix-core work, with
+// one wave per SIMD.  Fragments alternate between two register sets (the
+// loop is unrolled by two), global loads run two k-steps ahead.
+template <typename T>
+constexpr int split_threads() { return 64 * 2 * Mfma<T>::kWavesN; }
+
 template <typename T, int S>
-__global__ void __launch_bounds__(THREADS)
+__global__ void __launch_bounds__(split_threads<T>())
 gemm_split_kernel(int m, int n, int nblk, int kb0, int kb1, int flush, int accumulate,
                   const char *__restrict__ xs, int x_lines_pad, const char *__restrict__ ys,
                   int y_lines_pad, const int *__restrict__ ex, const int *__restrict__ ey,
@@ -170,15 +198,20 @@ gemm_split_kernel(int m, int n, int nblk, int kb0, int kb1, int flush, int accum
     using M = Mfma<T>;
     using acc_t = typename M::acc_t;
     constexpr int WNB = M::kWNB;
-    constexpr int BN = 64 * WNB;
-    using St = Stage<S, BN>;
+    constexpr int NW = 2 * M::kWavesN;
+    constexpr int BN = 32 * WNB * M::kWavesN;
+    constexpr int PSPLIT = (S + 1) / 3;  // slices of X multiplied before the barrier
+    using St = Stage<S, BN, NW>;
     __shared__ __attribute__((aligned(16))) i4 lds[NSTAGE][St::chunks];
 
     const int tiles_m = (m + BM - 1) / BM, tiles_n = (n + BN - 1) / BN;
     int tm, tn;
     tile_coords(tiles_m, tiles_n, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index is uniform across the wave: in a scalar register, the
+    // plane selection of issue_stage is a scalar branch
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     const int wm = wave & 1, wn = wave >> 1;
     const int l32 = lane & 31, half = lane >> 5;
 
@@ -195,54 +228,68 @@ gemm_split_kernel(int m, int n, int nblk, int kb0, int kb1, int flush, int accum
             for (int i = 0; i < 16; ++i) sum[b][i] = 0.0;
     }
 
-    // prologue: k-steps kb0 and kb0 + 1 in flight
-#pragma unroll
-    for (int st = 0; st < NSTAGE - 1; ++st)
-        if (kb0 + st < kb1)
-            issue_stage<S, BN>(lds[st], kb0 + st, nblk, xs, x_lines_pad, m0, ys, y_lines_pad,
-                               n0, wave, lane);
-
-    for (int kb = kb0; kb < kb1; ++kb) {
-        const int it = kb - kb0;
-        // this wave's loads of k-step kb are done once at most the later
-        // k-step already issued is outstanding; the barrier then publishes
-        // every wave's loads and retires all reads of the buffer reused below
-        if (kb + 1 < kb1) wait_vmcnt<St::per_wave>();
-        else wait_vmcnt<0>();
-        barrier_no_fence();
-        if (kb + NSTAGE - 1 < kb1)
-            issue_stage<S, BN>(lds[(it + NSTAGE - 1) % NSTAGE], kb + NSTAGE - 1, nblk, xs,
-                               x_lines_pad, m0, ys, y_lines_pad, n0, wave, lane);
-        const int cur = it % NSTAGE;
-        i4 fx[S], fy[S][WNB];
+    auto read = [&](const i4 *buf, i4 (&fx)[S], i4 (&fy)[S][WNB]) {
 #pragma unroll
         for (int p = 0; p < S; ++p) {
-            fx[p] = lds[cur][(p * 2 + half) * BM + wm * 32 + l32];
+            fx[p] = buf[(p * 2 + half) * BM + wm * 32 + l32];
 #pragma unroll
             for (int b = 0; b < WNB; ++b)
-                fy[p][b] = lds[cur][St::x_chunks + (p * 2 + half) * BN + wn * 32 * WNB +
-                                    b * 32 + l32];
+                fy[p][b] = buf[St::x_chunks + (p * 2 + half) * BN + wn * 32 * WNB + b * 32 + l32];
         }
-#pragma unroll
-        for (int p = 0; p < S; ++p)
-#pragma unroll
-            for (int q = 0; q + p < S; ++q)
-#pragma unroll
-                for (int b = 0; b < WNB; ++b)
-                    acc[p + q][b] = M::step(fx[p], fy[q][b], acc[p + q][b]);
+    };
+
+    auto flush_sum = [&]() {
         if constexpr (M::kSum) {
-            if ((it + 1) % flush == 0 || kb + 1 == kb1) {
 #pragma unroll
-                for (int d = 0; d < S; ++d)
+            for (int d = 0; d < S; ++d)
 #pragma unroll
-                    for (int b = 0; b < WNB; ++b) {
+                for (int b = 0; b < WNB; ++b) {
 #pragma unroll
-                        for (int i = 0; i < 16; ++i)
-                            sum[b][i] += ldexp((double)acc[d][b][i], -7 * (d + 2));
-                        acc[d][b] = acc_t{};
-                    }
-            }
+                    for (int i = 0; i < 16; ++i)
+                        sum[b][i] += ldexp((double)acc[d][b][i], -7 * (d + 2));
+                    acc[d][b] = acc_t{};
+                }
         }
+    };
+
+    // one k-step: fc holds its fragments, fn receives those of the next
+    auto kstep = [&](int kb, i4 (&fcx)[S], i4 (&fcy)[S][WNB], i4 (&fnx)[S],
+                     i4 (&fny)[S][WNB]) {
+        const int it = kb - kb0;
+        mfma_range<T, S, WNB, 0, PSPLIT>(fcx, fcy, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        if (kb + 1 < kb1) {
+            if (kb + 2 < kb1) wait_vmcnt<St::per_wave>();
+            else wait_vmcnt<0>();
+            barrier_no_fence();
+            if (kb + 3 < kb1)
+                issue_stage<S, BN, NW>(lds[(it + 3) % NSTAGE], kb + 3, nblk, xs, x_lines_pad, m0, ys,
+                                   y_lines_pad, n0, wave, lane);
+            read(lds[(it + 1) % NSTAGE], fnx, fny);
+        }
+        mfma_range<T, S, WNB, PSPLIT, S>(fcx, fcy, acc);
+        if constexpr (M::kSum) {
+            if ((it + 1) % flush == 0 || kb + 1 == kb1) flush_sum();
+        }
+    };
+
+    // prologue: k-steps kb0 .. kb0 + 2 in flight, fragments of kb0 read
+#pragma unroll
+    for (int st = 0; st < NSTAGE; ++st)
+        if (kb0 + st < kb1)
+            issue_stage<S, BN, NW>(lds[st], kb0 + st, nblk, xs, x_lines_pad, m0, ys, y_lines_pad,
+                               n0, wave, lane);
+    const int issued = kb1 - kb0 < NSTAGE ? kb1 - kb0 : NSTAGE;
+    if (issued == 3) wait_vmcnt<2 * St::per_wave>();
+    else if (issued == 2) wait_vmcnt<St::per_wave>();
+    else wait_vmcnt<0>();
+    barrier_no_fence();
+    i4 f0x[S], f0y[S][WNB], f1x[S], f1y[S][WNB];
+    read(lds[0], f0x, f0y);
+
+    for (int kb = kb0; kb < kb1; kb += 2) {
+        kstep(kb, f0x, f0y, f1x, f1y);
+        if (kb + 1 < kb1) kstep(kb + 1, f1x, f1y, f0x, f0y);
     }
 
     // epilogue: C (+)= 2^(e_g + f_h) * sum_t 2^(-7t) S_t
@@ -274,7 +321,7 @@ template <typename T, int S>
 hipError_t launch_s(int m, int n, int nblk, const void *xs, int x_lines_pad, const void *ys,
                     int y_lines_pad, const int *ex, const int *ey, double *C, int64_t ldc,
                     hipStream_t s) {
-    constexpr int BN = 64 * Mfma<T>::kWNB;
+    constexpr int BN = 32 * Mfma<T>::kWNB * Mfma<T>::kWavesN;
     const int tiles = ((m + BM - 1) / BM) * ((n + BN - 1) / BN);
     const int flush = flush_steps<T>(S);
     // int8: one launch per exact chunk (no FP64 sum held in registers);
@@ -282,7 +329,7 @@ hipError_t launch_s(int m, int n, int nblk, const void *xs, int x_lines_pad, con
     const int chunk = Mfma<T>::kSum ? nblk : flush;
     for (int kb0 = 0; kb0 < nblk; kb0 += chunk) {
         const int kb1 = kb0 + chunk < nblk ? kb0 + chunk : nblk;
-        gemm_split_kernel<T, S><<<tiles, THREADS, 0, s>>>(
+        gemm_split_kernel<T, S><<<tiles, split_threads<T>(), 0, s>>>(
             m, n, nblk, kb0, kb1, flush, kb0 > 0, static_cast<const char *>(xs), x_lines_pad,
             static_cast<const char *>(ys), y_lines_pad, ex, ey, C, ldc);
         const hipError_t e = hipGetLastError();

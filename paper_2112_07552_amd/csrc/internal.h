@@ -75,4 +75,17 @@ size_t row_workspace_bytes(int K, int N);
 hipError_t run_join_agg_row(const tcu_relation &A, const tcu_relation &B, int K, int N,
                             double *c, unsigned long long *count, void *ws, hipStream_t s);
 
+// bsr.hip: the join-aggregate on 16 x 16 block-sparse encodings (tiles
+// without records skipped); C dense M x N FP64.
+size_t bsr_workspace_bytes(int64_t na, int64_t nb, int M, int K, int N);
+hipError_t run_join_agg_bsr(const tcu_relation &A, const tcu_relation &B, int M, int K, int N,
+                            double *C, void *ws, hipStream_t s);
+
+// compact.hip: nonzero() of a dense matrix in row-major order (three-pass
+// stream compaction); *count receives the total (host synchronisation).
+size_t nonzero_workspace_bytes(int64_t rows, int64_t cols);
+hipError_t run_nonzero(const double *M, int64_t rows, int64_t cols, int64_t ld, int32_t *out_row,
+                       int32_t *out_col, const int32_t *col_map, int32_t *out_key,
+                       int64_t capacity, int64_t *count, void *ws, hipStream_t s);
+
 }  // namespace tcu

@@ -260,6 +260,99 @@ def join_agg_row(a_key, a_val, b_key, b_group, b_val, K: int, N: int, with_count
     return c, cnt, ws
 
 
+def join_agg_bsr(a_group, a_key, a_val, b_key, b_group, b_val, M: int, K: int, N: int,
+                 unique: bool = False) -> Tuple[torch.Tensor, torch.Tensor]:
+    """The operator on 16 x 16 block-sparse encodings (Section 4.2.4):
+    returns (C [M, N] FP64, workspace).  Blocks once per relation."""
+    A = make_relation(a_group, a_key, a_val, unique)
+    B = make_relation(b_group, b_key, b_val, unique)
+    dev = a_group.device
+    ws = alloc_workspace(int(_lib.load().tcu_join_agg_bsr_workspace_bytes(
+        C.byref(A), C.byref(B), M, K, N)), dev)
+    Cm = torch.empty((M, N), dtype=torch.float64, device=dev)
+    check(_lib.load().tcu_join_agg_bsr(C.byref(A), C.byref(B), M, K, N, _ptr(Cm), _ptr(ws),
+                                       ws.numel(), _stream(dev)), "tcu_join_agg_bsr")
+    return Cm, ws
+
+
+def nonzero(M: torch.Tensor, col_map: Optional[torch.Tensor] = None,
+            capacity: Optional[int] = None):
+    """The matrix-to-table conversion of Section 3.2: (rows, cols, keys) of
+    the nonzero cells of M in row-major order, int32; keys = col_map[cols]
+    (None without a map).  Scans again with a larger output if `capacity`
+    (default: a 2^22-entry guess) was too small."""
+    if not isinstance(M, torch.Tensor) or M.device.type != "cuda" or M.dtype != torch.float64:
+        raise ValueError("M must be a float64 CUDA (HIP) tensor")
+    if M.dim() != 2 or (M.numel() and (M.stride(1) != 1 or M.stride(0) < M.shape[1])):
+        raise ValueError("M must be a 2-D row-major matrix (unit column stride)")
+    rows, cols = M.shape
+    dev = M.device
+    if col_map is not None:
+        _need_cuda(col_map, "col_map", (torch.int32,))
+        if col_map.numel() != cols:
+            raise ValueError("col_map needs one entry per column")
+    L = _lib.load()
+    ws = alloc_workspace(int(L.tcu_nonzero_workspace_bytes(rows, cols)), dev)
+    cap = min(rows * cols, 1 << 22) if capacity is None else int(capacity)
+    while True:
+        r = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        c = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        k = torch.empty(max(cap, 1), dtype=torch.int32, device=dev) if col_map is not None else None
+        count = C.c_int64(0)
+        check(L.tcu_nonzero(_ptr(M) if M.numel() else None, rows, cols, M.stride(0) if rows else cols,
+                            _ptr(r), _ptr(c), _ptr(col_map), _ptr(k), cap, C.byref(count),
+                            _ptr(ws), ws.numel(), _stream(dev)), "tcu_nonzero")
+        if count.value <= cap:
+            n = count.value
+            return r[:n], c[:n], (None if k is None else k[:n])
+        cap = count.value
+
+
+def join3(a_id1: torch.Tensor, b_id1: torch.Tensor, b_id2: torch.Tensor, c_id2: torch.Tensor):
+    """Query Q2 of Section 3.2, A(ID1) JOIN B(ID1, ID2) JOIN C(ID2), in the
+    order A -> B -> C: C1 = mat(A) mat(B)^T, its nonzeros as the table AB,
+    re-encoded by B.ID2, then C3 = mat(AB) mat(C)^T.  Returns (pair_a,
+    pair_b, C3): C3[i, j] = 1 iff (A tuple pair_a[i], B tuple pair_b[i],
+    C tuple j) is a result tuple."""
+    dev = a_id1.device
+    d1, ka, kb1 = dict_encode(a_id1, b_id1)
+    d2, kb2, kc = dict_encode(b_id2, c_id2)
+    n, m, mc = a_id1.numel(), b_id1.numel(), c_id2.numel()
+    K1, K2 = max(1, d1.numel()), max(1, d2.numel())
+    empty = torch.empty(0, dtype=torch.int32, device=dev)
+    if n == 0 or m == 0:
+        return empty, empty, torch.zeros((0, mc), dtype=torch.float64, device=dev)
+    ta = torch.arange(n, dtype=torch.int32, device=dev)
+    tb = torch.arange(m, dtype=torch.int32, device=dev)
+    C1, _, ws = join_agg_fwd(ta, ka, None, kb1, tb, None, n, K1, m, unique=True)
+    pa, pb, keys = nonzero(C1, col_map=kb2)
+    del C1
+    n2 = pa.numel()
+    if n2 == 0 or mc == 0:
+        return pa, pb, torch.zeros((n2, mc), dtype=torch.float64, device=dev)
+    t2 = torch.arange(n2, dtype=torch.int32, device=dev)
+    tc = torch.arange(mc, dtype=torch.int32, device=dev)
+    C3, _, _ = join_agg_fwd(t2, keys, None, kc, tc, None, n2, K2, mc, unique=True)
+    return pa, pb, C3
+
+
+def join3_chain(a_id1: torch.Tensor, b_id1: torch.Tensor, b_id2: torch.Tensor,
+                c_id2: torch.Tensor) -> torch.Tensor:
+    """Q2 with B projected out (Section 3.2): mat(A) mat(B)^T mat(C)^T with
+    mat(B) the ID1 x ID2 incidence of B, no table conversion in between.
+    Returns R (n_A x n_C) FP64: R[a, c] = number of B tuples joining a and c."""
+    dev = a_id1.device
+    d1, ka, kb1 = dict_encode(a_id1, b_id1)
+    d2, kb2, kc = dict_encode(b_id2, c_id2)
+    n, mc = a_id1.numel(), c_id2.numel()
+    K1, K2 = max(1, d1.numel()), max(1, d2.numel())
+    ta = torch.arange(n, dtype=torch.int32, device=dev)
+    tc = torch.arange(mc, dtype=torch.int32, device=dev)
+    X1, _, _ = join_agg_fwd(ta, ka, None, kb1, kb2, None, n, K1, K2)   # n x K2
+    Y = encode(tc, kc, None, K2, mc, transpose=True, unique=True)      # K2 x n_C
+    return gemm_f64(X1, Y)
+
+
 class JoinAgg(torch.autograd.Function):
     """C = join-aggregate(A, B) with the hand-written adjoint as backward.
 

@@ -206,3 +206,17 @@ def id_column(n: int, distinct: int, seed: int, tag: int, device="cpu") -> torch
     u = uniform01(stream_key(seed, 100 + tag), torch.arange(n, dtype=torch.int64, device=device))
     return pool[torch.floor(u * distinct).to(torch.int64)]
 
+
+def local_edges(n: int, nodes: int, width: int, seed: int, tag: int, device="cpu",
+                values: str = "uniform", dtype=torch.float64) -> Relation:
+    """n edges (src, dst) of a graph with spatial locality, as in a road
+    network: src uniform over the nodes, dst = src + d mod nodes with d
+    uniform in [-width, width].  Returned as a Relation with group = src,
+    key = dst."""
+    idx = torch.arange(n, dtype=torch.int64, device=device)
+    src = torch.floor(uniform01(stream_key(seed, 9000 + tag), idx) * nodes).to(torch.int64)
+    d = torch.floor(uniform01(stream_key(seed, 9100 + tag), idx) * (2 * width + 1)).to(torch.int64)
+    dst = torch.remainder(src + d - width, nodes)
+    val = draw_values(values, n, seed, 9200 + tag, device=device, dtype=dtype)
+    return Relation(src.to(torch.int32), dst.to(torch.int32), val)
+

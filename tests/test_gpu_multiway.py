@@ -1,0 +1,72 @@
+"""Multi-way joins (Section 3.2, query Q2) on the GPU against the oracle.
+
+nonzero() is index work and must be bit-exact (cells and order); the
+three-way join result is a set of tuple triples, compared exactly; the
+chain product (B projected out) counts the B tuples linking each (a, c)
+pair, integers exact in FP64."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2112_07552_amd import ops
+from paper_2112_07552_amd import workloads as wl
+
+from .gpu_util import cuda_or_skip
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("rows,cols,density", [(1, 1, 1.0), (7, 5000, 0.3), (4097, 300, 0.01),
+                                               (3000, 3000, 0.0), (2048, 2048, 1.0)])
+def test_nonzero_exact_and_ordered(rows, cols, density):
+    dev = cuda_or_skip()
+    u = wl.uniform01(wl.stream_key(80, rows), torch.arange(rows * cols, device=dev))
+    M = torch.where(u < density, u + 0.5, torch.zeros_like(u)).reshape(rows, cols)
+    cmap = torch.arange(cols, dtype=torch.int32, device=dev) * 3 - 1
+    r, c, k = ops.nonzero(M, col_map=cmap, capacity=17)  # forces the retry path
+    er, ec = np.nonzero(M.cpu().numpy())   # row-major order
+    assert np.array_equal(r.cpu().numpy(), er) and np.array_equal(c.cpu().numpy(), ec)
+    assert np.array_equal(k.cpu().numpy(), ec * 3 - 1)
+
+
+def test_nonzero_leading_dimension():
+    dev = cuda_or_skip()
+    big = torch.zeros((50, 80), dtype=torch.float64, device=dev)
+    big[3, 7] = 1.0
+    big[3, 60] = 2.0   # outside the 50 x 40 view
+    big[49, 39] = -1.0
+    view = big[:, :40]
+    r, c, _ = ops.nonzero(view)
+    assert r.tolist() == [3, 49] and c.tolist() == [7, 39]
+
+
+@pytest.mark.parametrize("na,nb,nc,d1,d2", [(300, 400, 350, 20, 15), (2048, 2048, 2048, 128, 128),
+                                             (1000, 50, 1000, 1000, 1000), (64, 64, 0, 4, 4)])
+def test_three_way_join_matches_oracle(orc, na, nb, nc, d1, d2):
+    dev = cuda_or_skip()
+    a = wl.id_column(na, d1, 81, 1, device=dev)
+    b1 = wl.id_column(nb, d1, 81, 2, device=dev)
+    b2 = wl.id_column(nb, d2, 82, 3, device=dev)
+    c = wl.id_column(nc, d2, 82, 4, device=dev)
+    pa, pb, C3 = ops.join3(a, b1, b2, c)
+    want = orc.join3(a.cpu().numpy(), b1.cpu().numpy(), b2.cpu().numpy(), c.cpu().numpy())
+    i, j = np.nonzero(C3.cpu().numpy())
+    vals = C3.cpu().numpy()[i, j]
+    assert np.all(vals == 1.0)
+    got = np.stack([pa.cpu().numpy()[i], pb.cpu().numpy()[i], j], axis=1).astype(np.int64)
+    got = got[np.lexsort((got[:, 2], got[:, 1], got[:, 0]))]
+    assert got.shape == want.shape and np.array_equal(got, want)
+
+
+def test_three_way_chain_product(orc):
+    dev = cuda_or_skip()
+    na, nb, nc, d1, d2 = 700, 900, 800, 40, 30
+    a = wl.id_column(na, d1, 83, 1, device=dev)
+    b1 = wl.id_column(nb, d1, 83, 2, device=dev)
+    b2 = wl.id_column(nb, d2, 84, 3, device=dev)
+    c = wl.id_column(nc, d2, 84, 4, device=dev)
+    R = ops.join3_chain(a, b1, b2, c).cpu().numpy()
+    t = orc.join3(a.cpu().numpy(), b1.cpu().numpy(), b2.cpu().numpy(), c.cpu().numpy())
+    want = np.zeros((na, nc))
+    np.add.at(want, (t[:, 0], t[:, 2]), 1.0)
+    assert np.array_equal(R, want)

@@ -143,3 +143,41 @@ def test_q4_total(orc, n, n_ids):
     So, _, _ = orc.join_agg(abs_rel(orc, RA), abs_rel(orc, RB), 1, K, 1)
     assert int(cnt.cpu()[0]) == int(co[0, 0])
     assert abs(float(c.cpu()[0]) - Co[0, 0]) <= 1e-12 * So[0, 0]
+
+
+@pytest.mark.parametrize("n_ids", [32, 4096])
+def test_q3_q4_literal_matrix_form(orc, n_ids):
+    """Lemma Q3 as written: 1^T x (mat(A) mat(B)^T), one row of mat(A) per
+    A tuple, with the ones-vector reduction as a second product on the FP64
+    matrix cores; Q4 adds the reduction on the right.  4096 records per
+    table (the microbenchmark size), 32 or 4096 distinct join values."""
+    dev = cuda_or_skip()
+    n = 4096
+    ida, idb = wl.id_column(n, n_ids, 66, 1), wl.id_column(n, n_ids, 66, 2)
+    bval = wl.id_column(n, 64, 66, 7)
+    _, ka, kb = ops.dict_encode(ida.to(dev), idb.to(dev))
+    _, gb, _ = ops.dict_encode(bval.to(dev), bval[:0].to(dev))
+    K = int(max(ka.max(), kb.max())) + 1
+    N = int(gb.max()) + 1
+    av = wl.draw_values("uniform", n, 66, 3, device=dev)
+    bw = wl.draw_values("uniform", n, 66, 4, device=dev)
+    tuples = torch.arange(n, dtype=torch.int32, device=dev)
+    ones = torch.ones((1, n), dtype=torch.float64, device=dev)
+    # Q3: rows = A tuples, columns = B.Val groups, B side 0/1 (COUNT encoding)
+    Cfull, _, ws = ops.join_agg_fwd(tuples, ka, av, kb, gb, None, n, K, N)
+    assert ops.sync_status(ws)[0] == 0
+    q3 = ops.gemm_f64(ones, Cfull).cpu().numpy()[0]
+    RA = orc.Rel(np.zeros(n, np.int32), ka.cpu().numpy(), av.cpu().numpy())
+    RB = orc.Rel(gb.cpu().numpy(), kb.cpu().numpy(), None)
+    Co, _, _ = orc.join_agg(RA, RB, 1, K, N)
+    So, _, _ = orc.join_agg(abs_rel(orc, RA), abs_rel(orc, RB), 1, K, N)
+    assert err_cw(q3, Co[0], So[0]) <= 1e-12
+    # Q4: rows = A tuples, columns = B tuples, then 1^T C 1
+    Ct, _, ws = ops.join_agg_fwd(tuples, ka, av, kb, tuples, bw, n, K, n, unique=True)
+    assert ops.sync_status(ws)[0] == 0
+    col = ops.gemm_f64(Ct, torch.ones((n, 1), dtype=torch.float64, device=dev))
+    q4 = float(ops.gemm_f64(ones, col).cpu()[0, 0])
+    RB4 = orc.Rel(np.zeros(n, np.int32), kb.cpu().numpy(), bw.cpu().numpy())
+    C4, _, _ = orc.join_agg(RA, RB4, 1, K, 1)
+    S4, _, _ = orc.join_agg(abs_rel(orc, RA), abs_rel(orc, RB4), 1, K, 1)
+    assert abs(q4 - C4[0, 0]) <= 1e-12 * S4[0, 0]

@@ -304,3 +304,18 @@ def test_dictionary_matches_library_unique(orc):
     assert np.array_equal(np.concatenate([ca, cb]), inv.astype(np.int32))
     d, ca, cb = orc.dictionary(a[:0], b[:3])
     assert np.array_equal(d, np.unique(b[:3])) and ca.shape == (0,)
+
+
+def test_join3_matches_nested_loops(orc):
+    """Q2 (three-way join) against the triple loop over all tuple triples."""
+    rng = np.random.default_rng(41)
+    for na, nb, nc, d1, d2 in ((30, 40, 35, 6, 5), (0, 10, 10, 3, 3), (12, 0, 9, 4, 4),
+                               (20, 25, 0, 3, 3), (50, 1, 50, 2, 2)):
+        a = rng.integers(0, d1, na) * 1000003 - 7
+        b1 = rng.integers(0, d1, nb) * 1000003 - 7
+        b2 = rng.integers(0, d2, nb) * 999983 + 11
+        c = rng.integers(0, d2, nc) * 999983 + 11
+        want = sorted((i, j, k) for i in range(na) for j in range(nb) for k in range(nc)
+                      if a[i] == b1[j] and b2[j] == c[k])
+        got = orc.join3(a, b1, b2, c)
+        assert [tuple(r) for r in got.tolist()] == want
