@@ -67,8 +67,15 @@ __global__ void dict_insert_kernel(const long long *__restrict__ vals, int64_t n
     }
     unsigned long long h = fmix64(v) & mask;
     for (unsigned long long probe = 0; probe <= mask; ++probe) {
-        const unsigned long long prev = atomicCAS(table + h, kEmpty, v);
-        if (prev == kEmpty || prev == v) return;
+        // a plain read first: a column with few distinct values finds its
+        // value already present without an atomic on a contended slot
+        const unsigned long long seen = __hip_atomic_load(table + h, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+        if (seen == v) return;
+        if (seen == kEmpty) {
+            const unsigned long long prev = atomicCAS(table + h, kEmpty, v);
+            if (prev == kEmpty || prev == v) return;
+        }
         h = (h + 1) & mask;
     }
     atomicOr(&st->overflow, 1u);
