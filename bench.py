@@ -325,6 +325,51 @@ def bench_bsr(stream, log, steps, warmup):
     return out
 
 
+def bench_ooc(stream, log, N=32768, dev_gb=24):
+    """Section 4.2.3: the N x N x N FP64 product with A, B and C in pinned
+    host memory, streamed through dev_gb GB of device memory (the paper's
+    24 GB card), against the same product with everything resident in HBM.
+    One untimed call, then one timed call of each."""
+    import torch
+    from paper_2112_07552_amd import ops
+
+    dev = torch.device("cuda:0")
+    log(f"ooc: generating two {N}x{N} FP64 matrices in pinned host memory")
+    Ad = torch.rand((N, N), dtype=torch.float64, device=dev) * 2 - 1
+    Bd = torch.rand((N, N), dtype=torch.float64, device=dev) * 2 - 1
+    Ah = torch.empty((N, N), dtype=torch.float64, pin_memory=True)
+    Bh = torch.empty((N, N), dtype=torch.float64, pin_memory=True)
+    Ch = torch.empty((N, N), dtype=torch.float64, pin_memory=True)
+    Ah.copy_(Ad)
+    Bh.copy_(Bd)
+    Cd = torch.empty((N, N), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    flops = 2.0 * N ** 3
+    t_dev = time_loop(lambda: ops.gemm_f64(Ad, Bd, out=Cd), 1, 1, stream)
+    del Ad, Bd
+    torch.cuda.empty_cache()
+    dev_bytes = int(dev_gb * 1e9)
+    ops.gemm_f64_host(Ah, Bh, out=Ch, dev_bytes=dev_bytes)   # untimed
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ops.gemm_f64_host(Ah, Bh, out=Ch, dev_bytes=dev_bytes)
+    t_host = (time.perf_counter() - t0) * 1e3
+    b = 128
+    while (b + 128) ** 2 * 48 <= dev_bytes:
+        b += 128
+    nb = -(-N // b)
+    link = 8.0 * (2 * N * N * nb + N * N)
+    sample = float((Ch[:4, :4].to(dev) - Cd[:4, :4]).abs().max())
+    log(f"ooc: device-resident {t_dev:.1f} ms, host-resident {t_host:.1f} ms, block {b}, "
+        f"{link / 1e9:.0f} GB over the host link")
+    return {"N": N, "device_budget_bytes": dev_bytes, "block": b,
+            "ms_device_resident": t_dev, "ms_host_resident": t_host,
+            "tflops_device_resident": flops / (t_dev * 1e-3) / 1e12,
+            "tflops_host_resident": flops / (t_host * 1e-3) / 1e12,
+            "host_link_bytes": link, "host_link_gbs": link / (t_host * 1e-3) / 1e9,
+            "max_abs_diff_4x4_vs_device": sample}
+
+
 def bench_large(stream, log, N=32768):
     """2^30 records per table (N = 32768, the paper's largest MM query), FP32
     values N(0,1) with 5% x1e3 outliers (seed 4).  One forward and one
@@ -422,6 +467,9 @@ def main():
                     help="also time the largest workload: 2^30 records per table, FP32 "
                          "mixture values, mixed int8 form vs FP64 form, forward + adjoint "
                          "with checkpointing")
+    ap.add_argument("--ooc", action="store_true",
+                    help="also time the 32768^3 FP64 product over pinned host memory through "
+                         "a 24 GB device budget (blocked, pipelined) against the HBM-resident one")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 512 MiB device copy, the reference that scales "
                          "profiler byte counters")
@@ -538,6 +586,9 @@ def main():
     large = None
     if args.large:
         large = bench_large(stream, log)
+    ooc = None
+    if args.ooc:
+        ooc = bench_ooc(stream, log)
 
     cpu = None
     if not args.no_cpu:
@@ -576,6 +627,7 @@ def main():
         "mixed": mixed,
         "queries": queries,
         "large": large,
+        "out_of_core": ooc,
     }
     print(json.dumps(out), flush=True)
 

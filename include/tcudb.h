@@ -269,6 +269,27 @@ tcu_status tcu_nonzero(const double *M, int64_t rows, int64_t cols, int64_t ld, 
                        int64_t capacity, int64_t *count, void *ws, size_t ws_bytes,
                        hipStream_t stream);
 
+/* ---- Operands larger than device memory (Section 4.2.3) -----------------
+ *
+ * C (m x n, ldc) = A (m x k, lda) * B (k x n, ldb), FP64 row-major, with A, B
+ * and C in HOST memory (allocate them pinned, with hipHostMalloc, for the
+ * copies to overlap the products; pageable memory is correct but slow).
+ * The device holds only blocks: dev_buf (device memory, 256-byte aligned,
+ * dev_bytes long) must hold 6 block^2 doubles.  block: a multiple of 128,
+ * or 0 for the largest multiple of 128 that fits dev_bytes.
+ * Blocks of A and B stream in on one internal stream while the FP64 matrix
+ * cores multiply on `stream` and finished C blocks stream out on another;
+ * the call creates and destroys those two streams and SYNCHRONISES all
+ * three before it returns (C is complete on return).
+ * Host-link traffic: 8 (m k ceil(n / block) + k n ceil(m / block) + m n) bytes.
+ * Errors: TCU_ERR_ARG (m, n or k < 0, NULL pointer with a nonzero extent,
+ * ld smaller than the row length, block not a multiple of 128),
+ * TCU_ERR_WORKSPACE (dev_buf NULL, misaligned, or smaller than 6 block^2
+ * doubles), TCU_ERR_HIP. */
+tcu_status tcu_gemm_f64_host(int32_t m, int32_t n, int32_t k, const double *A, int64_t lda,
+                             const double *B, int64_t ldb, double *C, int64_t ldc, void *dev_buf,
+                             size_t dev_bytes, int64_t block, hipStream_t stream);
+
 /* SYNCHRONISES the stream, then reads the workspace status block written by
  * the last call that used `ws`.  Returns TCU_ERR_KEY_RANGE if records were
  * skipped, TCU_ERR_NONFINITE if the mixed form met NaN/Inf, else TCU_OK.

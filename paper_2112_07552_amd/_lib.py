@@ -39,7 +39,7 @@ EXPORTS = (
     "tcu_join_agg_fwd", "tcu_join_agg_bwd", "tcu_dict_workspace_bytes", "tcu_dict_encode",
     "tcu_join_agg_row_workspace_bytes", "tcu_join_agg_row",
     "tcu_join_agg_bsr_workspace_bytes", "tcu_join_agg_bsr", "tcu_nonzero_workspace_bytes",
-    "tcu_nonzero", "tcu_sync_status",
+    "tcu_nonzero", "tcu_gemm_f64_host", "tcu_sync_status",
     "tcu_status_str", "tcu_version",
 )
 
@@ -109,6 +109,9 @@ def load():
     L.tcu_nonzero.argtypes = [vp, i64, i64, i64, vp, vp, vp, vp, i64, C.POINTER(C.c_int64), vp,
                               C.c_size_t, vp]
     L.tcu_nonzero.restype = C.c_int
+    L.tcu_gemm_f64_host.argtypes = [i32, i32, i32, vp, i64, vp, i64, vp, i64, vp, C.c_size_t,
+                                    i64, vp]
+    L.tcu_gemm_f64_host.restype = C.c_int
     L.tcu_sync_status.argtypes = [vp, vp, C.POINTER(tcu_status_info)]
     L.tcu_sync_status.restype = C.c_int
     L.tcu_status_str.argtypes = [C.c_int]

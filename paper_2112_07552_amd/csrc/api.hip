@@ -364,6 +364,23 @@ tcu_status tcu_nonzero(const double *M, int64_t rows, int64_t cols, int64_t ld, 
                                   count, ws, stream));
 }
 
+tcu_status tcu_gemm_f64_host(int32_t m, int32_t n, int32_t k, const double *A, int64_t lda,
+                             const double *B, int64_t ldb, double *C, int64_t ldc, void *dev_buf,
+                             size_t dev_bytes, int64_t block, hipStream_t stream) {
+    if (m < 0 || n < 0 || k < 0 || block < 0 || block % 128 != 0) return TCU_ERR_ARG;
+    if ((m > 0 && n > 0 && C == nullptr) || (m > 0 && k > 0 && A == nullptr) ||
+        (k > 0 && n > 0 && B == nullptr))
+        return TCU_ERR_ARG;
+    if ((m > 0 && lda < k) || (k > 0 && ldb < n) || (m > 0 && ldc < n)) return TCU_ERR_ARG;
+    if (m == 0 || n == 0) return TCU_OK;
+    const int64_t b = block ? block : ooc_block(dev_bytes);
+    if (b == 0 || dev_buf == nullptr || ((uintptr_t)dev_buf % kAlign) != 0 ||
+        (size_t)b * (size_t)b * 48 > dev_bytes)
+        return TCU_ERR_WORKSPACE;
+    return hip_status(
+        run_gemm_f64_host(m, n, k, A, lda, B, ldb, C, ldc, dev_buf, dev_bytes, b, stream));
+}
+
 tcu_status tcu_sync_status(void *ws, hipStream_t stream, tcu_status_info *info) {
     if (ws == nullptr || ((uintptr_t)ws % kAlign) != 0) return TCU_ERR_WORKSPACE;
     StatusBlock host;

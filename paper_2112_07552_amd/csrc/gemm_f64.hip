@@ -1,7 +1,8 @@
 // gemm_f64.hip -- step a2 (the contraction C = X * Y of TCUDB Section 3.3)
 // and the two products of the adjoint, in FP64 on the CDNA4 matrix cores.
 //
-// C (m x n) = op(A) (m x k) * op(B) (k x n), all FP64, C overwritten.
+// C (m x n) = op(A) (m x k) * op(B) (k x n), all FP64; C overwritten, or
+// (accumulate) C += op(A) op(B).
 //
 // Design (gfx950):
 //  * v_mfma_f64_16x16x4_f64: one wave multiplies a 16x4 by a 4x16 block;
@@ -132,7 +133,7 @@ template <bool A_KC, bool B_KC, bool FULL>
 __global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
 gemm_f64_kernel(int m, int n, int k, const double *__restrict__ A, int64_t lda,
                 const double *__restrict__ B, int64_t ldb, double *__restrict__ C, int64_t ldc,
-                int vec_a, int vec_b) {
+                int vec_a, int vec_b, int accumulate) {
     __shared__ __attribute__((aligned(16))) double lds_a[2][Tile<A_KC>::elems];
     __shared__ __attribute__((aligned(16))) double lds_b[2][Tile<B_KC>::elems];
 
@@ -197,7 +198,10 @@ gemm_f64_kernel(int m, int n, int k, const double *__restrict__ A, int64_t lda,
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int row = m0 + wm * WM + a * 16 + j + 4 * i;
-                if (FULL || (row < m && col < n)) C[(int64_t)row * ldc + col] = acc[a][b][i];
+                if (FULL || (row < m && col < n)) {
+                    double *dst = C + (int64_t)row * ldc + col;
+                    *dst = accumulate ? *dst + acc[a][b][i] : acc[a][b][i];
+                }
             }
         }
     }
@@ -205,17 +209,17 @@ gemm_f64_kernel(int m, int n, int k, const double *__restrict__ A, int64_t lda,
 
 template <bool A_KC, bool B_KC>
 hipError_t launch(int m, int n, int k, const double *A, int64_t lda, const double *B,
-                  int64_t ldb, double *C, int64_t ldc, hipStream_t s) {
+                  int64_t ldb, double *C, int64_t ldc, int accumulate, hipStream_t s) {
     const int tiles = ((m + BM - 1) / BM) * ((n + BN - 1) / BN);
     const int vec_a = (lda % 2 == 0) && (((uintptr_t)A & 15) == 0);
     const int vec_b = (ldb % 2 == 0) && (((uintptr_t)B & 15) == 0);
     const bool full = vec_a && vec_b && m % BM == 0 && n % BN == 0 && k % BK == 0 && k > 0;
     if (full)
         gemm_f64_kernel<A_KC, B_KC, true><<<tiles, THREADS, 0, s>>>(m, n, k, A, lda, B, ldb, C,
-                                                                    ldc, vec_a, vec_b);
+                                                                    ldc, vec_a, vec_b, accumulate);
     else
         gemm_f64_kernel<A_KC, B_KC, false><<<tiles, THREADS, 0, s>>>(m, n, k, A, lda, B, ldb, C,
-                                                                     ldc, vec_a, vec_b);
+                                                                     ldc, vec_a, vec_b, accumulate);
     return hipGetLastError();
 }
 
@@ -223,12 +227,15 @@ hipError_t launch(int m, int n, int k, const double *A, int64_t lda, const doubl
 
 hipError_t launch_gemm_f64(int trans_a, int trans_b, int m, int n, int k, const double *A,
                            int64_t lda, const double *B, int64_t ldb, double *C, int64_t ldc,
-                           hipStream_t s) {
+                           hipStream_t s, int accumulate) {
     if (m == 0 || n == 0) return hipSuccess;
-    if (!trans_a && !trans_b) return launch<true, false>(m, n, k, A, lda, B, ldb, C, ldc, s);
-    if (!trans_a && trans_b) return launch<true, true>(m, n, k, A, lda, B, ldb, C, ldc, s);
-    if (trans_a && !trans_b) return launch<false, false>(m, n, k, A, lda, B, ldb, C, ldc, s);
-    return launch<false, true>(m, n, k, A, lda, B, ldb, C, ldc, s);
+    if (!trans_a && !trans_b)
+        return launch<true, false>(m, n, k, A, lda, B, ldb, C, ldc, accumulate, s);
+    if (!trans_a && trans_b)
+        return launch<true, true>(m, n, k, A, lda, B, ldb, C, ldc, accumulate, s);
+    if (trans_a && !trans_b)
+        return launch<false, false>(m, n, k, A, lda, B, ldb, C, ldc, accumulate, s);
+    return launch<false, true>(m, n, k, A, lda, B, ldb, C, ldc, accumulate, s);
 }
 
 }  // namespace tcu

@@ -58,10 +58,11 @@ hipError_t launch_gemm_split(int m, int n, int k, int S, int digit_bf16, const v
 // k-steps per exact integer chunk of the split GEMM (host side of its plan).
 int split_chunk_steps(int S, int digit_bf16);
 
-// gemm_f64.hip: C (m x n, ldc) = op(A) * op(B), FP64 matrix cores.
+// gemm_f64.hip: C (m x n, ldc) = op(A) * op(B), FP64 matrix cores; with
+// accumulate != 0, C += op(A) * op(B).
 hipError_t launch_gemm_f64(int trans_a, int trans_b, int m, int n, int k, const double *A,
                            int64_t lda, const double *B, int64_t ldb, double *C, int64_t ldc,
-                           hipStream_t s);
+                           hipStream_t s, int accumulate = 0);
 
 // dict.hip: dictionary encoding (ranks in the sorted union of two columns).
 size_t dict_workspace_bytes(int64_t n);
@@ -87,5 +88,12 @@ size_t nonzero_workspace_bytes(int64_t rows, int64_t cols);
 hipError_t run_nonzero(const double *M, int64_t rows, int64_t cols, int64_t ld, int32_t *out_row,
                        int32_t *out_col, const int32_t *col_map, int32_t *out_key,
                        int64_t capacity, int64_t *count, void *ws, hipStream_t s);
+
+// ooc.hip: C = A * B with A, B, C in host memory, streamed through a device
+// buffer of 6 block^2 doubles (blocked, pipelined over three streams).
+int64_t ooc_block(size_t dev_bytes);
+hipError_t run_gemm_f64_host(int m, int n, int k, const double *A, int64_t lda, const double *B,
+                             int64_t ldb, double *C, int64_t ldc, void *dev_buf,
+                             size_t dev_bytes, int64_t block, hipStream_t s);
 
 }  // namespace tcu

@@ -159,6 +159,28 @@ def gemm_f64(A: torch.Tensor, B: torch.Tensor, trans_a: bool = False, trans_b: b
     return out
 
 
+def gemm_f64_host(A: torch.Tensor, B: torch.Tensor, out: Optional[torch.Tensor] = None,
+                  dev_bytes: int = 1 << 30, block: int = 0, device=None) -> torch.Tensor:
+    """Section 4.2.3: C = A @ B with A, B, C in host memory (FP64 CPU tensors,
+    preferably pinned), streamed through `dev_bytes` of device memory in
+    blocks (block = 0: the largest multiple of 128 that fits)."""
+    for t, name in ((A, "A"), (B, "B")):
+        if t.device.type != "cpu" or t.dtype != torch.float64 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 CPU tensor")
+    m, k = A.shape
+    kb, n = B.shape
+    if k != kb:
+        raise ValueError(f"inner dimensions differ: {k} vs {kb}")
+    if out is None:
+        out = torch.empty((m, n), dtype=torch.float64, pin_memory=True)
+    dev = torch.device("cuda:0") if device is None else torch.device(device)
+    buf = alloc_workspace(int(dev_bytes), dev)
+    check(_lib.load().tcu_gemm_f64_host(m, n, k, _ptr(A), k, _ptr(B), n, _ptr(out), n, _ptr(buf),
+                                        buf.numel(), int(block), _stream(dev)),
+          "tcu_gemm_f64_host")
+    return out
+
+
 def join_agg_fwd(a_group, a_key, a_val, b_key, b_group, b_val, M: int, K: int, N: int,
                  precision: str = "fp64", tol: float = 0.0, with_count: bool = False,
                  ws: Optional[torch.Tensor] = None, unique: bool = False,

@@ -151,3 +151,50 @@ def test_mixed_forms_workspace_and_infeasible(lib):
     cbuf = C.c_void_p(0x2000)
     assert lib.tcu_join_agg_fwd(C.byref(A), C.byref(B), 4, 4, 4, 2, 1e-18, cbuf, None,
                                 C.c_void_p(0x100000), 1 << 30, None) == _lib.TCU_ERR_INFEASIBLE
+
+
+def test_queries_bsr_nonzero_host_argument_errors(lib):
+    """Argument checks of the later entry points, all before any HIP call."""
+    buf = (C.c_double * 16)()
+    p = C.cast(buf, C.c_void_p)
+    cnt = C.c_int64(-1)
+    dev = C.c_void_p(0x100000)
+    # nonzero: negative extents, ld < cols, missing count, one-sided map
+    assert lib.tcu_nonzero(p, -1, 4, 4, p, p, None, None, 4, C.byref(cnt), dev, 1 << 20,
+                           None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_nonzero(p, 4, 4, 3, p, p, None, None, 4, C.byref(cnt), dev, 1 << 20,
+                           None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_nonzero(p, 4, 4, 4, p, p, None, None, 4, None, dev, 1 << 20,
+                           None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_nonzero(p, 4, 4, 4, p, p, p, None, 4, C.byref(cnt), dev, 1 << 20,
+                           None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_nonzero(p, 4, 4, 4, p, p, None, None, 4, C.byref(cnt), None, 0,
+                           None) == _lib.TCU_ERR_WORKSPACE
+    assert lib.tcu_nonzero_workspace_bytes(-1, 5) == 0
+    # host-resident GEMM: shapes, leading dimensions, block size, device buffer
+    assert lib.tcu_gemm_f64_host(-1, 4, 4, p, 4, p, 4, p, 4, dev, 1 << 30, 0,
+                                 None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_gemm_f64_host(4, 4, 4, p, 3, p, 4, p, 4, dev, 1 << 30, 0,
+                                 None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_gemm_f64_host(4, 4, 4, p, 4, p, 4, p, 4, dev, 1 << 30, 100,
+                                 None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_gemm_f64_host(4, 4, 4, None, 4, p, 4, p, 4, dev, 1 << 30, 0,
+                                 None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_gemm_f64_host(4, 4, 4, p, 4, p, 4, p, 4, None, 1 << 30, 0,
+                                 None) == _lib.TCU_ERR_WORKSPACE
+    assert lib.tcu_gemm_f64_host(4, 4, 4, p, 4, p, 4, p, 4, dev, 1000, 0,
+                                 None) == _lib.TCU_ERR_WORKSPACE
+    assert lib.tcu_gemm_f64_host(4, 4, 4, p, 4, p, 4, p, 4, dev, 48 * 128 * 128 - 8, 128,
+                                 None) == _lib.TCU_ERR_WORKSPACE
+    assert lib.tcu_gemm_f64_host(0, 4, 4, p, 4, p, 4, p, 4, None, 0, 0, None) == _lib.TCU_OK
+    # row form and block-sparse form: bad shapes
+    A = _lib.tcu_relation(0, None, None, None, _lib.TCU_F64, 0)
+    assert lib.tcu_join_agg_row(C.byref(A), C.byref(A), 0, 4, p, None, dev, 1 << 20,
+                                None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_join_agg_row_workspace_bytes(4, 0) == 0
+    assert lib.tcu_join_agg_bsr(C.byref(A), C.byref(A), 4, 0, 4, p, dev, 1 << 20,
+                                None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_join_agg_bsr_workspace_bytes(C.byref(A), C.byref(A), 0, 4, 4) == 0
+    assert lib.tcu_dict_encode(None, 5, None, 0, None, None, None, C.byref(cnt), dev, 1 << 20,
+                               None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_dict_workspace_bytes(-3) == 0
