@@ -621,7 +621,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_F64_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_F64_MFMA_TFLOPS,
                      "traffic": counter_traffic(),
-                     "kernel": "gemm_f64_kernel<true,false> (NN, forward)",
+                     "kernel": "gemm_f64_kernel<true,false,true> (NN, forward)",
                      "kernel_ms": gemm_ms},
         "cpu_baseline": cpu,
         "mixed": mixed,
