@@ -178,7 +178,7 @@ def bench_mixed(N, args, stream, log):
     log(f"mixed workload fp64: fwd {f64_fwd:.3f} ms, fwd+adj {f64_step:.3f} ms, err {f64_err:.2e}")
     out["fp64"] = {"ms_fwd": f64_fwd, "ms_fwd_adjoint": f64_step, "err_cw": f64_err}
     target = max(1e-12, f64_err)
-    for precision in ("split_i8", "split_bf16"):
+    for precision in ("crt_i8", "split_i8", "split_bf16"):
         tol = 1e-12
         best = None
         for _ in range(4):
@@ -189,21 +189,28 @@ def bench_mixed(N, args, stream, log):
             best = (tol,) + res
             if res[2] <= target:
                 break
-            tol /= 128.0  # one more digit diagonal
+            # refine: one more digit diagonal (slice forms), 7 more bits (CRT)
+            tol /= 128.0
         if best is None:
             continue
         tol, t_fwd, t_step, err, S = best
-        log(f"mixed workload {precision}: S={S} fwd {t_fwd:.3f} ms, fwd+adj {t_step:.3f} ms, "
-            f"err {err:.2e}")
-        pairs = S * (S + 1) // 2
-        out[precision] = {
-            "slices": S, "tol": tol, "ms_fwd": t_fwd, "ms_fwd_adjoint": t_step, "err_cw": err,
+        log(f"mixed workload {precision}: {'L' if precision == 'crt_i8' else 'S'}={S} "
+            f"fwd {t_fwd:.3f} ms, fwd+adj {t_step:.3f} ms, err {err:.2e}")
+        products = S if precision == "crt_i8" else S * (S + 1) // 2
+        entry = {
+            "tol": tol, "ms_fwd": t_fwd, "ms_fwd_adjoint": t_step, "err_cw": err,
             "equal_accuracy": err <= target,
             "speedup_fwd_vs_fp64": f64_fwd / t_fwd,
             "speedup_fwd_adjoint_vs_fp64": f64_step / t_step,
-            "executed_ops_fwd": pairs * 2.0 * N ** 3,
+            "executed_ops_fwd": products * 2.0 * N ** 3,
             "fwd_elements_per_s": N * N / (t_fwd * 1e-3),
+            "fwd_adjoint_elements_per_s": N * N / (t_step * 1e-3),
         }
+        if precision == "crt_i8":
+            entry["moduli"], entry["bits"] = ops.crt_plan(N, tol)
+        else:
+            entry["slices"] = S
+        out[precision] = entry
     return out
 
 

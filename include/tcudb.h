@@ -55,12 +55,18 @@ typedef enum {
     TCU_PREC_SPLIT_BF16 = 1, /* FP64 encodings cut into 7-bit integer digits
                                 held in BF16, BF16 matrix cores with exact
                                 FP32 partial sums, FP64 combination          */
-    TCU_PREC_SPLIT_I8 = 2    /* the same digits held in int8, int8 matrix
+    TCU_PREC_SPLIT_I8 = 2,   /* the same digits held in int8, int8 matrix
                                 cores with exact int32 partial sums          */
+    TCU_PREC_CRT_I8 = 3      /* FP64 encodings truncated to integers of
+                                `bits` bits per line, residues modulo L small
+                                coprime moduli on the int8 matrix cores (one
+                                exact GEMM per modulus), the integer product
+                                recovered by the Chinese remainder theorem */
 } tcu_precision;
 
 /* Largest slice count of the mixed forms (8 digits of 7 bits). */
 #define TCU_MAX_SLICES 8
+#define TCU_MAX_MODULI 15
 
 /* Relation flags. */
 #define TCU_REL_UNIQUE_CELLS 1u /* no two records share a (group, key) pair, as
@@ -134,6 +140,19 @@ tcu_status tcu_encode(const tcu_relation *R, int transpose, int32_t rows, int32_
  * only: touches no device. */
 int tcu_split_slices(tcu_precision p, int32_t k, double tol);
 
+/* The plan of the CRT form (TCU_PREC_CRT_I8) for a contraction of length k:
+ * the smallest integer width `bits` with
+ *   2^(2 - bits) + 2^(2 - 2 bits) + 2^-51 <= tol
+ * (the bound on |error| / (k * max|row of A| * max|column of B|) from the
+ * truncation of both operands to `bits`-bit integers per line, plus the
+ * rounding of the reconstruction), and the smallest number L of moduli
+ * (from 256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 217, 211, 199,
+ * 197) whose product exceeds 4 k 2^(2 bits).  Returns L and writes *bits, or
+ * returns TCU_ERR_INFEASIBLE (tol below what 53-bit inputs or 15 moduli
+ * reach, or k >= 131072, beyond exact int32 sums), or TCU_ERR_ARG.
+ * tcu_split_slices(TCU_PREC_CRT_I8, k, tol) returns the same L.  Host only. */
+int tcu_crt_plan(int32_t k, double tol, int32_t *bits);
+
 /* Step a0 device part alone: the per-line scale exponents and S digit slices
  * of a dense FP64 matrix Z (rows x cols, leading dimension ld).
  * axis == 0: lines are rows (length cols); 1: lines are columns (length rows).
@@ -166,10 +185,12 @@ tcu_status tcu_gemm_f64(int trans_a, int trans_b, int32_t m, int32_t n, int32_t 
  * rows g ascending, columns h ascending) = the join-aggregate above.
  * count (M x N int32, or NULL): exact number of joined pairs per (g,h); SQL's
  * result holds exactly the cells with count > 0 (a dense C shows 0 elsewhere).
- * The mixed forms (TCU_PREC_SPLIT_*) guarantee, cell by cell,
+ * The mixed forms (TCU_PREC_SPLIT_*, TCU_PREC_CRT_I8) guarantee, cell by
+ * cell,
  *   |C - exact| <= tol * K * max_k |X[g,k]| * max_k |Y[k,h]|
- * with the slice count from tcu_split_slices (tol <= 0 means 1e-12), and
- * return TCU_ERR_INFEASIBLE (launching nothing) when no slice count can; the
+ * with the slice count from tcu_split_slices or the plan of tcu_crt_plan
+ * (tol <= 0 means 1e-12), and return TCU_ERR_INFEASIBLE (launching
+ * nothing) when no plan can; the
  * count output is exact in every form.  No call synchronises the host.
  * Device-side conditions (out-of-range records, NaN/Inf in the mixed forms)
  * are reported by tcu_sync_status. */

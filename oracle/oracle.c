@@ -451,3 +451,80 @@ int64_t orc_dict(int64_t na, const int64_t *a, int64_t nb, const int64_t *b, int
     for (int64_t i = 0; i < nb; ++i) cb[i] = rank_of(dict, k, b[i]);
     return k;
 }
+
+/*
+ * The product of integer truncations, the quantity the CRT mixed form
+ * computes exactly before its final scaling (the error model of that form:
+ * Section 4.2.1's feasibility bound, retargeted, as for orc_split).
+ *
+ * X is M x K and Y is K x N, row-major FP64.  Every row g of X gets
+ *   e_g = the exponent with 2^(e_g - 1) <= max_k |X[g,k]| < 2^e_g (0 if zero),
+ *   Xi[g,k] = trunc(X[g,k] * 2^(bits - e_g))            (|Xi| < 2^bits),
+ * every column h of Y likewise f_h and Yi[k,h]; then
+ *   out[g,h] = (sum_k Xi[g,k] Yi[k,h]) * 2^(e_g + f_h - 2 bits)
+ * with the sum exact in 128-bit integers and one rounding to FP64 at the end
+ * (the scaling by a power of two is exact).  bits in [1, 53]; non-finite
+ * inputs give -1 (returned), else the number of threads used.
+ */
+int orc_trunc_product(int32_t M, int32_t K, int32_t N, const double *X, const double *Y, int bits,
+                      double *out, int threads) {
+    if (bits < 1 || bits > 53) return -1;
+    int *ex = (int *)malloc(sizeof(int) * (size_t)(M > 0 ? M : 1));
+    int *ey = (int *)malloc(sizeof(int) * (size_t)(N > 0 ? N : 1));
+    int64_t *xi = (int64_t *)malloc(sizeof(int64_t) * ((size_t)M * (size_t)K + 1));
+    int64_t *yt = (int64_t *)malloc(sizeof(int64_t) * ((size_t)K * (size_t)N + 1));
+    if (!ex || !ey || !xi || !yt) {
+        free(ex); free(ey); free(xi); free(yt);
+        return -2;
+    }
+    int bad = 0;
+    for (int32_t g = 0; g < M; ++g) {
+        double mx = 0.0;
+        for (int32_t k = 0; k < K; ++k) {
+            const double v = X[(size_t)g * K + k];
+            if (!isfinite(v)) bad = 1;
+            else if (fabs(v) > mx) mx = fabs(v);
+        }
+        int e = 0;
+        if (mx > 0.0) frexp(mx, &e);
+        ex[g] = e;
+        for (int32_t k = 0; k < K; ++k)
+            xi[(size_t)g * K + k] = (int64_t)trunc(ldexp(X[(size_t)g * K + k], bits - e));
+    }
+    for (int32_t h = 0; h < N; ++h) {
+        double mx = 0.0;
+        for (int32_t k = 0; k < K; ++k) {
+            const double v = Y[(size_t)k * N + h];
+            if (!isfinite(v)) bad = 1;
+            else if (fabs(v) > mx) mx = fabs(v);
+        }
+        int f = 0;
+        if (mx > 0.0) frexp(mx, &f);
+        ey[h] = f;
+        /* column h of Y, transposed so the inner loop runs over contiguous k */
+        for (int32_t k = 0; k < K; ++k)
+            yt[(size_t)h * K + k] = (int64_t)trunc(ldexp(Y[(size_t)k * N + h], bits - f));
+    }
+    if (bad) {
+        free(ex); free(ey); free(xi); free(yt);
+        return -1;
+    }
+    int used = 1;
+#pragma omp parallel num_threads(threads)
+    {
+#pragma omp single
+        used = omp_get_num_threads();
+#pragma omp for schedule(dynamic, 4)
+        for (int32_t g = 0; g < M; ++g) {
+            const int64_t *a = xi + (size_t)g * K;
+            for (int32_t h = 0; h < N; ++h) {
+                const int64_t *b = yt + (size_t)h * K;
+                __int128 p = 0;
+                for (int32_t k = 0; k < K; ++k) p += (__int128)a[k] * (__int128)b[k];
+                out[(size_t)g * N + h] = ldexp((double)p, ex[g] + ey[h] - 2 * bits);
+            }
+        }
+    }
+    free(ex); free(ey); free(xi); free(yt);
+    return used;
+}

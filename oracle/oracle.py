@@ -68,6 +68,9 @@ def lib():
         L.orc_split.restype = C.c_int64
         L.orc_dict.argtypes = [C.c_int64, _i64p, C.c_int64, _i64p, _i32p, _i32p, _i64p]
         L.orc_dict.restype = C.c_int64
+        L.orc_trunc_product.argtypes = [C.c_int32, C.c_int32, C.c_int32, _f64p, _f64p, C.c_int,
+                                        _f64p, C.c_int]
+        L.orc_trunc_product.restype = C.c_int
         _lib = L
     return _lib
 
@@ -251,4 +254,23 @@ def join3(a_id1, b_id1, b_id2, c_id2):
         return np.empty((0, 3), dtype=np.int64)
     t = np.concatenate(out)
     return t[np.lexsort((t[:, 2], t[:, 1], t[:, 0]))]
+
+
+def trunc_product(X, Y, bits: int, threads: Optional[int] = None):
+    """(X' Y') 2^(e_g + f_h - 2 bits), X' and Y' the per-row / per-column
+    truncations of X and Y to `bits`-bit integers, the integer product exact
+    (128-bit) and rounded once: what the CRT mixed form reconstructs."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    M, K = X.shape
+    K2, N = Y.shape
+    assert K == K2
+    out = np.empty((M, N), dtype=np.float64)
+    r = lib().orc_trunc_product(M, K, N, _p(X, _f64p), _p(Y, _f64p), bits, _p(out, _f64p),
+                                threads or threads_default())
+    if r == -1:
+        raise FloatingPointError("oracle.trunc_product: non-finite input or bad bits")
+    if r < 0:
+        raise MemoryError("oracle: allocation failed")
+    return out
 

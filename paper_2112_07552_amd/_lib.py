@@ -26,6 +26,7 @@ TCU_F32 = 1
 TCU_PREC_FP64 = 0
 TCU_PREC_SPLIT_BF16 = 1
 TCU_PREC_SPLIT_I8 = 2
+TCU_PREC_CRT_I8 = 3
 TCU_MAX_SLICES = 8
 
 TCU_WS_BACKWARD = 1
@@ -35,7 +36,7 @@ TCU_REL_UNIQUE_CELLS = 1
 TCU_BWD_SAVED_ENCODINGS = 1
 
 EXPORTS = (
-    "tcu_workspace_bytes", "tcu_split_slices", "tcu_split", "tcu_encode", "tcu_gemm_f64",
+    "tcu_workspace_bytes", "tcu_split_slices", "tcu_crt_plan", "tcu_split", "tcu_encode", "tcu_gemm_f64",
     "tcu_join_agg_fwd", "tcu_join_agg_bwd", "tcu_dict_workspace_bytes", "tcu_dict_encode",
     "tcu_join_agg_row_workspace_bytes", "tcu_join_agg_row",
     "tcu_join_agg_bsr_workspace_bytes", "tcu_join_agg_bsr", "tcu_nonzero_workspace_bytes",
@@ -76,6 +77,8 @@ def load():
     vp, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     L.tcu_workspace_bytes.argtypes = [rel_p, rel_p, i32, i32, i32, C.c_int, C.c_int]
     L.tcu_workspace_bytes.restype = C.c_size_t
+    L.tcu_crt_plan.argtypes = [i32, f64, C.POINTER(C.c_int32)]
+    L.tcu_crt_plan.restype = C.c_int
     L.tcu_split_slices.argtypes = [C.c_int, i32, f64]
     L.tcu_split_slices.restype = C.c_int
     L.tcu_split.argtypes = [vp, i32, i32, i64, C.c_int, C.c_int, i32, vp, i32, i32, vp, vp,

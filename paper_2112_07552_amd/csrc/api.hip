@@ -29,11 +29,35 @@ bool relation_ok(const tcu_relation *R) {
 
 bool shapes_ok(int32_t M, int32_t K, int32_t N) { return M >= 1 && K >= 1 && N >= 1; }
 
-bool is_split(tcu_precision p) { return p == TCU_PREC_SPLIT_BF16 || p == TCU_PREC_SPLIT_I8; }
+bool is_split(tcu_precision p) {
+    return p == TCU_PREC_SPLIT_BF16 || p == TCU_PREC_SPLIT_I8 || p == TCU_PREC_CRT_I8;
+}
+bool is_crt(tcu_precision p) { return p == TCU_PREC_CRT_I8; }
+
+// The CRT form's plan: truncation width and number of moduli (see tcudb.h).
+int crt_plan(int32_t k, double tol, int32_t *bits_out) {
+    if (k < 1) return TCU_ERR_ARG;
+    if (!(tol > 0.0)) tol = 1e-12;
+    if (k >= 131072) return TCU_ERR_INFEASIBLE;
+    int bits = 0;
+    for (int b = 2; b <= 53; ++b) {
+        const double bound = ldexp(1.0, 2 - b) + ldexp(1.0, 2 - 2 * b) + ldexp(1.0, -51);
+        if (bound <= tol) { bits = b; break; }
+    }
+    if (bits == 0) return TCU_ERR_INFEASIBLE;
+    const double need = 2.0 * bits + log2((double)k) + 2.0;
+    for (int L = 1; L <= crt_max_moduli(); ++L)
+        if (crt_modulus_bits(L) > need) {
+            if (bits_out != nullptr) *bits_out = bits;
+            return L;
+        }
+    return TCU_ERR_INFEASIBLE;
+}
 bool precision_ok(tcu_precision p) { return p == TCU_PREC_FP64 || is_split(p); }
 
 size_t pad128(int64_t x) { return (size_t)((x + 127) / 128 * 128); }
 size_t pad64(int64_t x) { return (size_t)((x + 63) / 64 * 64); }
+size_t pad256(int64_t x) { return (size_t)((x + 255) / 256 * 256); }
 size_t maxz(size_t a, size_t b) { return a > b ? a : b; }
 
 // Workspace layout:
@@ -44,7 +68,8 @@ size_t maxz(size_t a, size_t b) { return a > b ? a : b; }
 // In the mixed forms "A" is the left operand of a product (X forward, W
 // for dX, X^T for dY) and "B" the right one (Y, Y^T, W).
 struct Layout {
-    size_t x = 0, y = 0, g = 0, mba = 0, mbb = 0, ea = 0, eb = 0, sa = 0, sb = 0, total = 0;
+    size_t x = 0, y = 0, g = 0, mba = 0, mbb = 0, ea = 0, eb = 0, sa = 0, sb = 0, res = 0;
+    size_t total = 0;
 };
 
 Layout plan_layout(int32_t M, int32_t K, int32_t N, tcu_precision p, int flags) {
@@ -60,23 +85,31 @@ Layout plan_layout(int32_t M, int32_t K, int32_t N, tcu_precision p, int flags) 
         off += align_up(maxz((size_t)M * K, (size_t)K * N) * sizeof(double));
     }
     if (is_split(p)) {
-        const size_t digit = p == TCU_PREC_SPLIT_I8 ? 1 : 2;
+        const size_t digit = p == TCU_PREC_SPLIT_BF16 ? 2 : 1;
+        const size_t planes = is_crt(p) ? TCU_MAX_MODULI : TCU_MAX_SLICES;
+        auto padl = [&](int64_t x) { return is_crt(p) ? pad256(x) : pad128(x); };
         // (lines, length) of each operand: forward X (M, K) and Y (N, K);
         // backward W (M, N) and Y^T (K, N) for dX, X^T (K, M) and W (N, M) for dY
-        size_t la = pad128(M), lb = pad128(N);
-        size_t za = pad128(M) * pad64(K), zb = pad128(N) * pad64(K);
+        size_t la = padl(M), lb = padl(N);
+        size_t za = padl(M) * pad64(K), zb = padl(N) * pad64(K);
+        size_t out = (size_t)M * N;  // CRT: per-modulus residues of each product
         if (bwd) {
-            la = maxz(la, pad128(K));
-            lb = maxz(lb, pad128(K));
-            za = maxz(za, maxz(pad128(M) * pad64(N), pad128(K) * pad64(M)));
-            zb = maxz(zb, maxz(pad128(K) * pad64(N), pad128(N) * pad64(M)));
+            la = maxz(la, padl(K));
+            lb = maxz(lb, padl(K));
+            za = maxz(za, maxz(padl(M) * pad64(N), padl(K) * pad64(M)));
+            zb = maxz(zb, maxz(padl(K) * pad64(N), padl(N) * pad64(M)));
+            out = maxz(out, maxz((size_t)M * K, (size_t)K * N));
         }
         L.mba = off; off += align_up(la * 8);
         L.mbb = off; off += align_up(lb * 8);
         L.ea = off; off += align_up(la * 4);
         L.eb = off; off += align_up(lb * 4);
-        L.sa = off; off += align_up(TCU_MAX_SLICES * za * digit);
-        L.sb = off; off += align_up(TCU_MAX_SLICES * zb * digit);
+        L.sa = off; off += align_up(planes * za * digit);
+        L.sb = off; off += align_up(planes * zb * digit);
+        if (is_crt(p)) {
+            L.res = off;
+            off += align_up(TCU_MAX_MODULI * out);
+        }
     }
     L.total = off;
     return L;
@@ -116,8 +149,31 @@ struct SplitOperand {
 };
 
 hipError_t split_product(const SplitOperand &a, const SplitOperand &b, int m, int n, int k,
-                         int S, tcu_precision p, void *ws, const Layout &L, StatusBlock *st,
-                         double *C, int64_t ldc, hipStream_t s) {
+                         int S, tcu_precision p, double tol, void *ws, const Layout &L,
+                         StatusBlock *st, double *C, int64_t ldc, hipStream_t s) {
+    if (is_crt(p)) {
+        int32_t bits = 0;
+        const int nmod = crt_plan(k, tol, &bits);
+        if (nmod != S) return hipErrorInvalidValue;  // the caller planned with the same k, tol
+        const int len_pad = (int)pad64(k);
+        const int la = (int)pad256(m), lb = (int)pad256(n);
+        auto *mba = at<unsigned long long>(ws, L.mba);
+        auto *mbb = at<unsigned long long>(ws, L.mbb);
+        int *ea = at<int>(ws, L.ea), *eb = at<int>(ws, L.eb);
+        int8_t *sa = at<int8_t>(ws, L.sa), *sb = at<int8_t>(ws, L.sb);
+        hipError_t e = launch_line_max(a.Z, a.rows, a.cols, a.ld, a.axis, mba, st, s);
+        if (e == hipSuccess)
+            e = launch_crt_split(a.Z, a.rows, a.cols, a.ld, a.axis, mba, S, bits, sa, la, len_pad,
+                                 ea, s);
+        if (e == hipSuccess) e = launch_line_max(b.Z, b.rows, b.cols, b.ld, b.axis, mbb, st, s);
+        if (e == hipSuccess)
+            e = launch_crt_split(b.Z, b.rows, b.cols, b.ld, b.axis, mbb, S, bits, sb, lb, len_pad,
+                                 eb, s);
+        if (e == hipSuccess)
+            e = launch_gemm_crt(m, n, k, S, bits, sa, la, sb, lb, len_pad, at<int8_t>(ws, L.res),
+                                ea, eb, C, ldc, 0, s);
+        return e;
+    }
     const int bf16 = p == TCU_PREC_SPLIT_BF16;
     const int len_pad = (int)pad64(k);
     const int la = (int)pad128(m), lb = (int)pad128(n);
@@ -148,8 +204,11 @@ size_t tcu_workspace_bytes(const tcu_relation *A, const tcu_relation *B, int32_t
     return plan_layout(M, K, N, p, flags).total;
 }
 
+int tcu_crt_plan(int32_t k, double tol, int32_t *bits) { return crt_plan(k, tol, bits); }
+
 int tcu_split_slices(tcu_precision p, int32_t k, double tol) {
     if (!is_split(p) || k < 1) return TCU_ERR_ARG;
+    if (is_crt(p)) return crt_plan(k, tol, nullptr);
     if (!(tol > 0.0)) tol = 1e-12;
     const int bf16 = p == TCU_PREC_SPLIT_BF16;
     const int kstep = bf16 ? 16 : 32;
@@ -170,7 +229,7 @@ tcu_status tcu_split(const double *Z, int32_t rows, int32_t cols, int64_t ld, in
                      hipStream_t stream) {
     if (Z == nullptr || slices == nullptr || exps == nullptr) return TCU_ERR_ARG;
     if (rows < 1 || cols < 1 || ld < cols || (axis != 0 && axis != 1)) return TCU_ERR_ARG;
-    if (!is_split(p) || S < 1 || S > TCU_MAX_SLICES) return TCU_ERR_ARG;
+    if (!is_split(p) || is_crt(p) || S < 1 || S > TCU_MAX_SLICES) return TCU_ERR_ARG;
     const int lines = axis == 0 ? rows : cols, len = axis == 0 ? cols : rows;
     if (lines_pad < lines || lines_pad % 128 || len_pad < len || len_pad % 64) return TCU_ERR_ARG;
     if (!ws_ok(ws, ws_bytes, sizeof(StatusBlock) + (size_t)lines_pad * 8)) return TCU_ERR_WORKSPACE;
@@ -239,7 +298,7 @@ tcu_status tcu_join_agg_fwd(const tcu_relation *A, const tcu_relation *B, int32_
     } else {
         // X: M lines (rows) of length K; Y: N lines (columns) of length K
         const SplitOperand a{X, M, K, K, 0}, b{Y, K, N, N, 1};
-        TCU_TRY(split_product(a, b, M, N, K, S, p, ws, L, st, C, N, stream));
+        TCU_TRY(split_product(a, b, M, N, K, S, p, tol, ws, L, st, C, N, stream));
     }
     return TCU_OK;
 }
@@ -277,7 +336,7 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
         } else {
             // dC: M lines (rows) of length N; Y^T: K lines = rows of Y, length N
             const SplitOperand a{dC, M, N, N, 0}, b{Y, K, N, N, 0};
-            TCU_TRY(split_product(a, b, M, K, N, S1, p, ws, L, st, G, K, stream));
+            TCU_TRY(split_product(a, b, M, K, N, S1, p, tol, ws, L, st, G, K, stream));
         }
         TCU_TRY(launch_gather(*A, 0, M, K, G, dA_val, stream));
     }
@@ -288,7 +347,7 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
         } else {
             // X^T: K lines = columns of X, length M; dC: N lines = columns, length M
             const SplitOperand a{X, M, K, K, 1}, b{dC, M, N, N, 1};
-            TCU_TRY(split_product(a, b, K, N, M, S2, p, ws, L, st, G, N, stream));
+            TCU_TRY(split_product(a, b, K, N, M, S2, p, tol, ws, L, st, G, N, stream));
         }
         TCU_TRY(launch_gather(*B, 1, K, N, G, dB_val, stream));
     }

@@ -1,0 +1,506 @@
+// crt.hip -- step a2 in a second mixed-precision form: the product from
+// residues modulo small pairwise-coprime moduli on the int8 matrix cores,
+// combined by the Chinese remainder theorem (the construction of Ozaki,
+// Uchino and Imamura's "Ozaki scheme II", written here from its idea).
+//
+// Every line (row of X, column of Y) is scaled by a power of two from its
+// largest magnitude and truncated to an integer of `bits` bits:
+//   e    = exponent with 2^(e-1) <= max |z| < 2^e  (0 for a zero line),
+//   z'   = trunc(z * 2^(bits - e)),   |z'| < 2^bits,
+// so the exact integer product P = X' Y' satisfies |P| < K 2^(2 bits).  With
+// moduli m_1..m_L (m_i <= 256, product M > 4 K 2^(2 bits)) the residues
+// X'_i = X' mod m_i and Y'_i = Y' mod m_i, taken in the symmetric range
+// [-floor(m/2), floor((m-1)/2)], fit int8; each T_i = X'_i Y'_i is one int8
+// GEMM with exact int32 accumulation (|T_i| <= K 2^14 < 2^31 for K < 2^17),
+// and P mod m_i = T_i mod m_i.  P itself is recovered from its L residues:
+//   S = sum_i r_i w_i,  w_i = (M / m_i) * ((M / m_i)^(-1) mod m_i),
+//   P = S - M * round(S / M),
+// with S and M held exactly as three limbs of 40 bits in FP64 (every limb
+// product and sum below 2^53), normalised, and summed into one double.
+// Then C = P * 2^(e_g + f_h - 2 bits).
+//
+// Work: L int8 GEMMs instead of the S (S+1) / 2 digit products of the slice
+// form, and one accumulator per output instead of one per diagonal, so the
+// workgroup tile is 256 x 256.  For tol = 1e-12 at K = 4096: bits = 42,
+// L = 13.
+//
+// The GEMM: 8 waves of 128 x 64 (4 x 2 blocks of v_mfma_i32_32x32x32_i8,
+// 128 accumulator registers), one stage = two k-steps of both operands (32
+// KB), four stages in LDS filled by direct-to-LDS loads issued three stages
+// ahead; the fragments of the next k-step are read while the current one
+// multiplies, and the barrier sits between the two k-steps of a stage.
+#include "internal.h"
+
+namespace tcu {
+namespace {
+
+typedef int i4 __attribute__((ext_vector_type(4)));
+typedef int i16v __attribute__((ext_vector_type(16)));
+
+constexpr int kThreads = 256;
+constexpr int kMaxMod = 15;
+constexpr int kModuli[kMaxMod] = {256, 255, 253, 251, 247, 241, 239, 233,
+                                  229, 227, 223, 217, 211, 199, 197};
+
+struct CrtConsts {
+    int L, bits;
+    double m[kMaxMod], inv_m[kMaxMod];
+    double w[kMaxMod][3];  // w_i = w2 2^80 + w1 2^40 + w0
+    double Mp[3];          // M in the same limbs
+    double Md;             // M rounded to double
+};
+
+// symmetric residue of an integer-valued double |x| < 2^53 modulo m
+__device__ inline double sym_mod(double x, double m, double inv_m) {
+    const double q = rint(x * inv_m);
+    double r = fma(-q, m, x);  // exact: |q m| < 2^53, |x - q m| < 2 m
+    const double hi = floor((m - 1.0) * 0.5), lo = -floor(m * 0.5);
+    if (r > hi) r -= m;
+    if (r < lo) r += m;
+    return r;
+}
+
+__device__ inline int line_exp(unsigned long long bits) {
+    const double mx = __longlong_as_double((long long)bits);
+    int e = 0;
+    if (mx > 0.0) frexp(mx, &e);
+    return e;
+}
+
+__device__ inline void store8(int8_t *dst, const int8_t (&d)[8]) {
+    uint2 v;
+    v.x = (uint32_t)(uint8_t)d[0] | ((uint32_t)(uint8_t)d[1] << 8) |
+          ((uint32_t)(uint8_t)d[2] << 16) | ((uint32_t)(uint8_t)d[3] << 24);
+    v.y = (uint32_t)(uint8_t)d[4] | ((uint32_t)(uint8_t)d[5] << 8) |
+          ((uint32_t)(uint8_t)d[6] << 16) | ((uint32_t)(uint8_t)d[7] << 24);
+    *reinterpret_cast<uint2 *>(dst) = v;
+}
+
+// residue plane layout (as the slice form): res[i][t / 32][(t % 32) / 16][line][t % 16]
+__device__ inline int64_t res_offset(int line, int t, int lines_pad) {
+    return (((int64_t)(t >> 5) * 2 + ((t >> 4) & 1)) * lines_pad + line) * 16 + (t & 15);
+}
+
+// Lines are rows.  A thread owns the 16 positions of one 16-byte half of one
+// row; consecutive threads own consecutive rows, so every residue store is
+// one 16-byte vector and a wave's stores form one contiguous 1 KB run.
+__global__ void __launch_bounds__(kThreads)
+crt_rows_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
+                const unsigned long long *__restrict__ maxbits, CrtConsts cc,
+                int8_t *__restrict__ out, int lines_pad, int len_pad, int *__restrict__ exps) {
+    const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (gid >= (int64_t)lines_pad * (len_pad / 16)) return;
+    const int row = (int)(gid % lines_pad);
+    const int t0 = (int)(gid / lines_pad) * 16;
+    const bool live = row < rows;
+    const int e = live ? line_exp(maxbits[row]) : 0;
+    if (live && t0 == 0) exps[row] = e;
+    double zi[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int c = t0 + j;
+        double z = (live && c < cols) ? Z[(int64_t)row * ld + c] : 0.0;
+        if (!isfinite(z)) z = 0.0;
+        zi[j] = trunc(ldexp(z, cc.bits - e));
+    }
+    const int64_t plane = (int64_t)lines_pad * len_pad;
+    int8_t *o = out + res_offset(row, t0, lines_pad);
+    for (int i = 0; i < cc.L; ++i) {
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint32_t v = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                v |= (uint32_t)(uint8_t)(int8_t)(int)sym_mod(zi[4 * q + j], cc.m[i], cc.inv_m[i])
+                     << (8 * j);
+            w[q] = v;
+        }
+        *reinterpret_cast<uint4 *>(o + (int64_t)i * plane) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
+// Lines are columns: a 64 x 64 tile through LDS, one modulus at a time.
+__global__ void __launch_bounds__(kThreads)
+crt_cols_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
+                const unsigned long long *__restrict__ maxbits, CrtConsts cc,
+                int8_t *__restrict__ out, int lines_pad, int len_pad, int *__restrict__ exps) {
+    __shared__ int8_t tile[64][64 + 8];  // [col][row]
+    const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+    const int tc = threadIdx.x & 63, tr = threadIdx.x >> 6;
+    const int col = c0 + tc;
+    const int e = col < cols ? line_exp(maxbits[col]) : 0;
+    if (blockIdx.x == 0 && tr == 0 && col < cols) exps[col] = e;
+    double zi[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int row = r0 + tr + 4 * j;
+        double z = (row < rows && col < cols) ? Z[(int64_t)row * ld + col] : 0.0;
+        if (!isfinite(z)) z = 0.0;
+        zi[j] = trunc(ldexp(z, cc.bits - e));
+    }
+    const int64_t plane = (int64_t)lines_pad * len_pad;
+    // writer: thread -> (column wc, 16 rows starting at 16 wq)
+    const int wc = threadIdx.x >> 2, wq = threadIdx.x & 3;
+    for (int i = 0; i < cc.L; ++i) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            tile[tc][tr + 4 * j] = (int8_t)(int)sym_mod(zi[j], cc.m[i], cc.inv_m[i]);
+        __syncthreads();
+        const int line = c0 + wc;
+        if (line < lines_pad) {
+            int8_t a[8], b[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                a[j] = tile[wc][16 * wq + j];
+                b[j] = tile[wc][16 * wq + 8 + j];
+            }
+            const int t = r0 + 16 * wq;
+            if (t < len_pad) {
+                int8_t *o = out + (int64_t)i * plane + res_offset(line, t, lines_pad);
+                store8(o, a);
+                store8(o + 8, b);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- the GEMM
+// Tile configuration: a workgroup computes GBM x BN outputs with NW waves in
+// a 2 x (NW / 2) grid (each wave 128 rows by BN / (NW / 2) columns, i.e. WA =
+// 4 by WB blocks of 32 x 32) and keeps NS stages of two k-steps in LDS.
+template <int BN_, int NW_, int NS_, int WPE_>
+struct Cfg {
+    static constexpr int BM = 256, BN = BN_, NW = NW_, NS = NS_, WPE = WPE_;
+    static constexpr int threads = 64 * NW;
+    static constexpr int WA = BM / 2 / 32, WB = BN / (NW / 2) / 32;
+    static constexpr int KS = 2 * BM + 2 * BN;      // 16-byte chunks per k-step
+    static constexpr int STAGE = 2 * KS;            // chunks per stage
+    static constexpr int PX = 2 * BM / 64, PY = 2 * BN / 64;  // 1 KB planes per k-step
+    static constexpr int PER_WAVE = 2 * (PX + PY) / NW;
+    static_assert(2 * (PX + PY) % NW == 0, "planes must split evenly over the waves");
+};
+// 256 x 256 tiles, 8 waves, 4 stages of 32 KB (128 KB of LDS, one workgroup
+// per CU).
+#ifndef CRT_CFG
+#define CRT_CFG Cfg<256, 8, 4, 2>
+#endif
+using CrtCfg = CRT_CFG;
+constexpr int NUM_XCD = 8, GROUP_M = 4;
+
+template <int V>
+__device__ inline void wait_vm() {
+    static_assert(V >= 0 && V < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((V & 15) | ((V >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+__device__ inline void barrier_nf() { asm volatile("s_barrier" ::: "memory"); }
+
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) const void global_cvoid;
+
+// stage st (k-steps 2 st, 2 st + 1) of modulus plane sets xi, yi into buf:
+// LDS chunk of (k-step s, half h, line l) is s KS + h BM + l for X and
+// s KS + 2 BM + h BN + l for Y
+template <typename G>
+__device__ inline void issue(i4 *buf, int st, const int8_t *xi, int xlp, int m0, const int8_t *yi,
+                             int ylp, int n0, int wave, int lane) {
+#pragma unroll
+    for (int j = 0; j < G::PER_WAVE; ++j) {
+        const int q = wave + G::NW * j;
+        const int s = q / (G::PX + G::PY), r = q % (G::PX + G::PY);
+        const int kb = 2 * st + s;
+        const int8_t *src;
+        int dst;
+        if (r < G::PX) {
+            const int h = r / (G::BM / 64), lb = r % (G::BM / 64);
+            src = xi + ((((int64_t)kb * 2 + h) * xlp) + m0 + lb * 64 + lane) * 16;
+            dst = s * G::KS + h * G::BM + lb * 64;
+        } else {
+            const int r2 = r - G::PX;
+            const int h = r2 / (G::BN / 64), lb = r2 % (G::BN / 64);
+            src = yi + ((((int64_t)kb * 2 + h) * ylp) + n0 + lb * 64 + lane) * 16;
+            dst = s * G::KS + 2 * G::BM + h * G::BN + lb * 64;
+        }
+        __builtin_amdgcn_global_load_lds((global_cvoid *)src, (lds_void *)(buf + dst), 16, 0, 0);
+    }
+}
+
+template <int WA, int WB>
+struct Frag {
+    i4 a[WA], b[WB];
+};
+
+template <typename G>
+__device__ inline void read_frag(const i4 *buf, int s, int wm, int wn, int half, int l32,
+                                 Frag<G::WA, G::WB> &f) {
+#pragma unroll
+    for (int a = 0; a < G::WA; ++a)
+        f.a[a] = buf[s * G::KS + half * G::BM + wm * 32 * G::WA + a * 32 + l32];
+#pragma unroll
+    for (int b = 0; b < G::WB; ++b)
+        f.b[b] = buf[s * G::KS + 2 * G::BM + half * G::BN + wn * 32 * G::WB + b * 32 + l32];
+}
+
+// Half H of one k-step's products: row blocks [H WA / 2, (H + 1) WA / 2).
+template <int H, int WA, int WB>
+__device__ inline void mma_half(const Frag<WA, WB> &f, i16v (&acc)[WA][WB]) {
+#pragma unroll
+    for (int a = H * WA / 2; a < (H + 1) * WA / 2; ++a)
+#pragma unroll
+        for (int b = 0; b < WB; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a[a], f.b[b], acc[a][b], 0, 0, 0);
+}
+
+template <typename G>
+__global__ void __launch_bounds__(G::threads) __attribute__((amdgpu_waves_per_eu(G::WPE, G::WPE)))
+gemm_crt_kernel(int m, int n, int nblk, int tiles_m, int tiles_n, const int8_t *__restrict__ xs,
+                int xlp, const int8_t *__restrict__ ys, int ylp, int64_t plane_x,
+                int64_t plane_y, CrtConsts cc, int8_t *__restrict__ res) {
+    constexpr int WA = G::WA, WB = G::WB, PW = G::PER_WAVE, NS = G::NS, NW = G::NW;
+    __shared__ __attribute__((aligned(16))) i4 lds[NS][G::STAGE];
+    // workgroup -> (modulus, tile); tiles of one modulus are consecutive and
+    // grouped GROUP_M tile-rows deep, spread over the XCDs in contiguous runs
+    const int tiles = tiles_m * tiles_n;
+    const int total = tiles * cc.L;
+    const int wg = blockIdx.x;
+    const int per = total / NUM_XCD;
+    const int logical = wg < per * NUM_XCD ? (wg % NUM_XCD) * per + wg / NUM_XCD : wg;
+    const int mod = logical / tiles;
+    const int t = logical % tiles;
+    const int group = GROUP_M * tiles_n;
+    const int first_m = (t / group) * GROUP_M;
+    const int gm = min(tiles_m - first_m, GROUP_M);
+    const int tm = first_m + (t % group) % gm, tn = (t % group) / gm;
+    const int m0 = tm * G::BM, n0 = tn * G::BN;
+    const int8_t *xi = xs + (int64_t)mod * plane_x;
+    const int8_t *yi = ys + (int64_t)mod * plane_y;
+
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int l32 = lane & 31, half = lane >> 5;
+
+    i16v acc[WA][WB];
+#pragma unroll
+    for (int a = 0; a < WA; ++a)
+#pragma unroll
+        for (int b = 0; b < WB; ++b) acc[a][b] = i16v{};
+
+    const int nst = nblk / 2;
+    // prologue: stages 0 .. NS-2 in flight (repeating the last stage when
+    // there are fewer), fragments of k-step 0
+#pragma unroll
+    for (int st = 0; st < NS - 1; ++st)
+        issue<G>(lds[st], st < nst ? st : nst - 1, xi, xlp, m0, yi, ylp, n0, wave, lane);
+    wait_vm<(NS - 2) * PW>();
+    barrier_nf();
+
+    // One stage: fc holds the fragments of its first k-step.  The fragments
+    // of the second k-step (fm) are read between the two halves of the
+    // first k-step's MFMAs, and the next stage's first k-step (into fc)
+    // between the two halves of the second's, so every LDS read has half a
+    // k-step of matrix work to land before its use.  Every stage issues one
+    // stage of loads (the last ones repeat stage nst - 1 into buffers no
+    // wave reads any more), so "stage st + 1 has landed" is always "at most
+    // NS - 3 later stages in flight".
+    Frag<WA, WB> fc, fm;
+    read_frag<G>(lds[0], 0, wm, wn, half, l32, fc);
+    for (int st = 0; st < nst; ++st) {
+        mma_half<0>(fc, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        read_frag<G>(lds[st % NS], 1, wm, wn, half, l32, fm);
+        __builtin_amdgcn_sched_barrier(0);
+        mma_half<1>(fc, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        wait_vm<(NS - 3) * PW>();
+        barrier_nf();
+        const int ist = st + NS - 1 < nst ? st + NS - 1 : nst - 1;
+        issue<G>(lds[(st + NS - 1) % NS], ist, xi, xlp, m0, yi, ylp, n0, wave, lane);
+        __builtin_amdgcn_sched_barrier(0);
+        mma_half<0>(fm, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        read_frag<G>(lds[(st + 1) % NS], 0, wm, wn, half, l32, fc);
+        __builtin_amdgcn_sched_barrier(0);
+        mma_half<1>(fm, acc);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    wait_vm<0>();  // no load into LDS outlives the loop
+
+    // epilogue: residues of the int32 sums, int8, row-major per modulus
+    const double md = cc.m[mod], inv = cc.inv_m[mod];
+    int8_t *r = res + (int64_t)mod * m * n;
+#pragma unroll
+    for (int a = 0; a < WA; ++a)
+#pragma unroll
+        for (int b = 0; b < WB; ++b) {
+            const int col = n0 + wn * 32 * WB + b * 32 + l32;
+            if (col >= n) continue;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int row = m0 + wm * 32 * WA + a * 32 + 8 * (i >> 2) + 4 * half + (i & 3);
+                if (row < m)
+                    r[(int64_t)row * n + col] = (int8_t)(int)sym_mod((double)acc[a][b][i], md, inv);
+            }
+        }
+}
+
+// --------------------------------------------------------- reconstruction
+constexpr double kLimb = 1099511627776.0;  // 2^40
+
+// P from S = s2 2^80 + s1 2^40 + s0 (exact limb sums of r_i w_i):
+// q = round(S / M) (|P| < M / 4, so rounding errors cannot move q), the
+// limbs of S - q M exactly, balanced carries (|p0|, |p1| <= 2^39, so the sum
+// rounds only at the end), one double.
+__device__ inline double crt_finish(double s0, double s1, double s2, const CrtConsts &cc) {
+    const double sd = fma(s2, kLimb * kLimb, fma(s1, kLimb, s0));
+    const double q = rint(sd / cc.Md);
+    double p0 = fma(-q, cc.Mp[0], s0), p1 = fma(-q, cc.Mp[1], s1), p2 = fma(-q, cc.Mp[2], s2);
+    double c = rint(p0 * (1.0 / kLimb));
+    p0 = fma(-c, kLimb, p0);
+    p1 += c;
+    c = rint(p1 * (1.0 / kLimb));
+    p1 = fma(-c, kLimb, p1);
+    p2 += c;
+    return fma(p2, kLimb * kLimb, fma(p1, kLimb, p0));
+}
+
+// One thread per 4 consecutive outputs of one row (blockIdx.x = row): the
+// residue reads are 4-byte loads, contiguous across the wave.
+__global__ void __launch_bounds__(kThreads)
+crt_reconstruct_kernel(int m, int n, const int8_t *__restrict__ res, CrtConsts cc,
+                       const int *__restrict__ ex, const int *__restrict__ ey,
+                       double *__restrict__ C, int64_t ldc, int accumulate) {
+    const int row = blockIdx.x;
+    const int col0 = (blockIdx.y * kThreads + threadIdx.x) * 4;
+    if (col0 >= n) return;
+    const int64_t mn = (int64_t)m * n;
+    const int64_t base = (int64_t)row * n + col0;
+    const bool whole = col0 + 4 <= n && (base & 3) == 0;
+    double s[4][3];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s[j][0] = s[j][1] = s[j][2] = 0.0;
+#pragma unroll
+    for (int i = 0; i < kMaxMod; ++i) {
+        if (i >= cc.L) break;
+        const int8_t *p = res + (int64_t)i * mn + base;
+        uint32_t v = 0;
+        if (whole) {
+            v = *reinterpret_cast<const uint32_t *>(p);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (col0 + j < n) v |= (uint32_t)(uint8_t)p[j] << (8 * j);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double r = (double)(int8_t)(v >> (8 * j));
+            s[j][0] = fma(r, cc.w[i][0], s[j][0]);  // exact: |r w| < 2^47, sums < 2^51
+            s[j][1] = fma(r, cc.w[i][1], s[j][1]);
+            s[j][2] = fma(r, cc.w[i][2], s[j][2]);
+        }
+    }
+    const int er = ex[row] - 2 * cc.bits;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int col = col0 + j;
+        if (col < n) {
+            const double v = ldexp(crt_finish(s[j][0], s[j][1], s[j][2], cc), er + ey[col]);
+            double *dst = C + (int64_t)row * ldc + col;
+            *dst = accumulate ? *dst + v : v;
+        }
+    }
+}
+
+// ------------------------------------------------------------- host side
+typedef unsigned __int128 u128;
+
+int inv_mod(int a, int m) {  // a^(-1) mod m, gcd(a, m) = 1
+    int t = 0, nt = 1, r = m, nr = a % m;
+    while (nr != 0) {
+        const int q = r / nr;
+        int tmp = t - q * nt;
+        t = nt;
+        nt = tmp;
+        tmp = r - q * nr;
+        r = nr;
+        nr = tmp;
+    }
+    return t < 0 ? t + m : t;
+}
+
+CrtConsts make_consts(int L, int bits) {
+    CrtConsts cc{};
+    cc.L = L;
+    cc.bits = bits;
+    u128 M = 1;
+    for (int i = 0; i < L; ++i) M *= (u128)kModuli[i];
+    const u128 mask = ((u128)1 << 40) - 1;
+    for (int i = 0; i < L; ++i) {
+        const int mi = kModuli[i];
+        cc.m[i] = mi;
+        cc.inv_m[i] = 1.0 / mi;
+        const u128 Mi = M / (u128)mi;
+        const int yi = inv_mod((int)(Mi % (u128)mi), mi);
+        const u128 w = Mi * (u128)yi;  // < M
+        cc.w[i][0] = (double)(uint64_t)(w & mask);
+        cc.w[i][1] = (double)(uint64_t)((w >> 40) & mask);
+        cc.w[i][2] = (double)(uint64_t)(w >> 80);
+    }
+    cc.Mp[0] = (double)(uint64_t)(M & mask);
+    cc.Mp[1] = (double)(uint64_t)((M >> 40) & mask);
+    cc.Mp[2] = (double)(uint64_t)(M >> 80);
+    cc.Md = (double)M;
+    return cc;
+}
+
+}  // namespace
+
+double crt_modulus_bits(int L) {
+    double b = 0.0;
+    for (int i = 0; i < L && i < kMaxMod; ++i) b += log2((double)kModuli[i]);
+    return b;
+}
+
+int crt_max_moduli() { return kMaxMod; }
+
+hipError_t launch_crt_split(const double *Z, int rows, int cols, int64_t ld, int axis,
+                            const unsigned long long *maxbits, int L, int bits, int8_t *out,
+                            int lines_pad, int len_pad, int *exps, hipStream_t s) {
+    const CrtConsts cc = make_consts(L, bits);
+    if (axis == 0) {
+        const int64_t threads = (int64_t)lines_pad * (len_pad / 16);
+        crt_rows_kernel<<<(unsigned)((threads + kThreads - 1) / kThreads), kThreads, 0, s>>>(
+            Z, rows, cols, ld, maxbits, cc, out, lines_pad, len_pad, exps);
+    } else {
+        dim3 grid((unsigned)(len_pad / 64), (unsigned)(lines_pad / 64));
+        crt_cols_kernel<<<grid, kThreads, 0, s>>>(Z, rows, cols, ld, maxbits, cc, out, lines_pad,
+                                                  len_pad, exps);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_crt(int m, int n, int k, int L, int bits, const int8_t *xs, int x_lines_pad,
+                           const int8_t *ys, int y_lines_pad, int len_pad, int8_t *res,
+                           const int *ex, const int *ey, double *C, int64_t ldc, int accumulate,
+                           hipStream_t s) {
+    if (m == 0 || n == 0) return hipSuccess;
+    if (x_lines_pad % CrtCfg::BM || y_lines_pad % CrtCfg::BN || len_pad % 64 || len_pad < k ||
+        x_lines_pad < m || y_lines_pad < n || L < 1 || L > kMaxMod)
+        return hipErrorInvalidValue;
+    const CrtConsts cc = make_consts(L, bits);
+    const int nblk = len_pad / 32;
+    const int tiles_m = (m + CrtCfg::BM - 1) / CrtCfg::BM, tiles_n = (n + CrtCfg::BN - 1) / CrtCfg::BN;
+    const int64_t wgs = (int64_t)tiles_m * tiles_n * L;
+    using G = CrtCfg;
+    gemm_crt_kernel<G><<<(unsigned)wgs, G::threads, 0, s>>>(
+        m, n, nblk, tiles_m, tiles_n, xs, x_lines_pad, ys, y_lines_pad,
+        (int64_t)x_lines_pad * len_pad, (int64_t)y_lines_pad * len_pad, cc, res);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 grid((unsigned)m, (unsigned)((n + 4 * kThreads - 1) / (4 * kThreads)));
+    crt_reconstruct_kernel<<<grid, kThreads, 0, s>>>(m, n, res, cc, ex, ey, C, ldc, accumulate);
+    return hipGetLastError();
+}
+
+}  // namespace tcu

@@ -96,4 +96,18 @@ hipError_t run_gemm_f64_host(int m, int n, int k, const double *A, int64_t lda, 
                              int64_t ldb, double *C, int64_t ldc, void *dev_buf,
                              size_t dev_bytes, int64_t block, hipStream_t s);
 
+// crt.hip: the CRT form.  Residues of each line's `bits`-bit truncation
+// modulo the first L moduli, int8, in the slice layout with lines_pad a
+// multiple of 256; the GEMM writes per-modulus residues of the product into
+// res (L x m x n int8) and reconstructs C (m x n, ldc) from them.
+double crt_modulus_bits(int L);
+int crt_max_moduli();
+hipError_t launch_crt_split(const double *Z, int rows, int cols, int64_t ld, int axis,
+                            const unsigned long long *maxbits, int L, int bits, int8_t *out,
+                            int lines_pad, int len_pad, int *exps, hipStream_t s);
+hipError_t launch_gemm_crt(int m, int n, int k, int L, int bits, const int8_t *xs, int x_lines_pad,
+                           const int8_t *ys, int y_lines_pad, int len_pad, int8_t *res,
+                           const int *ex, const int *ey, double *C, int64_t ldc, int accumulate,
+                           hipStream_t s);
+
 }  // namespace tcu

@@ -20,7 +20,7 @@ from . import _lib
 from ._lib import TcuError, check
 
 PRECISIONS = {"fp64": _lib.TCU_PREC_FP64, "split_bf16": _lib.TCU_PREC_SPLIT_BF16,
-              "split_i8": _lib.TCU_PREC_SPLIT_I8}
+              "split_i8": _lib.TCU_PREC_SPLIT_I8, "crt_i8": _lib.TCU_PREC_CRT_I8}
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -87,6 +87,16 @@ def split_slices(precision: str, k: int, tol: float) -> int:
     if S < 0:
         raise TcuError(S, "tcu_split_slices")
     return S
+
+
+def crt_plan(k: int, tol: float):
+    """The CRT form's plan for a contraction of length k: (number of moduli,
+    truncation bits); raises TcuError (TCU_ERR_INFEASIBLE) when none meets tol."""
+    bits = C.c_int32(0)
+    L = _lib.load().tcu_crt_plan(int(k), float(tol), C.byref(bits))
+    if L < 0:
+        raise TcuError(L, "tcu_crt_plan")
+    return L, bits.value
 
 
 def _pad(x: int, m: int) -> int:

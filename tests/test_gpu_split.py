@@ -17,6 +17,7 @@ from .gpu_util import abs_rel, cuda_or_skip, err_cw, to_orc
 pytestmark = pytest.mark.gpu
 
 FORMS = ["split_i8", "split_bf16"]
+ALL_FORMS = FORMS + ["crt_i8"]   # the digit forms and the CRT form
 
 
 def special_matrix(R, L, seed, kind="uniform"):
@@ -77,7 +78,7 @@ def bound_check(orc, A, B, M, K, N, Cg, tol):
     return err_cw(Cg, Co, S)
 
 
-@pytest.mark.parametrize("precision", FORMS)
+@pytest.mark.parametrize("precision", ALL_FORMS)
 @pytest.mark.parametrize("tol", [1e-6, 1e-9, 1e-12])
 @pytest.mark.parametrize("seed,nA,nB,M,K,N,kind", [
     (50, 40_000, 50_000, 200, 129, 257, "uniform"),
@@ -95,7 +96,7 @@ def test_split_forward_within_bound(orc, precision, tol, seed, nA, nB, M, K, N, 
     bound_check(orc, A, B, M, K, N, Cg.cpu().numpy(), tol)
 
 
-@pytest.mark.parametrize("precision", FORMS)
+@pytest.mark.parametrize("precision", ALL_FORMS)
 def test_split_dense_workload_2pow20(orc, precision):
     """2^20 records per table, U[-1,1): bound on sampled cells, and the
     measured componentwise error against |X||Y| stays far below 1e-12."""
@@ -109,7 +110,7 @@ def test_split_dense_workload_2pow20(orc, precision):
     assert sampled_checks(orc, A, B, Cg, N, N, N, seed=5, ncells=2048) <= 1e-12
 
 
-@pytest.mark.parametrize("precision", FORMS)
+@pytest.mark.parametrize("precision", ALL_FORMS)
 @pytest.mark.parametrize("lo,hi", [(0, 2), (-2**15, 2**15)])
 def test_split_integer_values_exact(orc, precision, lo, hi):
     """Integer inputs below 2^15 need at most 3 digits; with 7 slices every
@@ -139,7 +140,7 @@ def test_split_i8_long_contraction_chunks(orc):
     bound_check(orc, A, B, M, K, N, Cg.cpu().numpy(), 1e-12)
 
 
-@pytest.mark.parametrize("precision", FORMS)
+@pytest.mark.parametrize("precision", ALL_FORMS)
 def test_split_infeasible_tolerance(precision):
     dev = cuda_or_skip()
     A = wl.random_relation(100, 10, 10, 54, 1, device=dev)
@@ -150,7 +151,7 @@ def test_split_infeasible_tolerance(precision):
     assert ei.value.status == ops._lib.TCU_ERR_INFEASIBLE
 
 
-@pytest.mark.parametrize("precision", FORMS)
+@pytest.mark.parametrize("precision", ALL_FORMS)
 def test_split_non_finite_reported(precision):
     dev = cuda_or_skip()
     A = wl.random_relation(2000, 30, 20, 55, 1, device=dev)
@@ -161,7 +162,7 @@ def test_split_non_finite_reported(precision):
     assert ops.sync_status(ws)[0] == ops._lib.TCU_ERR_NONFINITE
 
 
-@pytest.mark.parametrize("precision", FORMS)
+@pytest.mark.parametrize("precision", ALL_FORMS)
 def test_split_adjoint_within_bound(orc, precision):
     """Both adjoint products carry the same guarantee with their contraction
     lengths: |dA - dA*| <= tol * N * max|W[g,:]| * max|Y[k,:]| and

@@ -8,6 +8,7 @@ the difference quotient has no truncation error).
 Slicing (the mixed-precision form's number format): checked against an exact
 integer re-derivation in Python and against the reconstruction identity.
 """
+import math
 from fractions import Fraction
 
 import numpy as np
@@ -158,3 +159,50 @@ def test_split_rejects_non_finite(orc):
     X[1, 2] = np.inf
     with pytest.raises(FloatingPointError):
         orc.split(X, 0, 3, 8)
+
+
+def _trunc_product_exact(X, Y, bits):
+    """The same definition in Python integers (independent arithmetic)."""
+    M, K = X.shape
+    N = Y.shape[1]
+    ex = [math.frexp(max(abs(v) for v in X[g]))[1] if any(X[g]) else 0 for g in range(M)]
+    ey = [math.frexp(max(abs(Y[k, h]) for k in range(K)))[1] if any(Y[:, h]) else 0
+          for h in range(N)]
+    xi = [[int(math.ldexp(X[g, k], bits - ex[g])) for k in range(K)] for g in range(M)]
+    yi = [[int(math.ldexp(Y[k, h], bits - ey[h])) for h in range(N)] for k in range(K)]
+    out = np.empty((M, N))
+    for g in range(M):
+        for h in range(N):
+            p = sum(xi[g][k] * yi[k][h] for k in range(K))
+            out[g, h] = math.ldexp(float(p), ex[g] + ey[h] - 2 * bits)
+    return out
+
+
+@pytest.mark.parametrize("bits", [7, 30, 42, 53])
+def test_trunc_product_matches_python_integers(orc, bits):
+    rng = np.random.default_rng(bits)
+    X = rng.standard_normal((6, 9)) * np.exp(rng.uniform(-8, 8, (6, 9)))
+    Y = rng.standard_normal((9, 5)) * np.exp(rng.uniform(-8, 8, (9, 5)))
+    X[2] = 0.0           # an all-zero line
+    Y[:, 1] *= 1e-300    # a line of subnormal-range magnitudes
+    got = orc.trunc_product(X, Y, bits)
+    assert np.array_equal(got, _trunc_product_exact(X, Y, bits))
+
+
+def test_trunc_product_error_bound_and_integers(orc):
+    """|X'Y' scaled - XY| <= K max|X_g| max|Y_h| (2^(2-b) + 2^(2-2b)) against the
+    exact rational product; integer inputs below 2^bits come back exact."""
+    rng = np.random.default_rng(7)
+    X = rng.uniform(-1, 1, (8, 12)) * 10.0 ** rng.uniform(-4, 4, (8, 12))
+    Y = rng.uniform(-1, 1, (12, 6)) * 10.0 ** rng.uniform(-4, 4, (12, 6))
+    for bits in (10, 20, 42):
+        got = orc.trunc_product(X, Y, bits)
+        for g in range(8):
+            for h in range(6):
+                exact = sum(Fraction(X[g, k]) * Fraction(Y[k, h]) for k in range(12))
+                bound = 12 * np.abs(X[g]).max() * np.abs(Y[:, h]).max() * (
+                    2.0 ** (2 - bits) + 2.0 ** (2 - 2 * bits))
+                assert abs(Fraction(got[g, h]) - exact) <= Fraction(bound)
+    Xi = rng.integers(-1000, 1000, (7, 11)).astype(np.float64)
+    Yi = rng.integers(-1000, 1000, (11, 4)).astype(np.float64)
+    assert np.array_equal(orc.trunc_product(Xi, Yi, 42), Xi @ Yi)
