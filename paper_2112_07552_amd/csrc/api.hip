@@ -88,17 +88,22 @@ Layout plan_layout(int32_t M, int32_t K, int32_t N, tcu_precision p, int flags) 
         const size_t digit = p == TCU_PREC_SPLIT_BF16 ? 2 : 1;
         const size_t planes = is_crt(p) ? TCU_MAX_MODULI : TCU_MAX_SLICES;
         auto padl = [&](int64_t x) { return is_crt(p) ? pad256(x) : pad128(x); };
+        auto padk = [&](int64_t x) {
+            const int64_t a = is_crt(p) ? crt_len_align() : 64;
+            return (size_t)((x + a - 1) / a * a);
+        };
         // (lines, length) of each operand: forward X (M, K) and Y (N, K);
         // backward W (M, N) and Y^T (K, N) for dX, X^T (K, M) and W (N, M) for dY
         size_t la = padl(M), lb = padl(N);
-        size_t za = padl(M) * pad64(K), zb = padl(N) * pad64(K);
-        size_t out = (size_t)M * N;  // CRT: per-modulus residues of each product
+        size_t za = padl(M) * padk(K), zb = padl(N) * padk(K);
+        // CRT: per-modulus residues of each product (m x n, rows padded to 32)
+        size_t out = (size_t)crt_residue_plane(M, N);
         if (bwd) {
             la = maxz(la, padl(K));
             lb = maxz(lb, padl(K));
-            za = maxz(za, maxz(padl(M) * pad64(N), padl(K) * pad64(M)));
-            zb = maxz(zb, maxz(padl(K) * pad64(N), padl(N) * pad64(M)));
-            out = maxz(out, maxz((size_t)M * K, (size_t)K * N));
+            za = maxz(za, maxz(padl(M) * padk(N), padl(K) * padk(M)));
+            zb = maxz(zb, maxz(padl(K) * padk(N), padl(N) * padk(M)));
+            out = maxz(out, maxz((size_t)crt_residue_plane(M, K), (size_t)crt_residue_plane(K, N)));
         }
         L.mba = off; off += align_up(la * 8);
         L.mbb = off; off += align_up(lb * 8);
@@ -155,7 +160,7 @@ hipError_t split_product(const SplitOperand &a, const SplitOperand &b, int m, in
         int32_t bits = 0;
         const int nmod = crt_plan(k, tol, &bits);
         if (nmod != S) return hipErrorInvalidValue;  // the caller planned with the same k, tol
-        const int len_pad = (int)pad64(k);
+        const int len_pad = (k + crt_len_align() - 1) / crt_len_align() * crt_len_align();
         const int la = (int)pad256(m), lb = (int)pad256(n);
         auto *mba = at<unsigned long long>(ws, L.mba);
         auto *mbb = at<unsigned long long>(ws, L.mbb);

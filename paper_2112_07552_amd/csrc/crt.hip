@@ -45,6 +45,8 @@ constexpr int kModuli[kMaxMod] = {256, 255, 253, 251, 247, 241, 239, 233,
 struct CrtConsts {
     int L, bits;
     double m[kMaxMod], inv_m[kMaxMod];
+    int mi[kMaxMod], c16[kMaxMod];  // m_i and 2^16 mod m_i
+    float inv_f[kMaxMod];           // 1 / m_i rounded to float
     double w[kMaxMod][3];  // w_i = w2 2^80 + w1 2^40 + w0
     double Mp[3];          // M in the same limbs
     double Md;             // M rounded to double
@@ -57,6 +59,22 @@ __device__ inline double sym_mod(double x, double m, double inv_m) {
     const double hi = floor((m - 1.0) * 0.5), lo = -floor(m * 0.5);
     if (r > hi) r -= m;
     if (r < lo) r += m;
+    return r;
+}
+
+// The same residue of any int32 x.  r1 = (x >> 16)(2^16 mod m) + (x & 0xffff)
+// is congruent to x and |r1| < 2^24, so it converts to float exactly; the
+// float quotient is within 0.006 of r1 / m, so r1 - m rint(r1 / m) lies in
+// [-m/2 - 2, m/2 + 2] and one correction each way lands in the symmetric
+// range.  Every product fits the 24-bit multiplier.  (Checked exhaustively
+// over all int32 x for each modulus.)
+__device__ inline int sym_mod32(int x, int m, int c16, float inv) {
+    const int r1 = __mul24(x >> 16, c16) + (x & 0xffff);
+    const int q = (int)rintf((float)r1 * inv);
+    int r = r1 - __mul24(q, m);
+    const int hi = (m - 1) >> 1, lo = -(m >> 1);
+    r = r > hi ? r - m : r;
+    r = r < lo ? r + m : r;
     return r;
 }
 
@@ -167,9 +185,9 @@ crt_cols_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
 }
 
 // ---------------------------------------------------------------- the GEMM
-// Tile configuration: a workgroup computes GBM x BN outputs with NW waves in
-// a 2 x (NW / 2) grid (each wave 128 rows by BN / (NW / 2) columns, i.e. WA =
-// 4 by WB blocks of 32 x 32) and keeps NS stages of two k-steps in LDS.
+// Tile configuration: a workgroup computes BM x BN outputs with NW waves in a
+// 2 x (NW / 2) grid (each wave 128 rows by BN / (NW / 2) columns, i.e. WA = 4
+// by WB blocks of 32 x 32) and keeps NS stages of two k-steps in LDS.
 template <int BN_, int NW_, int NS_, int WPE_>
 struct Cfg {
     static constexpr int BM = 256, BN = BN_, NW = NW_, NS = NS_, WPE = WPE_;
@@ -187,7 +205,10 @@ struct Cfg {
 #define CRT_CFG Cfg<256, 8, 4, 2>
 #endif
 using CrtCfg = CRT_CFG;
-constexpr int NUM_XCD = 8, GROUP_M = 4;
+constexpr int NUM_XCD = 8, GROUP_M = 4, RUN = 32;
+// k-steps of 32 per unrolled round of the main loop: the contraction length
+// of the residue planes is padded to a multiple of this
+constexpr int kCrtLenAlign = 64 * CrtCfg::NS;
 
 template <int V>
 __device__ inline void wait_vm() {
@@ -196,34 +217,70 @@ __device__ inline void wait_vm() {
 }
 __device__ inline void barrier_nf() { asm volatile("s_barrier" ::: "memory"); }
 
-typedef __attribute__((address_space(3))) void lds_void;
-typedef __attribute__((address_space(1))) const void global_cvoid;
+// While the matrix cores are kept busy, vector-ALU instructions of every wave
+// on the SIMD get few issue slots (measured on gfx950: a load whose address
+// takes one VALU instruction issued at about a third of its rate beside a
+// stream of int8 MFMAs).  The main loop therefore holds no VALU work: each
+// load is a direct-to-LDS load whose address is a uniform SGPR base plus the
+// lane's fixed byte offset (the SADDR form), with its LDS address in M0,
+// both from scalar arithmetic.
+__device__ inline void load_lds16(const int8_t *sbase, unsigned voff, unsigned lds_addr) {
+    asm volatile("global_load_lds_dwordx4 %0, %1" : : "v"(voff), "s"(sbase), "{m0}"(lds_addr)
+                 : "memory");
+}
 
-// stage st (k-steps 2 st, 2 st + 1) of modulus plane sets xi, yi into buf:
-// LDS chunk of (k-step s, half h, line l) is s KS + h BM + l for X and
-// s KS + 2 BM + h BN + l for Y
+// A uniform value computed on the vector ALU (64-bit products are) moved to
+// scalar registers, so that arithmetic on it stays scalar.
+__device__ inline const int8_t *to_sgpr(const int8_t *p) {
+    const uint64_t u = (uint64_t)(uintptr_t)p;
+    // the builtin returns int: widen through uint32_t (zero-extend), or the
+    // low word's bit 31 would spill into the high word
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((unsigned)u);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+    const uint64_t s = lo | (hi << 32);
+    return (const int8_t *)(uintptr_t)s;
+}
+
+// The wave's share of one stage's loads: chunk j of the stage is 1 KB (64
+// lines x 16 bytes) of operand plane (k-step s, half h) at line block lb.
+// Everything here is uniform.
 template <typename G>
-__device__ inline void issue(i4 *buf, int st, const int8_t *xi, int xlp, int m0, const int8_t *yi,
-                             int ylp, int n0, int wave, int lane) {
+struct StageLoads {
+    const int8_t *src[G::PER_WAVE];  // address of the chunk in stage 0
+    int64_t step[G::PER_WAVE];       // bytes from one stage to the next
+    unsigned dst[G::PER_WAVE];       // byte offset inside a stage buffer
+};
+
+template <typename G>
+__device__ inline StageLoads<G> stage_loads(int wave, const int8_t *xi, int xlp, int m0,
+                                            const int8_t *yi, int ylp, int n0) {
+    StageLoads<G> L;
 #pragma unroll
     for (int j = 0; j < G::PER_WAVE; ++j) {
         const int q = wave + G::NW * j;
         const int s = q / (G::PX + G::PY), r = q % (G::PX + G::PY);
-        const int kb = 2 * st + s;
-        const int8_t *src;
-        int dst;
         if (r < G::PX) {
             const int h = r / (G::BM / 64), lb = r % (G::BM / 64);
-            src = xi + ((((int64_t)kb * 2 + h) * xlp) + m0 + lb * 64 + lane) * 16;
-            dst = s * G::KS + h * G::BM + lb * 64;
+            L.src[j] = xi + (((int64_t)s * 2 + h) * xlp + m0 + lb * 64) * 16;
+            L.step[j] = (int64_t)4 * xlp * 16;
+            L.dst[j] = (unsigned)(s * G::KS + h * G::BM + lb * 64) * 16u;
         } else {
             const int r2 = r - G::PX;
             const int h = r2 / (G::BN / 64), lb = r2 % (G::BN / 64);
-            src = yi + ((((int64_t)kb * 2 + h) * ylp) + n0 + lb * 64 + lane) * 16;
-            dst = s * G::KS + 2 * G::BM + h * G::BN + lb * 64;
+            L.src[j] = yi + (((int64_t)s * 2 + h) * ylp + n0 + lb * 64) * 16;
+            L.step[j] = (int64_t)4 * ylp * 16;
+            L.dst[j] = (unsigned)(s * G::KS + 2 * G::BM + h * G::BN + lb * 64) * 16u;
         }
-        __builtin_amdgcn_global_load_lds((global_cvoid *)src, (lds_void *)(buf + dst), 16, 0, 0);
+        L.src[j] = to_sgpr(L.src[j]);
     }
+    return L;
+}
+
+template <typename G>
+__device__ inline void issue(const StageLoads<G> &L, int st, unsigned buf_addr, unsigned voff) {
+#pragma unroll
+    for (int j = 0; j < G::PER_WAVE; ++j)
+        load_lds16(L.src[j] + (int64_t)st * L.step[j], voff, buf_addr + L.dst[j]);
 }
 
 template <int WA, int WB>
@@ -231,15 +288,14 @@ struct Frag {
     i4 a[WA], b[WB];
 };
 
-template <typename G>
-__device__ inline void read_frag(const i4 *buf, int s, int wm, int wn, int half, int l32,
-                                 Frag<G::WA, G::WB> &f) {
+// Fragments of k-step S of stage buffer B: fixed per-lane bases plus
+// compile-time offsets (the reads need no address arithmetic in the loop).
+template <typename G, int B, int S>
+__device__ inline void read_frag(const i4 *lds_a, const i4 *lds_b, Frag<G::WA, G::WB> &f) {
 #pragma unroll
-    for (int a = 0; a < G::WA; ++a)
-        f.a[a] = buf[s * G::KS + half * G::BM + wm * 32 * G::WA + a * 32 + l32];
+    for (int a = 0; a < G::WA; ++a) f.a[a] = lds_a[B * G::STAGE + S * G::KS + a * 32];
 #pragma unroll
-    for (int b = 0; b < G::WB; ++b)
-        f.b[b] = buf[s * G::KS + 2 * G::BM + half * G::BN + wn * 32 * G::WB + b * 32 + l32];
+    for (int b = 0; b < G::WB; ++b) f.b[b] = lds_b[B * G::STAGE + S * G::KS + b * 32];
 }
 
 // Half H of one k-step's products: row blocks [H WA / 2, (H + 1) WA / 2).
@@ -252,20 +308,75 @@ __device__ inline void mma_half(const Frag<WA, WB> &f, i16v (&acc)[WA][WB]) {
             acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a[a], f.b[b], acc[a][b], 0, 0, 0);
 }
 
+// One stage of the main loop, stage index st held in buffer B.  fc holds
+// the fragments of its first k-step.  The second k-step's fragments (fm) are
+// read between the two halves of the first k-step's MFMAs, the next stage's
+// first k-step (into fc) between the halves of the second's, so every LDS
+// read has half a k-step of matrix work to land.  Every stage issues one
+// stage of loads (the last ones repeat stage nst - 1 into buffers no wave
+// reads any more), so "stage st + 1 has landed" is always "at most NS - 3
+// later stages in flight".
+template <typename G, int B>
+__device__ inline void crt_stage(int st, int nst, const StageLoads<G> &L, unsigned lds_addr,
+                                 unsigned voff, const i4 *lds_a, const i4 *lds_b,
+                                 Frag<G::WA, G::WB> &fc, Frag<G::WA, G::WB> &fm,
+                                 i16v (&acc)[G::WA][G::WB]) {
+    constexpr int NS = G::NS, PW = G::PER_WAVE;
+    mma_half<0>(fc, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    read_frag<G, B, 1>(lds_a, lds_b, fm);
+    __builtin_amdgcn_sched_barrier(0);
+    mma_half<1>(fc, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    wait_vm<(NS - 3) * PW>();
+    barrier_nf();
+    const int ist = st + NS - 1 < nst ? st + NS - 1 : nst - 1;
+    issue<G>(L, ist, lds_addr + (unsigned)((B + NS - 1) % NS) * G::STAGE * 16u, voff);
+    __builtin_amdgcn_sched_barrier(0);
+    mma_half<0>(fm, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    read_frag<G, (B + 1) % NS, 0>(lds_a, lds_b, fc);
+    __builtin_amdgcn_sched_barrier(0);
+    mma_half<1>(fm, acc);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <typename G, int B>
+__device__ inline void crt_stages(int st, int nst, const StageLoads<G> &L, unsigned lds_addr,
+                                  unsigned voff, const i4 *lds_a, const i4 *lds_b,
+                                  Frag<G::WA, G::WB> &fc, Frag<G::WA, G::WB> &fm,
+                                  i16v (&acc)[G::WA][G::WB]) {
+    crt_stage<G, B>(st + B, nst, L, lds_addr, voff, lds_a, lds_b, fc, fm, acc);
+    if constexpr (B + 1 < G::NS)
+        crt_stages<G, B + 1>(st, nst, L, lds_addr, voff, lds_a, lds_b, fc, fm, acc);
+}
+
+// nblk (k-steps) must be a multiple of 2 NS.
 template <typename G>
 __global__ void __launch_bounds__(G::threads) __attribute__((amdgpu_waves_per_eu(G::WPE, G::WPE)))
 gemm_crt_kernel(int m, int n, int nblk, int tiles_m, int tiles_n, const int8_t *__restrict__ xs,
                 int xlp, const int8_t *__restrict__ ys, int ylp, int64_t plane_x,
-                int64_t plane_y, CrtConsts cc, int8_t *__restrict__ res) {
-    constexpr int WA = G::WA, WB = G::WB, PW = G::PER_WAVE, NS = G::NS, NW = G::NW;
-    __shared__ __attribute__((aligned(16))) i4 lds[NS][G::STAGE];
-    // workgroup -> (modulus, tile); tiles of one modulus are consecutive and
-    // grouped GROUP_M tile-rows deep, spread over the XCDs in contiguous runs
+                int64_t plane_y, CrtConsts cc, int8_t *__restrict__ res, int64_t plane_res) {
+    constexpr int WA = G::WA, WB = G::WB, PW = G::PER_WAVE, NS = G::NS;
+    __shared__ __attribute__((aligned(16))) i4 lds[NS * G::STAGE];
+    // workgroup -> (modulus, tile).  Tiles of one modulus are numbered in
+    // groups GROUP_M tile-rows deep.  Workgroups go to the XCDs round robin;
+    // when the count allows, the j-th workgroup of XCD x takes run
+    // (j / 32) * NUM_XCD + x of 32 consecutive tiles, so at any time the
+    // eight XCDs work on neighbouring runs of one modulus (each XCD's L2
+    // reuses its run's panels; their misses meet in the shared last-level
+    // cache); otherwise each XCD takes one contiguous share.
     const int tiles = tiles_m * tiles_n;
     const int total = tiles * cc.L;
     const int wg = blockIdx.x;
-    const int per = total / NUM_XCD;
-    const int logical = wg < per * NUM_XCD ? (wg % NUM_XCD) * per + wg / NUM_XCD : wg;
+    const int x = wg % NUM_XCD, j = wg / NUM_XCD;
+    int logical = wg;
+    if (total % (NUM_XCD * RUN) == 0) {
+        logical = ((j / RUN) * NUM_XCD + x) * RUN + j % RUN;
+    } else {
+        const int per = total / NUM_XCD;
+        if (wg < per * NUM_XCD) logical = x * per + j;
+    }
     const int mod = logical / tiles;
     const int t = logical % tiles;
     const int group = GROUP_M * tiles_n;
@@ -273,13 +384,17 @@ gemm_crt_kernel(int m, int n, int nblk, int tiles_m, int tiles_n, const int8_t *
     const int gm = min(tiles_m - first_m, GROUP_M);
     const int tm = first_m + (t % group) % gm, tn = (t % group) / gm;
     const int m0 = tm * G::BM, n0 = tn * G::BN;
-    const int8_t *xi = xs + (int64_t)mod * plane_x;
-    const int8_t *yi = ys + (int64_t)mod * plane_y;
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int wm = wave & 1, wn = wave >> 1;
     const int l32 = lane & 31, half = lane >> 5;
+    const unsigned voff = (unsigned)lane * 16u;
+    const unsigned lds_addr = (unsigned)(uintptr_t)lds;
+    const i4 *lds_a = lds + half * G::BM + wm * 32 * WA + l32;
+    const i4 *lds_b = lds + 2 * G::BM + half * G::BN + wn * 32 * WB + l32;
+    const StageLoads<G> L = stage_loads<G>(wave, xs + (int64_t)mod * plane_x, xlp, m0,
+                                           ys + (int64_t)mod * plane_y, ylp, n0);
 
     i16v acc[WA][WB];
 #pragma unroll
@@ -292,57 +407,42 @@ gemm_crt_kernel(int m, int n, int nblk, int tiles_m, int tiles_n, const int8_t *
     // there are fewer), fragments of k-step 0
 #pragma unroll
     for (int st = 0; st < NS - 1; ++st)
-        issue<G>(lds[st], st < nst ? st : nst - 1, xi, xlp, m0, yi, ylp, n0, wave, lane);
+        issue<G>(L, st < nst ? st : nst - 1, lds_addr + (unsigned)st * G::STAGE * 16u, voff);
     wait_vm<(NS - 2) * PW>();
     barrier_nf();
-
-    // One stage: fc holds the fragments of its first k-step.  The fragments
-    // of the second k-step (fm) are read between the two halves of the
-    // first k-step's MFMAs, and the next stage's first k-step (into fc)
-    // between the two halves of the second's, so every LDS read has half a
-    // k-step of matrix work to land before its use.  Every stage issues one
-    // stage of loads (the last ones repeat stage nst - 1 into buffers no
-    // wave reads any more), so "stage st + 1 has landed" is always "at most
-    // NS - 3 later stages in flight".
     Frag<WA, WB> fc, fm;
-    read_frag<G>(lds[0], 0, wm, wn, half, l32, fc);
-    for (int st = 0; st < nst; ++st) {
-        mma_half<0>(fc, acc);
-        __builtin_amdgcn_sched_barrier(0);
-        read_frag<G>(lds[st % NS], 1, wm, wn, half, l32, fm);
-        __builtin_amdgcn_sched_barrier(0);
-        mma_half<1>(fc, acc);
-        __builtin_amdgcn_sched_barrier(0);
-        wait_vm<(NS - 3) * PW>();
-        barrier_nf();
-        const int ist = st + NS - 1 < nst ? st + NS - 1 : nst - 1;
-        issue<G>(lds[(st + NS - 1) % NS], ist, xi, xlp, m0, yi, ylp, n0, wave, lane);
-        __builtin_amdgcn_sched_barrier(0);
-        mma_half<0>(fm, acc);
-        __builtin_amdgcn_sched_barrier(0);
-        read_frag<G>(lds[(st + 1) % NS], 0, wm, wn, half, l32, fc);
-        __builtin_amdgcn_sched_barrier(0);
-        mma_half<1>(fm, acc);
-        __builtin_amdgcn_sched_barrier(0);
-    }
+    read_frag<G, 0, 0>(lds_a, lds_b, fc);
+    for (int st = 0; st < nst; st += NS)
+        crt_stages<G, 0>(st, nst, L, lds_addr, voff, lds_a, lds_b, fc, fm, acc);
     wait_vm<0>();  // no load into LDS outlives the loop
 
-    // epilogue: residues of the int32 sums, int8, row-major per modulus
-    const double md = cc.m[mod], inv = cc.inv_m[mod];
-    int8_t *r = res + (int64_t)mod * m * n;
+    // epilogue: residues of the int32 sums as int8 in the accumulator's own
+    // order (see crt_reconstruct_kernel): one 16-byte store per 32 x 32 block
+    const int mi = cc.mi[mod], c16 = cc.c16[mod];
+    const float inv = cc.inv_f[mod];
+    int8_t *r = res + (int64_t)mod * plane_res;
 #pragma unroll
-    for (int a = 0; a < WA; ++a)
+    for (int a = 0; a < WA; ++a) {
+        const int rb = (m0 + wm * 32 * WA + a * 32) >> 5;
+        if (rb * 32 >= m) continue;
 #pragma unroll
         for (int b = 0; b < WB; ++b) {
             const int col = n0 + wn * 32 * WB + b * 32 + l32;
             if (col >= n) continue;
+            uint32_t w[4];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int row = m0 + wm * 32 * WA + a * 32 + 8 * (i >> 2) + 4 * half + (i & 3);
-                if (row < m)
-                    r[(int64_t)row * n + col] = (int8_t)(int)sym_mod((double)acc[a][b][i], md, inv);
+            for (int q = 0; q < 4; ++q) {
+                uint32_t v = 0;
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+                    v |= (uint32_t)(uint8_t)(int8_t)sym_mod32(acc[a][b][4 * q + jj], mi, c16, inv)
+                         << (8 * jj);
+                w[q] = v;
             }
+            *reinterpret_cast<uint4 *>(r + ((int64_t)rb * n + col) * 32 + 16 * half) =
+                make_uint4(w[0], w[1], w[2], w[3]);
         }
+    }
 }
 
 // --------------------------------------------------------- reconstruction
@@ -365,47 +465,42 @@ __device__ inline double crt_finish(double s0, double s1, double s2, const CrtCo
     return fma(p2, kLimb * kLimb, fma(p1, kLimb, p0));
 }
 
-// One thread per 4 consecutive outputs of one row (blockIdx.x = row): the
-// residue reads are 4-byte loads, contiguous across the wave.
+// Residue layout: res[i][row / 32][col][p], p = 16 ((row % 8) / 4) + 4 ((row %
+// 32) / 8) + row % 4 -- the order in which one lane of the int8 MFMA holds a
+// column of its 32 x 32 block.  A thread takes 8 bytes (8 rows of one column:
+// rows 32 rb + 8 j + 4 h + (0..3) for j = 2 (q % 2) + (0, 1), h = q / 2) from
+// each modulus plane; a wave reads 512 contiguous bytes per modulus.
 __global__ void __launch_bounds__(kThreads)
-crt_reconstruct_kernel(int m, int n, const int8_t *__restrict__ res, CrtConsts cc,
+crt_reconstruct_kernel(int m, int n, const int8_t *__restrict__ res, int64_t plane, CrtConsts cc,
                        const int *__restrict__ ex, const int *__restrict__ ey,
                        double *__restrict__ C, int64_t ldc, int accumulate) {
-    const int row = blockIdx.x;
-    const int col0 = (blockIdx.y * kThreads + threadIdx.x) * 4;
-    if (col0 >= n) return;
-    const int64_t mn = (int64_t)m * n;
-    const int64_t base = (int64_t)row * n + col0;
-    const bool whole = col0 + 4 <= n && (base & 3) == 0;
-    double s[4][3];
+    const int col = blockIdx.x * (kThreads / 4) + (threadIdx.x >> 2);
+    const int q = threadIdx.x & 3;
+    const int rb = blockIdx.y;
+    if (col >= n) return;
+    const int8_t *base = res + ((int64_t)rb * n + col) * 32 + 8 * q;
+    double s[8][3];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) s[j][0] = s[j][1] = s[j][2] = 0.0;
+    for (int j = 0; j < 8; ++j) s[j][0] = s[j][1] = s[j][2] = 0.0;
 #pragma unroll
     for (int i = 0; i < kMaxMod; ++i) {
         if (i >= cc.L) break;
-        const int8_t *p = res + (int64_t)i * mn + base;
-        uint32_t v = 0;
-        if (whole) {
-            v = *reinterpret_cast<const uint32_t *>(p);
-        } else {
+        const uint2 v = *reinterpret_cast<const uint2 *>(base + (int64_t)i * plane);
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (col0 + j < n) v |= (uint32_t)(uint8_t)p[j] << (8 * j);
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const double r = (double)(int8_t)(v >> (8 * j));
+        for (int j = 0; j < 8; ++j) {
+            const double r = (double)(int8_t)((j < 4 ? v.x : v.y) >> (8 * (j & 3)));
             s[j][0] = fma(r, cc.w[i][0], s[j][0]);  // exact: |r w| < 2^47, sums < 2^51
             s[j][1] = fma(r, cc.w[i][1], s[j][1]);
             s[j][2] = fma(r, cc.w[i][2], s[j][2]);
         }
     }
-    const int er = ex[row] - 2 * cc.bits;
+    const int ec = ey[col] - 2 * cc.bits;
+    const int row0 = 32 * rb + 16 * (q & 1) + 4 * (q >> 1);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int col = col0 + j;
-        if (col < n) {
-            const double v = ldexp(crt_finish(s[j][0], s[j][1], s[j][2], cc), er + ey[col]);
+    for (int j = 0; j < 8; ++j) {
+        const int row = row0 + 8 * (j >> 2) + (j & 3);
+        if (row < m) {
+            const double v = ldexp(crt_finish(s[j][0], s[j][1], s[j][2], cc), ex[row] + ec);
             double *dst = C + (int64_t)row * ldc + col;
             *dst = accumulate ? *dst + v : v;
         }
@@ -440,6 +535,9 @@ CrtConsts make_consts(int L, int bits) {
         const int mi = kModuli[i];
         cc.m[i] = mi;
         cc.inv_m[i] = 1.0 / mi;
+        cc.mi[i] = mi;
+        cc.c16[i] = 65536 % mi;
+        cc.inv_f[i] = (float)(1.0 / mi);
         const u128 Mi = M / (u128)mi;
         const int yi = inv_mod((int)(Mi % (u128)mi), mi);
         const u128 w = Mi * (u128)yi;  // < M
@@ -464,6 +562,10 @@ double crt_modulus_bits(int L) {
 
 int crt_max_moduli() { return kMaxMod; }
 
+int64_t crt_residue_plane(int64_t m, int64_t n) { return (m + 31) / 32 * 32 * n; }
+
+int crt_len_align() { return kCrtLenAlign; }
+
 hipError_t launch_crt_split(const double *Z, int rows, int cols, int64_t ld, int axis,
                             const unsigned long long *maxbits, int L, int bits, int8_t *out,
                             int lines_pad, int len_pad, int *exps, hipStream_t s) {
@@ -485,21 +587,23 @@ hipError_t launch_gemm_crt(int m, int n, int k, int L, int bits, const int8_t *x
                            const int *ex, const int *ey, double *C, int64_t ldc, int accumulate,
                            hipStream_t s) {
     if (m == 0 || n == 0) return hipSuccess;
-    if (x_lines_pad % CrtCfg::BM || y_lines_pad % CrtCfg::BN || len_pad % 64 || len_pad < k ||
+    if (x_lines_pad % CrtCfg::BM || y_lines_pad % CrtCfg::BN || len_pad % kCrtLenAlign || len_pad < k ||
         x_lines_pad < m || y_lines_pad < n || L < 1 || L > kMaxMod)
         return hipErrorInvalidValue;
     const CrtConsts cc = make_consts(L, bits);
     const int nblk = len_pad / 32;
     const int tiles_m = (m + CrtCfg::BM - 1) / CrtCfg::BM, tiles_n = (n + CrtCfg::BN - 1) / CrtCfg::BN;
     const int64_t wgs = (int64_t)tiles_m * tiles_n * L;
+    const int64_t plane_res = crt_residue_plane(m, n);
     using G = CrtCfg;
     gemm_crt_kernel<G><<<(unsigned)wgs, G::threads, 0, s>>>(
         m, n, nblk, tiles_m, tiles_n, xs, x_lines_pad, ys, y_lines_pad,
-        (int64_t)x_lines_pad * len_pad, (int64_t)y_lines_pad * len_pad, cc, res);
+        (int64_t)x_lines_pad * len_pad, (int64_t)y_lines_pad * len_pad, cc, res, plane_res);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const dim3 grid((unsigned)m, (unsigned)((n + 4 * kThreads - 1) / (4 * kThreads)));
-    crt_reconstruct_kernel<<<grid, kThreads, 0, s>>>(m, n, res, cc, ex, ey, C, ldc, accumulate);
+    const dim3 grid((unsigned)((n + kThreads / 4 - 1) / (kThreads / 4)), (unsigned)((m + 31) / 32));
+    crt_reconstruct_kernel<<<grid, kThreads, 0, s>>>(m, n, res, plane_res, cc, ex, ey, C, ldc,
+                                                     accumulate);
     return hipGetLastError();
 }
 

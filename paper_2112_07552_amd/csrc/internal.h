@@ -99,9 +99,12 @@ hipError_t run_gemm_f64_host(int m, int n, int k, const double *A, int64_t lda, 
 // crt.hip: the CRT form.  Residues of each line's `bits`-bit truncation
 // modulo the first L moduli, int8, in the slice layout with lines_pad a
 // multiple of 256; the GEMM writes per-modulus residues of the product into
-// res (L x m x n int8) and reconstructs C (m x n, ldc) from them.
+// res (L planes of crt_residue_plane(m, n) int8) and reconstructs C (m x n,
+// ldc) from them.
 double crt_modulus_bits(int L);
 int crt_max_moduli();
+int64_t crt_residue_plane(int64_t m, int64_t n);
+int crt_len_align();  // the residue planes' length is a multiple of this
 hipError_t launch_crt_split(const double *Z, int rows, int cols, int64_t ld, int axis,
                             const unsigned long long *maxbits, int L, int bits, int8_t *out,
                             int lines_pad, int len_pad, int *exps, hipStream_t s);
