@@ -2,7 +2,7 @@
 counter passes (rocprofv3 --pmc ... -- python3 -m paper_2112_07552_amd.kernel_driver W N R).
 
 W: nn, nt, tn or tt runs tcu_gemm_f64 on N x N operands (uniform [-1, 1));
-   fp64, split_i8 or split_bf16 runs the forward operator on the MM-query
+   fp64, split_i8, split_bf16 or crt_i8 runs the forward operator on the MM-query
    tables of N x N records with log-uniform values (seed 3), tol 1e-12.
 N: matrix edge (default 4096).  R: repetitions (default 3).
 """
