@@ -36,21 +36,32 @@ COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_gemm_f64_mm_query_4096.
 GEMM_SOURCE = os.path.join(ROOT, "paper_2112_07552_amd", "csrc", "gemm_f64.hip")
 
 
+def code_digest(path):
+    """SHA-256 of a C/HIP source with its comments, trailing blanks and empty
+    lines removed: it changes when the code does, not when a comment does."""
+    import hashlib
+    import re
+    text = open(path, encoding="utf-8").read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    lines = [ln.rstrip() for ln in text.splitlines()]
+    return hashlib.sha256("\n".join(ln for ln in lines if ln).encode()).hexdigest()
+
+
 def counter_traffic():
     """HBM bytes per NN launch from the committed counter summary, or None.
 
     The summary records FETCH_SIZE and WRITE_SIZE per dispatch, already
-    scaled by the plain-copy calibration, and the SHA-256 of the kernel
-    source they were taken with; a changed source makes the figure stale, so
-    it is not reported."""
-    import hashlib
+    scaled by the plain-copy calibration, and the code digest (code_digest)
+    of the kernel source they were taken with; changed code makes the figure
+    stale, so it is not reported."""
     import re
     try:
         text = open(COUNTERS_FILE).read()
-        src = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
+        src = code_digest(GEMM_SOURCE)
     except OSError:
         return None
-    m = re.search(r"traffic: nn_bytes=(\d+) source_sha256=([0-9a-f]{64})", text)
+    m = re.search(r"traffic: nn_bytes=(\d+) code_sha256=([0-9a-f]{64})", text)
     if not m or m.group(2) != src:
         return None
     return int(m.group(1))

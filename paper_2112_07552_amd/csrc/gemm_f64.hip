@@ -27,6 +27,9 @@
 //  * Tiles are numbered so that each of the 8 XCDs (workgroup w runs on XCD
 //    w mod 8) owns a contiguous run of tiles, grouped 8 tile-rows deep, so
 //    the A and B panels a run needs stay in that XCD's L2.
+//  * Whole-tile launches (the common case) run a main loop whose address
+//    arithmetic is all scalar (see the whole-tile path below): busy matrix
+//    cores leave vector-ALU instructions few issue slots.
 #include "internal.h"
 
 namespace tcu {
@@ -111,6 +114,104 @@ __device__ inline void read_frags(const double *__restrict__ L, int wbase, int t
     }
 }
 
+// ----- whole-tile path: no vector-ALU work in the main loop.  While the
+// matrix cores are busy, VALU instructions of every wave on the SIMD get few
+// issue slots, so the whole-tile loop keeps its address arithmetic scalar:
+// each panel load is a uniform SGPR base (advanced by scalar arithmetic) plus
+// the lane's fixed 32-bit byte offset, and the loop is unrolled over the two
+// LDS buffers so every LDS access is a fixed register plus an immediate.
+
+typedef __attribute__((address_space(1))) const char gchar;
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const d2v gd2v;
+
+// A uniform global address computed on the vector ALU moved to scalar
+// registers (kept in the global address space, so loads stay global loads).
+__device__ __forceinline__ gchar *to_sgpr(const double *p) {
+    const uint64_t u = (uint64_t)(uintptr_t)p;
+    // the builtin returns int: widen through uint32_t (zero-extend)
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((unsigned)u);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+    return (gchar *)(uintptr_t)(lo | (hi << 32));
+}
+
+// One operand's panel loads: stage kt's chunk i of this lane is at byte
+// base + kt * step + i * istep + off.  Chunk i of a thread is chunk 0 moved
+// by 32 tile rows (KC) or 4 k rows (!KC), a uniform stride, so one 32-bit
+// lane offset serves all four.
+struct Panel {
+    gchar *base;
+    int64_t step, istep;
+    unsigned off;
+};
+
+template <bool KC>
+__device__ __forceinline__ Panel make_panel(const double *P, int64_t ld, int o0) {
+    Panel q;
+    const unsigned tid = threadIdx.x;
+    q.base = to_sgpr(KC ? P + (int64_t)o0 * ld : P + o0);
+    q.step = KC ? (int64_t)BK * 8 : (int64_t)BK * ld * 8;
+    q.istep = KC ? (int64_t)(THREADS / 8) * ld * 8 : (int64_t)(THREADS / 64) * ld * 8;
+    // chunk 0: KC (o, kk) = (tid / 8, 2 (tid % 8)); !KC (kk, o) = (tid / 64, 2 (tid % 64))
+    const unsigned ldu = (unsigned)ld;
+    q.off = KC ? ((tid >> 3) * ldu + (tid & 7) * 2u) * 8u : ((tid >> 6) * ldu + (tid & 63) * 2u) * 8u;
+    return q;
+}
+
+__device__ __forceinline__ void load_panel(const Panel &q, int kt, double2 (&r)[4]) {
+    gchar *b = q.base + (int64_t)kt * q.step;
+    // Redefine the offset here so its zero extension is not hoisted out of
+    // the loop: the SGPR-base + 32-bit-offset load form needs to see it.
+    unsigned off = q.off;
+    asm volatile("" : "+v"(off));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        // a native vector load (a HIP double2 copied from the global address
+        // space would go through private memory)
+        gchar *bi = b + i * q.istep;
+        asm volatile("" : "+s"(bi));  // keep the chunk's base a scalar operand
+        const d2v v = *reinterpret_cast<gd2v *>(bi + off);
+        r[i].x = v.x;
+        r[i].y = v.y;
+    }
+}
+
+// One stage of the whole-tile loop reading LDS buffer CUR: loads of stage
+// kt + 1 (the last stage reloads itself into the idle buffer), 3 k-steps of
+// MFMAs, the loaded tiles stored to buffer CUR ^ 1, the last k-step, a
+// barrier.
+template <bool A_KC, bool B_KC, int CUR>
+__device__ __forceinline__ void full_stage(int kt, int nk, const Panel &pa, const Panel &pb,
+                                  double (*lds_a)[Tile<A_KC>::elems],
+                                  double (*lds_b)[Tile<B_KC>::elems], int wm, int wn,
+                                  d4 (&acc)[FM][FN]) {
+    double2 ra[4], rb[4];
+    const int knext = kt + 1 < nk ? kt + 1 : kt;
+    load_panel(pa, knext, ra);
+    load_panel(pb, knext, rb);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        // No wave reads buffer CUR ^ 1 during this stage (all passed the
+        // previous barrier), so the loaded tiles go there before the last
+        // k-step, whose MFMAs then cover the LDS writes.
+        if (t == 3) {
+            store_tile<A_KC>(lds_a[CUR ^ 1], ra);
+            store_tile<B_KC>(lds_b[CUR ^ 1], rb);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        double fa[FM], fb[FN];
+        read_frags<A_KC, FM>(lds_a[CUR], wm * WM, t, fa);
+        read_frags<B_KC, FN>(lds_b[CUR], wn * WN, t, fb);
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+            for (int b = 0; b < FN; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+}
+
 __device__ inline void tile_coords(int tiles_m, int tiles_n, int &tm, int &tn) {
     const int nt = tiles_m * tiles_n;
     const int wg = blockIdx.x;
@@ -142,7 +243,7 @@ gemm_f64_kernel(int m, int n, int k, const double *__restrict__ A, int64_t lda,
     tile_coords(tiles_m, tiles_n, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
 
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wm = wave & 1, wn = wave >> 1;
 
     d4 acc[FM][FN];
@@ -152,6 +253,22 @@ gemm_f64_kernel(int m, int n, int k, const double *__restrict__ A, int64_t lda,
         for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
     const int nk = (k + BK - 1) / BK;
+    if constexpr (FULL) {
+        const Panel pa = make_panel<A_KC>(A, lda, m0);
+        const Panel pb = make_panel<B_KC>(B, ldb, n0);
+        {
+            double2 ra[4], rb[4];
+            load_panel(pa, 0, ra);
+            load_panel(pb, 0, rb);
+            store_tile<A_KC>(lds_a[0], ra);
+            store_tile<B_KC>(lds_b[0], rb);
+        }
+        __syncthreads();
+        for (int kt = 0; kt < nk; kt += 2) {
+            full_stage<A_KC, B_KC, 0>(kt, nk, pa, pb, lds_a, lds_b, wm, wn, acc);
+            if (kt + 1 < nk) full_stage<A_KC, B_KC, 1>(kt + 1, nk, pa, pb, lds_a, lds_b, wm, wn, acc);
+        }
+    } else {
     double2 ra[4], rb[4];
     load_tile<A_KC, FULL>(A, lda, m0, 0, m, k, vec_a, ra);
     load_tile<B_KC, FULL>(B, ldb, n0, 0, n, k, vec_b, rb);
@@ -187,6 +304,7 @@ gemm_f64_kernel(int m, int n, int k, const double *__restrict__ A, int64_t lda,
         store_tile<B_KC>(lds_b[cur ^ 1], rb);
         __syncthreads();
     }
+    }
 
     const int lane = threadIdx.x & 63;
     const int j = lane >> 4, l16 = lane & 15;
@@ -213,7 +331,12 @@ hipError_t launch(int m, int n, int k, const double *A, int64_t lda, const doubl
     const int tiles = ((m + BM - 1) / BM) * ((n + BN - 1) / BN);
     const int vec_a = (lda % 2 == 0) && (((uintptr_t)A & 15) == 0);
     const int vec_b = (ldb % 2 == 0) && (((uintptr_t)B & 15) == 0);
-    const bool full = vec_a && vec_b && m % BM == 0 && n % BN == 0 && k % BK == 0 && k > 0;
+    // whole tiles, 16-byte loads, and every lane's byte offset inside a
+    // stage's panel below 2^32
+    const int64_t span_a = (A_KC ? (int64_t)BM * lda : (int64_t)BK * lda) * 8;
+    const int64_t span_b = (B_KC ? (int64_t)BN * ldb : (int64_t)BK * ldb) * 8;
+    const bool full = vec_a && vec_b && m % BM == 0 && n % BN == 0 && k % BK == 0 && k > 0 &&
+                      span_a < ((int64_t)1 << 32) && span_b < ((int64_t)1 << 32);
     if (full)
         gemm_f64_kernel<A_KC, B_KC, true><<<tiles, THREADS, 0, s>>>(m, n, k, A, lda, B, ldb, C,
                                                                     ldc, vec_a, vec_b, accumulate);
