@@ -391,9 +391,10 @@ def bench_ooc(stream, log, N=32768, dev_gb=24):
 def bench_large(stream, log, N=32768):
     """2^30 records per table (N = 32768, the paper's largest MM query), FP32
     values N(0,1) with 5% x1e3 outliers (seed 4).  One forward and one
-    forward + adjoint with checkpointing (the adjoint re-encodes) in the mixed
-    int8 form at tol = 1e-12 and in the FP64 form, each timed once after one
-    untimed run; errors on a 64 x 64 block of C against the oracle."""
+    forward + adjoint with checkpointing (the adjoint re-encodes) in the two
+    mixed int8 forms (digit slices, residues) at tol = 1e-12 and in the FP64
+    form, each timed once after one untimed run; errors on a 64 x 64 block of
+    C against the oracle."""
     import numpy as np
     import torch
     from oracle import oracle as orc
@@ -432,7 +433,7 @@ def bench_large(stream, log, N=32768):
                             orc.Rel(Bf.group, Bf.key, np.abs(Bf.val)), 64, N, 64)
     del ag, ak, av, bk, bh, bw, ga, hb
     tr, tc = torch.as_tensor(rows, device=dev), torch.as_tensor(cols, device=dev)
-    for precision in ("fp64", "split_i8"):
+    for precision in ("fp64", "split_i8", "crt_i8"):
         prec = ops.PRECISIONS[precision]
         ws = ops.alloc_workspace(ops.workspace_bytes(relA, relB, N, N, N, precision,
                                                      backward=True), dev)
@@ -459,14 +460,20 @@ def bench_large(stream, log, N=32768):
         err = float(np.max(np.abs(blk - Co) / So))
         log(f"large {precision}: fwd {t_fwd:.1f} ms, fwd+adj {t_step:.1f} ms, err {err:.2e}")
         out[precision] = {"ms_fwd": t_fwd, "ms_fwd_adjoint_checkpointed": t_step,
-                          "err_cw_block": err, "slices": info["slices"],
+                          "err_cw_block": err,
                           "fwd_elements_per_s": N * N / (t_fwd * 1e-3),
                           "fwd_adjoint_elements_per_s": N * N / (t_step * 1e-3)}
+        if precision == "crt_i8":
+            out[precision]["moduli"] = info["slices"]
+        elif precision != "fp64":
+            out[precision]["slices"] = info["slices"]
         del ws
         torch.cuda.empty_cache()
-    out["speedup_fwd"] = out["fp64"]["ms_fwd"] / out["split_i8"]["ms_fwd"]
-    out["speedup_fwd_adjoint"] = (out["fp64"]["ms_fwd_adjoint_checkpointed"] /
-                                  out["split_i8"]["ms_fwd_adjoint_checkpointed"])
+    for precision in ("split_i8", "crt_i8"):
+        out[precision]["speedup_fwd_vs_fp64"] = out["fp64"]["ms_fwd"] / out[precision]["ms_fwd"]
+        out[precision]["speedup_fwd_adjoint_vs_fp64"] = (
+            out["fp64"]["ms_fwd_adjoint_checkpointed"] /
+            out[precision]["ms_fwd_adjoint_checkpointed"])
     return out
 
 

@@ -1,8 +1,9 @@
 """The largest workload on one GPU: 2^30 records per table (N = 32768, the
 paper's largest matrix multiplication query, Section 5.4.1), FP32 values from
-N(0,1) with 5% of the values multiplied by 1e3 (seed 4).  The mixed int8 form
-runs forward plus adjoint with activation checkpointing (the adjoint rebuilds
-X and Y from the records); the FP64 form is the comparator.
+N(0,1) with 5% of the values multiplied by 1e3 (seed 4).  Both mixed int8
+forms (digit slices and residues) run forward plus adjoint with activation
+checkpointing (the adjoint rebuilds X and Y from the records); the FP64 form
+is the comparator.
 
 The oracle checks, all from the records:
   * a 64 x 64 block of C (relations filtered to the block's groups, which is
@@ -35,7 +36,7 @@ def remap(values, chosen, size):
     return lut[values]
 
 
-def test_mixed_form_2pow30_records_forward_adjoint_checkpointed(orc):
+def test_mixed_forms_2pow30_records_forward_adjoint_checkpointed(orc):
     dev = cuda_or_skip()
     free, total = torch.cuda.mem_get_info(dev)
     if free < 160 * 2**30:
@@ -45,18 +46,6 @@ def test_mixed_form_2pow30_records_forward_adjoint_checkpointed(orc):
     W = wl.draw_values("uniform", N * N, 1004, 0, device=dev).reshape(N, N)
     torch.cuda.synchronize()
 
-    log("split_i8 forward")
-    Cs, _, ws = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, N, N, N,
-                                 precision="split_i8", tol=TOL, unique=True)
-    st, info = ops.sync_status(ws)
-    assert st == 0 and info["slices"] == ops.split_slices("split_i8", N, TOL)
-    del ws
-    log("split_i8 adjoint, checkpointed")
-    dAs, dBs, ws = ops.join_agg_bwd(A.group, A.key, A.val, B.key, B.group, B.val, N, N, N, W,
-                                    precision="split_i8", tol=TOL, unique=True)
-    assert ops.sync_status(ws)[0] == 0
-    del ws
-    torch.cuda.empty_cache()
     log("fp64 forward")
     C64, _, ws = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, N, N, N,
                                   unique=True)
@@ -74,8 +63,9 @@ def test_mixed_form_2pow30_records_forward_adjoint_checkpointed(orc):
     rows = np.sort(rng.choice(N, 64, replace=False)).astype(np.int64)
     cols = np.sort(rng.choice(N, 64, replace=False)).astype(np.int64)
     keys = np.sort(rng.choice(N, 64, replace=False)).astype(np.int64)
+    trows, tcols = torch.as_tensor(rows, device=dev), torch.as_tensor(cols, device=dev)
 
-    # -- C on a 64 x 64 block ------------------------------------------------
+    # -- oracle: C on a 64 x 64 block -----------------------------------------
     log("oracle block of C")
     ga = remap(ag, rows, N)
     ma = ga >= 0
@@ -88,38 +78,40 @@ def test_mixed_form_2pow30_records_forward_adjoint_checkpointed(orc):
                             orc.Rel(Bf.group, Bf.key, np.abs(Bf.val)), 64, N, 64)
     mu = np.zeros(64); np.maximum.at(mu, Af.group, np.abs(Af.val))
     nu = np.zeros(64); np.maximum.at(nu, Bf.group, np.abs(Bf.val))
-    blk_s = Cs[torch.as_tensor(rows, device=dev)][:, torch.as_tensor(cols, device=dev)].cpu().numpy()
-    blk_64 = C64[torch.as_tensor(rows, device=dev)][:, torch.as_tensor(cols, device=dev)].cpu().numpy()
-    assert np.all(np.abs(blk_s - Co) <= TOL * N * np.outer(mu, nu))
-    err64 = float(np.max(np.abs(blk_64 - Co) / So))
-    errs = float(np.max(np.abs(blk_s - Co) / So))
-    log(f"block err_cw: fp64 {err64:.2e}, split_i8 {errs:.2e}")
-    assert err64 <= 1e-12 and errs <= 1e-12
 
-    # -- Freivalds on the whole of C ----------------------------------------
-    log("Freivalds")
+    # -- oracle: Freivalds right-hand sides ---------------------------------
+    log("oracle Freivalds")
     scale = orc.freivalds(orc.Rel(ag, ak, np.abs(av)), orc.Rel(bh, bk, np.abs(bw)), N, N, N,
                           np.ones(N))
+    probes = []
     for trial in range(2):
         r = np.where(rng.random(N) < 0.5, -1.0, 1.0)
-        rhs = orc.freivalds(RA, RB, N, N, N, r)
-        rt = torch.as_tensor(r, device=dev)
-        for name, Cm in (("split_i8", Cs), ("fp64", C64)):
+        probes.append((r, orc.freivalds(RA, RB, N, N, N, r)))
+
+    def freivalds_err(Cm):
+        worst = 0.0
+        for r, rhs in probes:
+            rt = torch.as_tensor(r, device=dev)
             # C r with r = +-1: exact products, pairwise summation on the host
             lhs = np.empty(N)
             for r0 in range(0, N, 2048):
                 chunk = (Cm[r0:r0 + 2048] * rt).cpu().numpy()
                 lhs[r0:r0 + 2048] = chunk.sum(axis=1)
-            fe = float(np.max(np.abs(lhs - rhs) / scale))
-            log(f"Freivalds {trial} {name}: {fe:.2e}")
-            assert fe <= 1e-12
+            worst = max(worst, float(np.max(np.abs(lhs - rhs) / scale)))
+        return worst
+
+    blk_64 = C64[trows][:, tcols].cpu().numpy()
+    err64 = float(np.max(np.abs(blk_64 - Co) / So))
+    fe64 = freivalds_err(C64)
+    log(f"fp64: block err_cw {err64:.2e}, Freivalds {fe64:.2e}")
+    assert err64 <= 1e-12 and fe64 <= 1e-12
     del C64
     torch.cuda.empty_cache()
 
-    # -- gradients on a block of keys ----------------------------------------
+    # -- oracle: gradients on a block of keys --------------------------------
     log("oracle gradients")
-    Wn_rows = W[torch.as_tensor(rows, device=dev)].cpu().numpy()          # 64 x N
-    Wn_cols = W[:, torch.as_tensor(cols, device=dev)].cpu().numpy()       # N x 64
+    Wn_rows = W[trows].cpu().numpy()          # 64 x N
+    Wn_cols = W[:, tcols].cpu().numpy()       # N x 64
     kk_a = remap(ak, keys, N)
     kk_b = remap(bk, keys, N)
     # dA for A records with group in rows and key in keys
@@ -130,8 +122,6 @@ def test_mixed_form_2pow30_records_forward_adjoint_checkpointed(orc):
     gA = orc.grad(A_sub, B_key, 64, 64, N, Wn_rows, "A")
     ymax = np.zeros(64); np.maximum.at(ymax, B_key.key, np.abs(B_key.val))
     bound_a = TOL * N * np.abs(Wn_rows).max(axis=1)[A_sub.group] * ymax[A_sub.key]
-    got_a = dAs[torch.as_tensor(ia, device=dev)].cpu().numpy()
-    assert np.all(np.abs(got_a - gA) <= bound_a)
     # dB for B records with key in keys and group in cols
     ib = np.nonzero(mb & mbk)[0]
     mak = kk_a >= 0
@@ -140,6 +130,32 @@ def test_mixed_form_2pow30_records_forward_adjoint_checkpointed(orc):
     gB = orc.grad(A_key, B_sub, N, 64, 64, Wn_cols, "B")
     xmax = np.zeros(64); np.maximum.at(xmax, A_key.key, np.abs(A_key.val))
     bound_b = TOL * N * xmax[B_sub.key] * np.abs(Wn_cols).max(axis=0)[B_sub.group]
-    got_b = dBs[torch.as_tensor(ib, device=dev)].cpu().numpy()
-    assert np.all(np.abs(got_b - gB) <= bound_b)
-    log(f"gradient checks: {len(ia)} A records, {len(ib)} B records")
+    tia, tib = torch.as_tensor(ia, device=dev), torch.as_tensor(ib, device=dev)
+
+    # -- each mixed form -------------------------------------------------------
+    for precision in ("split_i8", "crt_i8"):
+        log(f"{precision} forward")
+        Cs, _, ws = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, N, N, N,
+                                     precision=precision, tol=TOL, unique=True)
+        st, info = ops.sync_status(ws)
+        assert st == 0 and info["slices"] == ops.split_slices(precision, N, TOL)
+        del ws
+        log(f"{precision} adjoint, checkpointed")
+        dAs, dBs, ws = ops.join_agg_bwd(A.group, A.key, A.val, B.key, B.group, B.val, N, N, N,
+                                        W, precision=precision, tol=TOL, unique=True)
+        assert ops.sync_status(ws)[0] == 0
+        del ws
+        torch.cuda.empty_cache()
+        blk_s = Cs[trows][:, tcols].cpu().numpy()
+        assert np.all(np.abs(blk_s - Co) <= TOL * N * np.outer(mu, nu))
+        errs = float(np.max(np.abs(blk_s - Co) / So))
+        fes = freivalds_err(Cs)
+        log(f"{precision}: block err_cw {errs:.2e}, Freivalds {fes:.2e}")
+        assert errs <= 1e-12 and fes <= 1e-12
+        got_a = dAs[tia].cpu().numpy()
+        assert np.all(np.abs(got_a - gA) <= bound_a)
+        got_b = dBs[tib].cpu().numpy()
+        assert np.all(np.abs(got_b - gB) <= bound_b)
+        log(f"{precision} gradient checks: {len(ia)} A records, {len(ib)} B records")
+        del Cs, dAs, dBs
+        torch.cuda.empty_cache()
