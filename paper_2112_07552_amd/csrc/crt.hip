@@ -78,6 +78,38 @@ __device__ inline int sym_mod32(int x, int m, int c16, float inv) {
     return r;
 }
 
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// The symmetric residues of four int32 sums as four int8 bytes of one word.
+// SMALL: every |x| <= 2^26; otherwise x is first replaced by r1 above
+// (congruent, |r1| < 2^24).  Then q = rint(x * (1/m)) in float is within
+// 0.57 of x / m, r = x - q m (24-bit multiply-add) lies within 0.57 m of 0,
+// and the symmetric range follows from d = r - lo (mod 2^16) with two
+// unsigned 16-bit minimums, min(d, d + m) then min(d, d - m), on two
+// residues per instruction.  (Checked exhaustively for |x| <= 2^26 and
+// every modulus.)
+template <bool SMALL>
+__device__ inline uint32_t sym_mod32x4(const int (&x)[4], int m, int c16, float inv) {
+    int r[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int v = SMALL ? x[j] : __mul24(x[j] >> 16, c16) + (x[j] & 0xffff);
+        const int q = (int)rintf((float)v * inv);
+        r[j] = __mul24(q, -m) + v;
+    }
+    const unsigned short lo = (unsigned short)(-(m >> 1)), mm = (unsigned short)m;
+    const u16x2 lo2 = {lo, lo}, m2 = {mm, mm};
+    u16x2 d01 = u16x2{(unsigned short)r[0], (unsigned short)r[1]} - lo2;
+    u16x2 d23 = u16x2{(unsigned short)r[2], (unsigned short)r[3]} - lo2;
+    d01 = __builtin_elementwise_min(d01, d01 + m2);
+    d23 = __builtin_elementwise_min(d23, d23 + m2);
+    d01 = __builtin_elementwise_min(d01, d01 - m2) + lo2;
+    d23 = __builtin_elementwise_min(d23, d23 - m2) + lo2;
+    // bytes 0 and 2 of each pair: residues 0, 1, 2, 3
+    return __builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, d23),
+                                 __builtin_bit_cast(uint32_t, d01), 0x06040200u);
+}
+
 __device__ inline int line_exp(unsigned long long bits) {
     const double mx = __longlong_as_double((long long)bits);
     int e = 0;
@@ -351,8 +383,9 @@ __device__ inline void crt_stages(int st, int nst, const StageLoads<G> &L, unsig
         crt_stages<G, B + 1>(st, nst, L, lds_addr, voff, lds_a, lds_b, fc, fm, acc);
 }
 
-// nblk (k-steps) must be a multiple of 2 NS.
-template <typename G>
+// nblk (k-steps) must be a multiple of 2 NS.  SMALL: nblk * 32 <= 4096, so
+// every int32 sum is at most 2^26 in magnitude.
+template <typename G, bool SMALL>
 __global__ void __launch_bounds__(G::threads) __attribute__((amdgpu_waves_per_eu(G::WPE, G::WPE)))
 gemm_crt_kernel(int m, int n, int nblk, int tiles_m, int tiles_n, const int8_t *__restrict__ xs,
                 int xlp, const int8_t *__restrict__ ys, int ylp, int64_t plane_x,
@@ -432,12 +465,9 @@ gemm_crt_kernel(int m, int n, int nblk, int tiles_m, int tiles_n, const int8_t *
             uint32_t w[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                uint32_t v = 0;
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj)
-                    v |= (uint32_t)(uint8_t)(int8_t)sym_mod32(acc[a][b][4 * q + jj], mi, c16, inv)
-                         << (8 * jj);
-                w[q] = v;
+                const int xs4[4] = {acc[a][b][4 * q], acc[a][b][4 * q + 1], acc[a][b][4 * q + 2],
+                                    acc[a][b][4 * q + 3]};
+                w[q] = sym_mod32x4<SMALL>(xs4, mi, c16, inv);
             }
             *reinterpret_cast<uint4 *>(r + ((int64_t)rb * n + col) * 32 + 16 * half) =
                 make_uint4(w[0], w[1], w[2], w[3]);
@@ -596,9 +626,15 @@ hipError_t launch_gemm_crt(int m, int n, int k, int L, int bits, const int8_t *x
     const int64_t wgs = (int64_t)tiles_m * tiles_n * L;
     const int64_t plane_res = crt_residue_plane(m, n);
     using G = CrtCfg;
-    gemm_crt_kernel<G><<<(unsigned)wgs, G::threads, 0, s>>>(
-        m, n, nblk, tiles_m, tiles_n, xs, x_lines_pad, ys, y_lines_pad,
-        (int64_t)x_lines_pad * len_pad, (int64_t)y_lines_pad * len_pad, cc, res, plane_res);
+    // |sum| <= len_pad 2^14 (residues at most 128 in magnitude)
+    if (len_pad <= 4096)
+        gemm_crt_kernel<G, true><<<(unsigned)wgs, G::threads, 0, s>>>(
+            m, n, nblk, tiles_m, tiles_n, xs, x_lines_pad, ys, y_lines_pad,
+            (int64_t)x_lines_pad * len_pad, (int64_t)y_lines_pad * len_pad, cc, res, plane_res);
+    else
+        gemm_crt_kernel<G, false><<<(unsigned)wgs, G::threads, 0, s>>>(
+            m, n, nblk, tiles_m, tiles_n, xs, x_lines_pad, ys, y_lines_pad,
+            (int64_t)x_lines_pad * len_pad, (int64_t)y_lines_pad * len_pad, cc, res, plane_res);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 grid((unsigned)((n + kThreads / 4 - 1) / (kThreads / 4)), (unsigned)((m + 31) / 32));
