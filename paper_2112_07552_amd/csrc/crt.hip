@@ -44,45 +44,21 @@ constexpr int kModuli[kMaxMod] = {256, 255, 253, 251, 247, 241, 239, 233,
 
 struct CrtConsts {
     int L, bits;
-    double m[kMaxMod], inv_m[kMaxMod];
     int mi[kMaxMod], c16[kMaxMod];  // m_i and 2^16 mod m_i
+    int c18[kMaxMod], c36[kMaxMod]; // 2^18 and 2^36 mod m_i, symmetric (|c| <= 128)
     float inv_f[kMaxMod];           // 1 / m_i rounded to float
     double w[kMaxMod][3];  // w_i = w2 2^80 + w1 2^40 + w0
     double Mp[3];          // M in the same limbs
     double Md;             // M rounded to double
 };
 
-// symmetric residue of an integer-valued double |x| < 2^53 modulo m
-__device__ inline double sym_mod(double x, double m, double inv_m) {
-    const double q = rint(x * inv_m);
-    double r = fma(-q, m, x);  // exact: |q m| < 2^53, |x - q m| < 2 m
-    const double hi = floor((m - 1.0) * 0.5), lo = -floor(m * 0.5);
-    if (r > hi) r -= m;
-    if (r < lo) r += m;
-    return r;
-}
-
-// The same residue of any int32 x.  r1 = (x >> 16)(2^16 mod m) + (x & 0xffff)
-// is congruent to x and |r1| < 2^24, so it converts to float exactly; the
-// float quotient is within 0.006 of r1 / m, so r1 - m rint(r1 / m) lies in
-// [-m/2 - 2, m/2 + 2] and one correction each way lands in the symmetric
-// range.  Every product fits the 24-bit multiplier.  (Checked exhaustively
-// over all int32 x for each modulus.)
-__device__ inline int sym_mod32(int x, int m, int c16, float inv) {
-    const int r1 = __mul24(x >> 16, c16) + (x & 0xffff);
-    const int q = (int)rintf((float)r1 * inv);
-    int r = r1 - __mul24(q, m);
-    const int hi = (m - 1) >> 1, lo = -(m >> 1);
-    r = r > hi ? r - m : r;
-    r = r < lo ? r + m : r;
-    return r;
-}
-
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 // The symmetric residues of four int32 sums as four int8 bytes of one word.
-// SMALL: every |x| <= 2^26; otherwise x is first replaced by r1 above
-// (congruent, |r1| < 2^24).  Then q = rint(x * (1/m)) in float is within
+// SMALL: every |x| <= 2^26; otherwise x is first replaced by the congruent
+// r1 = (x >> 16)(2^16 mod m) + (x & 0xffff), |r1| < 2^24 (c16 = 2^16 mod m;
+// checked exhaustively over all int32 x for each modulus).  Then
+// q = rint(x * (1/m)) in float is within
 // 0.57 of x / m, r = x - q m (24-bit multiply-add) lies within 0.57 m of 0,
 // and the symmetric range follows from d = r - lo (mod 2^16) with two
 // unsigned 16-bit minimums, min(d, d + m) then min(d, d - m), on two
@@ -117,103 +93,104 @@ __device__ inline int line_exp(unsigned long long bits) {
     return e;
 }
 
-__device__ inline void store8(int8_t *dst, const int8_t (&d)[8]) {
-    uint2 v;
-    v.x = (uint32_t)(uint8_t)d[0] | ((uint32_t)(uint8_t)d[1] << 8) |
-          ((uint32_t)(uint8_t)d[2] << 16) | ((uint32_t)(uint8_t)d[3] << 24);
-    v.y = (uint32_t)(uint8_t)d[4] | ((uint32_t)(uint8_t)d[5] << 8) |
-          ((uint32_t)(uint8_t)d[6] << 16) | ((uint32_t)(uint8_t)d[7] << 24);
-    *reinterpret_cast<uint2 *>(dst) = v;
-}
-
 // residue plane layout (as the slice form): res[i][t / 32][(t % 32) / 16][line][t % 16]
 __device__ inline int64_t res_offset(int line, int t, int lines_pad) {
     return (((int64_t)(t >> 5) * 2 + ((t >> 4) & 1)) * lines_pad + line) * 16 + (t & 15);
 }
 
-// Lines are rows.  A thread owns the 16 positions of one 16-byte half of one
-// row; consecutive threads own consecutive rows, so every residue store is
-// one 16-byte vector and a wave's stores form one contiguous 1 KB run.
+// The truncated integer z' = trunc(z 2^(bits - e)) (|z'| < 2^53) as exact
+// FP64 pieces z' = z2 2^36 + z1 2^18 + z0, 0 <= z0, z1 < 2^18, |z2| <= 2^17;
+// then x = z2 c36 + z1 c18 + z0 is congruent to z' modulo m with |x| < 2^26
+// (|c| <= 128), two 24-bit multiply-adds per modulus, and sym_mod32x4<true>
+// gives the residues.
+struct Pieces {
+    int z2, z1, z0;
+};
+
+__device__ inline Pieces pieces(double z, int shift) {
+    if (!isfinite(z)) z = 0.0;  // non-finite inputs are flagged by the line maxima
+    const double zt = trunc(ldexp(z, shift));
+    const double h = floor(zt * 0x1p-36);
+    const double t = fma(-h, 0x1p36, zt);  // exact, in [0, 2^36)
+    const double mid = floor(t * 0x1p-18);
+    return Pieces{(int)h, (int)mid, (int)fma(-mid, 0x1p18, t)};
+}
+
+// residues modulo m_i of 16 pieces, as one 16-byte vector
+__device__ inline uint4 residues16(const Pieces (&p)[16], const CrtConsts &cc, int i) {
+    const int m = cc.mi[i], c18 = cc.c18[i], c36 = cc.c36[i];
+    const float inv = cc.inv_f[i];
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int x[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const Pieces &z = p[4 * q + j];
+            x[j] = __mul24(z.z2, c36) + __mul24(z.z1, c18) + z.z0;
+        }
+        w[q] = sym_mod32x4<true>(x, m, 0, inv);
+    }
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// One workgroup per 64 lines x 64 positions (grid: len_pad / 64, lines_pad /
+// 64).  Thread (r, g) = (t % 64, t / 64) owns line l0 + r, positions p0 +
+// 16 g .. + 15; a wave's 16-byte residue stores are then one contiguous 1 KB
+// run per modulus.
+
+// Lines are rows: the 64 x 64 tile is read row-contiguously (a wave reads
+// 512 B of one row per load) into padded LDS, then each thread takes its 16
+// positions of one row from there.
 __global__ void __launch_bounds__(kThreads)
 crt_rows_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
                 const unsigned long long *__restrict__ maxbits, CrtConsts cc,
                 int8_t *__restrict__ out, int lines_pad, int len_pad, int *__restrict__ exps) {
-    const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (gid >= (int64_t)lines_pad * (len_pad / 16)) return;
-    const int row = (int)(gid % lines_pad);
-    const int t0 = (int)(gid / lines_pad) * 16;
-    const bool live = row < rows;
-    const int e = live ? line_exp(maxbits[row]) : 0;
-    if (live && t0 == 0) exps[row] = e;
-    double zi[16];
+    __shared__ double tile[64][64 + 2];  // [line][position]; the pad spreads lines over banks
+    const int p0 = blockIdx.x * 64, l0 = blockIdx.y * 64;
+    const int t = threadIdx.x;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-        const int c = t0 + j;
-        double z = (live && c < cols) ? Z[(int64_t)row * ld + c] : 0.0;
-        if (!isfinite(z)) z = 0.0;
-        zi[j] = trunc(ldexp(z, cc.bits - e));
+        const int lr = (t >> 6) + 4 * j, pc = t & 63;
+        const int row = l0 + lr, c = p0 + pc;
+        tile[lr][pc] = (row < rows && c < cols) ? Z[(int64_t)row * ld + c] : 0.0;
     }
+    __syncthreads();
+    const int r = t & 63, g = t >> 6;
+    const int line = l0 + r;
+    const int e = line < rows ? line_exp(maxbits[line]) : 0;
+    if (line < rows && blockIdx.x == 0 && g == 0) exps[line] = e;
+    Pieces pc[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) pc[k] = pieces(tile[r][16 * g + k], cc.bits - e);
     const int64_t plane = (int64_t)lines_pad * len_pad;
-    int8_t *o = out + res_offset(row, t0, lines_pad);
-    for (int i = 0; i < cc.L; ++i) {
-        uint32_t w[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            uint32_t v = 0;
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                v |= (uint32_t)(uint8_t)(int8_t)(int)sym_mod(zi[4 * q + j], cc.m[i], cc.inv_m[i])
-                     << (8 * j);
-            w[q] = v;
-        }
-        *reinterpret_cast<uint4 *>(o + (int64_t)i * plane) = make_uint4(w[0], w[1], w[2], w[3]);
-    }
+    int8_t *o = out + res_offset(line, p0 + 16 * g, lines_pad);
+    for (int i = 0; i < cc.L; ++i)
+        *reinterpret_cast<uint4 *>(o + (int64_t)i * plane) = residues16(pc, cc, i);
 }
 
-// Lines are columns: a 64 x 64 tile through LDS, one modulus at a time.
+// Lines are columns: thread (r, g) reads its column's 16 positions directly
+// (for each position the wave reads 512 contiguous bytes of one row).
 __global__ void __launch_bounds__(kThreads)
 crt_cols_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
                 const unsigned long long *__restrict__ maxbits, CrtConsts cc,
                 int8_t *__restrict__ out, int lines_pad, int len_pad, int *__restrict__ exps) {
-    __shared__ int8_t tile[64][64 + 8];  // [col][row]
-    const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
-    const int tc = threadIdx.x & 63, tr = threadIdx.x >> 6;
-    const int col = c0 + tc;
+    const int p0 = blockIdx.x * 64, l0 = blockIdx.y * 64;
+    const int r = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int col = l0 + r;
     const int e = col < cols ? line_exp(maxbits[col]) : 0;
-    if (blockIdx.x == 0 && tr == 0 && col < cols) exps[col] = e;
-    double zi[16];
+    if (col < cols && blockIdx.x == 0 && g == 0) exps[col] = e;
+    Pieces pc[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const int row = r0 + tr + 4 * j;
-        double z = (row < rows && col < cols) ? Z[(int64_t)row * ld + col] : 0.0;
-        if (!isfinite(z)) z = 0.0;
-        zi[j] = trunc(ldexp(z, cc.bits - e));
+    for (int k = 0; k < 16; ++k) {
+        const int row = p0 + 16 * g + k;
+        pc[k] = pieces((row < rows && col < cols) ? Z[(int64_t)row * ld + col] : 0.0,
+                       cc.bits - e);
     }
     const int64_t plane = (int64_t)lines_pad * len_pad;
-    // writer: thread -> (column wc, 16 rows starting at 16 wq)
-    const int wc = threadIdx.x >> 2, wq = threadIdx.x & 3;
-    for (int i = 0; i < cc.L; ++i) {
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-            tile[tc][tr + 4 * j] = (int8_t)(int)sym_mod(zi[j], cc.m[i], cc.inv_m[i]);
-        __syncthreads();
-        const int line = c0 + wc;
-        if (line < lines_pad) {
-            int8_t a[8], b[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                a[j] = tile[wc][16 * wq + j];
-                b[j] = tile[wc][16 * wq + 8 + j];
-            }
-            const int t = r0 + 16 * wq;
-            if (t < len_pad) {
-                int8_t *o = out + (int64_t)i * plane + res_offset(line, t, lines_pad);
-                store8(o, a);
-                store8(o + 8, b);
-            }
-        }
-        __syncthreads();
-    }
+    int8_t *o = out + res_offset(col, p0 + 16 * g, lines_pad);
+    for (int i = 0; i < cc.L; ++i)
+        *reinterpret_cast<uint4 *>(o + (int64_t)i * plane) = residues16(pc, cc, i);
 }
 
 // ---------------------------------------------------------------- the GEMM
@@ -563,10 +540,12 @@ CrtConsts make_consts(int L, int bits) {
     const u128 mask = ((u128)1 << 40) - 1;
     for (int i = 0; i < L; ++i) {
         const int mi = kModuli[i];
-        cc.m[i] = mi;
-        cc.inv_m[i] = 1.0 / mi;
         cc.mi[i] = mi;
         cc.c16[i] = 65536 % mi;
+        const int c18 = (int)((1ull << 18) % (unsigned long long)mi);
+        const int c36 = (int)((1ull << 36) % (unsigned long long)mi);
+        cc.c18[i] = c18 > mi / 2 ? c18 - mi : c18;
+        cc.c36[i] = c36 > mi / 2 ? c36 - mi : c36;
         cc.inv_f[i] = (float)(1.0 / mi);
         const u128 Mi = M / (u128)mi;
         const int yi = inv_mod((int)(Mi % (u128)mi), mi);
@@ -599,16 +578,15 @@ int crt_len_align() { return kCrtLenAlign; }
 hipError_t launch_crt_split(const double *Z, int rows, int cols, int64_t ld, int axis,
                             const unsigned long long *maxbits, int L, int bits, int8_t *out,
                             int lines_pad, int len_pad, int *exps, hipStream_t s) {
+    if (lines_pad % 64 || len_pad % 64) return hipErrorInvalidValue;
     const CrtConsts cc = make_consts(L, bits);
-    if (axis == 0) {
-        const int64_t threads = (int64_t)lines_pad * (len_pad / 16);
-        crt_rows_kernel<<<(unsigned)((threads + kThreads - 1) / kThreads), kThreads, 0, s>>>(
-            Z, rows, cols, ld, maxbits, cc, out, lines_pad, len_pad, exps);
-    } else {
-        dim3 grid((unsigned)(len_pad / 64), (unsigned)(lines_pad / 64));
+    const dim3 grid((unsigned)(len_pad / 64), (unsigned)(lines_pad / 64));
+    if (axis == 0)
+        crt_rows_kernel<<<grid, kThreads, 0, s>>>(Z, rows, cols, ld, maxbits, cc, out, lines_pad,
+                                                  len_pad, exps);
+    else
         crt_cols_kernel<<<grid, kThreads, 0, s>>>(Z, rows, cols, ld, maxbits, cc, out, lines_pad,
                                                   len_pad, exps);
-    }
     return hipGetLastError();
 }
 
