@@ -129,36 +129,76 @@ __device__ inline void barrier_no_fence() { asm volatile("s_barrier" ::: "memory
 typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(1))) const void global_cvoid;
 
-// Issue this wave's share of the loads of k-step kb into LDS buffer `buf`.
-// Plane q (wave-uniform) goes to wave q % NW; waves with fewer real planes
-// load a valid dummy run into the scratch plane, so every wave issues exactly
-// per_wave instructions and its vmcnt bookkeeping is a constant.
+// While the matrix cores are kept busy, vector-ALU instructions of every
+// wave on the SIMD get few issue slots, so the main loop does its address
+// arithmetic on the scalar unit: each direct-to-LDS load is a uniform SGPR
+// base plus the lane's fixed byte offset (the SADDR form), with its LDS
+// address in M0.
+__device__ inline void load_lds16(const char *sbase, unsigned voff, unsigned lds_addr) {
+    asm volatile("global_load_lds_dwordx4 %0, %1" : : "v"(voff), "s"(sbase), "{m0}"(lds_addr)
+                 : "memory");
+}
+
+// A uniform address computed on the vector ALU (64-bit products are) moved to
+// scalar registers; the builtin returns int, so widen through uint32_t.
+__device__ inline const char *to_sgpr(const char *p) {
+    const uint64_t u = (uint64_t)(uintptr_t)p;
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((unsigned)u);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+    return (const char *)(uintptr_t)(lo | (hi << 32));
+}
+
+// This wave's share of every stage's loads.  Plane q (wave-uniform) goes to
+// wave q % NW; waves with fewer real planes load a valid dummy run into the
+// scratch plane, so every wave issues exactly per_wave instructions and its
+// vmcnt bookkeeping is a constant.  Load j of k-step kb reads
+// src[j] + kb * step[j] (+ the lane's 16 bytes) into stage offset dst[j].
 template <int S, int BN, int NW>
-__device__ inline void issue_stage(i4 *buf, int kb, int nblk, const char *xs, int x_lines_pad,
-                                   int m0, const char *ys, int y_lines_pad, int n0, int wave,
-                                   int lane) {
+struct WaveLoads {
     using St = Stage<S, BN, NW>;
+    const char *src[St::per_wave];
+    int64_t step[St::per_wave];
+    unsigned dst[St::per_wave];
+};
+
+template <int S, int BN, int NW>
+__device__ inline WaveLoads<S, BN, NW> wave_loads(int wave, int nblk, const char *xs,
+                                                  int x_lines_pad, int m0, const char *ys,
+                                                  int y_lines_pad, int n0) {
+    using St = Stage<S, BN, NW>;
+    WaveLoads<S, BN, NW> L;
 #pragma unroll
     for (int j = 0; j < St::per_wave; ++j) {
         const int q = wave + NW * j;
         const char *src;
-        int dst;
         if (q < St::xi) {
             const int p = q >> 1, h = q & 1;
-            src = xs + ((((int64_t)p * nblk + kb) * 2 + h) * x_lines_pad + m0 + lane) * 16;
-            dst = q * 64;
+            src = xs + ((((int64_t)p * nblk) * 2 + h) * x_lines_pad + m0) * 16;
+            L.step[j] = (int64_t)2 * x_lines_pad * 16;
+            L.dst[j] = (unsigned)q * 64u * 16u;
         } else if (q < St::planes) {
             const int qq = q - St::xi;
             const int rb = qq % (BN / 64), ph = qq / (BN / 64);
             const int p = ph >> 1, h = ph & 1;
-            src = ys + ((((int64_t)p * nblk + kb) * 2 + h) * y_lines_pad + n0 + rb * 64 + lane) * 16;
-            dst = q * 64;
+            src = ys + ((((int64_t)p * nblk) * 2 + h) * y_lines_pad + n0 + rb * 64) * 16;
+            L.step[j] = (int64_t)2 * y_lines_pad * 16;
+            L.dst[j] = (unsigned)q * 64u * 16u;
         } else {
-            src = xs + lane * 16;
-            dst = St::planes * 64;
+            src = xs;
+            L.step[j] = 0;
+            L.dst[j] = (unsigned)St::planes * 64u * 16u;
         }
-        __builtin_amdgcn_global_load_lds((global_cvoid *)src, (lds_void *)(buf + dst), 16, 0, 0);
+        L.src[j] = to_sgpr(src);
     }
+    return L;
+}
+
+template <int S, int BN, int NW>
+__device__ inline void issue_stage(const WaveLoads<S, BN, NW> &L, int kb, unsigned buf_addr,
+                                   unsigned voff) {
+#pragma unroll
+    for (int j = 0; j < Stage<S, BN, NW>::per_wave; ++j)
+        load_lds16(L.src[j] + (int64_t)kb * L.step[j], voff, buf_addr + L.dst[j]);
 }
 
 // Digit products of slices p in [P0, P1) with every q on the kept diagonals.
@@ -209,11 +249,18 @@ gemm_split_kernel(int m, int n, int nblk, int kb0, int kb1, int flush, int accum
     tile_coords(tiles_m, tiles_n, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
     // the wave index is uniform across the wave: in a scalar register, the
-    // plane selection of issue_stage is a scalar branch
+    // plane selection of the loads is scalar
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int wm = wave & 1, wn = wave >> 1;
     const int l32 = lane & 31, half = lane >> 5;
+    const unsigned voff = (unsigned)lane * 16u;
+    const unsigned lds_addr = (unsigned)(uintptr_t)&lds[0][0];
+    const WaveLoads<S, BN, NW> L =
+        wave_loads<S, BN, NW>(wave, nblk, xs, x_lines_pad, m0, ys, y_lines_pad, n0);
+    // this lane's fragment bases; buffer, slice and block offsets are constants
+    const i4 *lx = &lds[0][0] + half * BM + wm * 32 + l32;
+    const i4 *ly = &lds[0][0] + St::x_chunks + half * BN + wn * 32 * WNB + l32;
 
     acc_t acc[S][WNB];
     double sum[M::kSum ? WNB : 1][M::kSum ? 16 : 1];
@@ -227,16 +274,6 @@ gemm_split_kernel(int m, int n, int nblk, int kb0, int kb1, int flush, int accum
 #pragma unroll
             for (int i = 0; i < 16; ++i) sum[b][i] = 0.0;
     }
-
-    auto read = [&](const i4 *buf, i4 (&fx)[S], i4 (&fy)[S][WNB]) {
-#pragma unroll
-        for (int p = 0; p < S; ++p) {
-            fx[p] = buf[(p * 2 + half) * BM + wm * 32 + l32];
-#pragma unroll
-            for (int b = 0; b < WNB; ++b)
-                fy[p][b] = buf[St::x_chunks + (p * 2 + half) * BN + wn * 32 * WNB + b * 32 + l32];
-        }
-    };
 
     auto flush_sum = [&]() {
         if constexpr (M::kSum) {
@@ -252,24 +289,42 @@ gemm_split_kernel(int m, int n, int nblk, int kb0, int kb1, int flush, int accum
         }
     };
 
-    // one k-step: fc holds its fragments, fn receives those of the next
-    auto kstep = [&](int kb, i4 (&fcx)[S], i4 (&fcy)[S][WNB], i4 (&fnx)[S],
-                     i4 (&fny)[S][WNB]) {
-        const int it = kb - kb0;
+    i4 f0x[S], f0y[S][WNB], f1x[S], f1y[S][WNB];
+    // fragments of the k-step in LDS buffer B
+    auto read = [&](auto Bc, i4 (&fx)[S], i4 (&fy)[S][WNB]) {
+        constexpr int B = decltype(Bc)::value;
+#pragma unroll
+        for (int p = 0; p < S; ++p) {
+            fx[p] = lx[B * St::chunks + p * 2 * BM];
+#pragma unroll
+            for (int b = 0; b < WNB; ++b) fy[p][b] = ly[B * St::chunks + p * 2 * BN + b * 32];
+        }
+    };
+
+    // one k-step; IT3 = (kb - kb0) mod 3 is its LDS buffer, REG = (kb - kb0)
+    // mod 2 its fragment register set (the other set receives the next
+    // k-step's fragments)
+    auto kstep = [&](auto IT3c, auto REGc, int kb) {
+        constexpr int IT3 = decltype(IT3c)::value, REG = decltype(REGc)::value;
+        i4(&fcx)[S] = REG == 0 ? f0x : f1x;
+        i4(&fcy)[S][WNB] = REG == 0 ? f0y : f1y;
+        i4(&fnx)[S] = REG == 0 ? f1x : f0x;
+        i4(&fny)[S][WNB] = REG == 0 ? f1y : f0y;
         mfma_range<T, S, WNB, 0, PSPLIT>(fcx, fcy, acc);
         __builtin_amdgcn_sched_barrier(0);
         if (kb + 1 < kb1) {
             if (kb + 2 < kb1) wait_vmcnt<St::per_wave>();
             else wait_vmcnt<0>();
             barrier_no_fence();
+            // kb's buffer is free: every wave has read its fragments
             if (kb + 3 < kb1)
-                issue_stage<S, BN, NW>(lds[(it + 3) % NSTAGE], kb + 3, nblk, xs, x_lines_pad, m0, ys,
-                                   y_lines_pad, n0, wave, lane);
-            read(lds[(it + 1) % NSTAGE], fnx, fny);
+                issue_stage<S, BN, NW>(L, kb + 3, lds_addr + (unsigned)IT3 * St::chunks * 16u, voff);
+            read(std::integral_constant<int, (IT3 + 1) % NSTAGE>{}, fnx, fny);
         }
+        __builtin_amdgcn_sched_barrier(0);
         mfma_range<T, S, WNB, PSPLIT, S>(fcx, fcy, acc);
         if constexpr (M::kSum) {
-            if ((it + 1) % flush == 0 || kb + 1 == kb1) flush_sum();
+            if ((kb - kb0 + 1) % flush == 0 || kb + 1 == kb1) flush_sum();
         }
     };
 
@@ -277,19 +332,26 @@ gemm_split_kernel(int m, int n, int nblk, int kb0, int kb1, int flush, int accum
 #pragma unroll
     for (int st = 0; st < NSTAGE; ++st)
         if (kb0 + st < kb1)
-            issue_stage<S, BN, NW>(lds[st], kb0 + st, nblk, xs, x_lines_pad, m0, ys, y_lines_pad,
-                               n0, wave, lane);
+            issue_stage<S, BN, NW>(L, kb0 + st, lds_addr + (unsigned)st * St::chunks * 16u, voff);
     const int issued = kb1 - kb0 < NSTAGE ? kb1 - kb0 : NSTAGE;
     if (issued == 3) wait_vmcnt<2 * St::per_wave>();
     else if (issued == 2) wait_vmcnt<St::per_wave>();
     else wait_vmcnt<0>();
     barrier_no_fence();
-    i4 f0x[S], f0y[S][WNB], f1x[S], f1y[S][WNB];
-    read(lds[0], f0x, f0y);
+    read(std::integral_constant<int, 0>{}, f0x, f0y);
 
-    for (int kb = kb0; kb < kb1; kb += 2) {
-        kstep(kb, f0x, f0y, f1x, f1y);
-        if (kb + 1 < kb1) kstep(kb + 1, f1x, f1y, f0x, f0y);
+    // unrolled by 6 so the LDS buffer (period 3) and the register set
+    // (period 2) of every k-step are compile-time constants
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    for (int kb = kb0; kb < kb1; kb += 6) {
+        kstep(I0{}, I0{}, kb);
+        if (kb + 1 < kb1) kstep(I1{}, I1{}, kb + 1);
+        if (kb + 2 < kb1) kstep(I2{}, I0{}, kb + 2);
+        if (kb + 3 < kb1) kstep(I0{}, I1{}, kb + 3);
+        if (kb + 4 < kb1) kstep(I1{}, I0{}, kb + 4);
+        if (kb + 5 < kb1) kstep(I2{}, I1{}, kb + 5);
     }
 
     // epilogue: C (+)= 2^(e_g + f_h) * sum_t 2^(-7t) S_t
