@@ -84,7 +84,11 @@ def test_encode_duplicates_float_and_skips(orc):
 # -------------------------------------------------------------------- gemm --
 
 GEMM_SHAPES = [(1, 1, 1), (17, 33, 5), (128, 128, 16), (129, 255, 130), (300, 200, 67),
-               (64, 1, 64), (1, 300, 257), (257, 129, 1)]
+               (64, 1, 64), (1, 300, 257), (257, 129, 1),
+               # whole tiles (m, n multiples of 128, k of 16): the unguarded
+               # path, whose loop takes two 16-deep stages per iteration, with
+               # 3, 4, 5 and 65 stages
+               (256, 128, 48), (256, 384, 64), (128, 256, 80), (384, 128, 1040)]
 
 
 @pytest.mark.parametrize("m,n,k", GEMM_SHAPES)

@@ -84,6 +84,7 @@ def bound_check(orc, A, B, M, K, N, Cg, tol):
     (50, 40_000, 50_000, 200, 129, 257, "uniform"),
     (51, 30_000, 30_000, 130, 70, 65, "loguniform"),
     (52, 20_000, 30_000, 1, 300, 140, "uniform"),
+    (53, 8_000, 9_000, 140, 40, 150, "uniform"),  # two int8 k-steps
 ])
 def test_split_forward_within_bound(orc, precision, tol, seed, nA, nB, M, K, N, kind):
     dev = cuda_or_skip()
