@@ -50,13 +50,27 @@ row_max_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
     const int row = blockIdx.x * (kThreads / 64) + wave;
     if (row >= rows) return;
     const double *z = Z + (int64_t)row * ld;
-    double mx = 0.0;
+    // eight independent loads in flight per lane (the loop is latency-bound
+    // with one)
+    double m[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     bool bad = false;
-    for (int c = lane; c < cols; c += 64) {
-        const double v = z[c];
-        if (!isfinite(v)) bad = true;
-        else mx = fmax(mx, fabs(v));
+    int c = lane;
+    for (; c + 7 * 64 < cols; c += 8 * 64) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = z[c + 64 * u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            bad |= !isfinite(v[u]);
+            m[u] = fmax(m[u], fabs(v[u]));
+        }
     }
+    for (; c < cols; c += 64) {
+        const double v = z[c];
+        bad |= !isfinite(v);
+        m[0] = fmax(m[0], fabs(v));
+    }
+    double mx = fmax(fmax(fmax(m[0], m[1]), fmax(m[2], m[3])), fmax(fmax(m[4], m[5]), fmax(m[6], m[7])));
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
     const unsigned long long anybad = __ballot(bad);
     if (lane == 0) {
@@ -68,7 +82,7 @@ row_max_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
 // Max |z| per column: threads own columns, blocks own chunks of rows, and the
 // partial maxima meet in an atomic max on the (monotone) bit patterns of the
 // non-negative doubles.  maxbits must be zero beforehand.
-constexpr int kColChunk = 64;
+constexpr int kColChunk = 128;
 
 __global__ void __launch_bounds__(kThreads)
 col_max_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
@@ -79,11 +93,26 @@ col_max_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
     double mx = 0.0;
     bool bad = false;
     if (col < cols) {
-        for (int r = r0; r < r1; ++r) {
-            const double v = Z[(int64_t)r * ld + col];
-            if (!isfinite(v)) bad = true;
-            else mx = fmax(mx, fabs(v));
+        // eight independent loads in flight per thread
+        double m[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        const double *z = Z + col;
+        int r = r0;
+        for (; r + 7 < r1; r += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = z[(int64_t)(r + u) * ld];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                bad |= !isfinite(v[u]);
+                m[u] = fmax(m[u], fabs(v[u]));
+            }
         }
+        for (; r < r1; ++r) {
+            const double v = z[(int64_t)r * ld];
+            bad |= !isfinite(v);
+            m[0] = fmax(m[0], fabs(v));
+        }
+        mx = fmax(fmax(fmax(m[0], m[1]), fmax(m[2], m[3])), fmax(fmax(m[4], m[5]), fmax(m[6], m[7])));
         atomicMax(maxbits + col, abs_bits(mx));
     }
     const unsigned long long anybad = __ballot(bad);
