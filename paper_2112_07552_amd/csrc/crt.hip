@@ -489,16 +489,24 @@ crt_reconstruct_kernel(int m, int n, const int8_t *__restrict__ res, int64_t pla
     double s[8][3];
 #pragma unroll
     for (int j = 0; j < 8; ++j) s[j][0] = s[j][1] = s[j][2] = 0.0;
+    // all of this thread's residue loads first (independent, in flight
+    // together); planes past L read as zero residues
+    uint2 vr[kMaxMod];
+#pragma unroll
+    for (int i = 0; i < kMaxMod; ++i)
+        vr[i] = i < cc.L ? *reinterpret_cast<const uint2 *>(base + (int64_t)i * plane)
+                         : make_uint2(0u, 0u);
 #pragma unroll
     for (int i = 0; i < kMaxMod; ++i) {
-        if (i >= cc.L) break;
-        const uint2 v = *reinterpret_cast<const uint2 *>(base + (int64_t)i * plane);
+        if (i < cc.L) {  // uniform; keeps the loop fully unrolled
+            const uint2 v = vr[i];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const double r = (double)(int8_t)((j < 4 ? v.x : v.y) >> (8 * (j & 3)));
-            s[j][0] = fma(r, cc.w[i][0], s[j][0]);  // exact: |r w| < 2^47, sums < 2^51
-            s[j][1] = fma(r, cc.w[i][1], s[j][1]);
-            s[j][2] = fma(r, cc.w[i][2], s[j][2]);
+            for (int j = 0; j < 8; ++j) {
+                const double r = (double)(int8_t)((j < 4 ? v.x : v.y) >> (8 * (j & 3)));
+                s[j][0] = fma(r, cc.w[i][0], s[j][0]);  // exact: |r w| < 2^47, sums < 2^51
+                s[j][1] = fma(r, cc.w[i][1], s[j][1]);
+                s[j][2] = fma(r, cc.w[i][2], s[j][2]);
+            }
         }
     }
     const int ec = ey[col] - 2 * cc.bits;
