@@ -14,9 +14,15 @@
  *
  * Conventions shared by every call:
  *  - Array pointers are DEVICE pointers owned by the caller.  The library never
- *    allocates, frees or keeps caller memory and keeps no mutable global state.
+ *    allocates, frees or keeps caller memory.  Its only global state is one
+ *    internal non-blocking stream per device (tcu_join_agg_bwd), created on
+ *    first use and kept for the life of the process.
  *  - Work is enqueued on the caller's stream and is asynchronous unless a call
  *    says otherwise; results are valid once the stream has reached that point.
+ *    Work a call puts on an internal stream is ordered after the caller's
+ *    earlier work and before its later work by events, so every call stays
+ *    stream-ordered with respect to the caller's stream.  The device whose
+ *    memory a call uses must be current.
  *  - Matrices are dense row-major with the leading dimension equal to the
  *    column count, unless a call takes explicit leading dimensions.
  *  - Host-side argument errors return a negative status and enqueue nothing.
@@ -207,7 +213,10 @@ tcu_status tcu_join_agg_fwd(const tcu_relation *A, const tcu_relation *B, int32_
  * output may be NULL.  Skipped records get 0.  Gradients are FP64 whatever
  * the value dtype.  In the mixed forms both products carry the forward's
  * guarantee with their own contraction length (N for dX, M for dY).  Needs a
- * workspace sized with TCU_WS_BACKWARD. */
+ * workspace sized with TCU_WS_BACKWARD.  With both outputs, the gather of
+ * dA_val (and, when re-encoding, the encoding of X) runs on the device's
+ * internal stream beside the products on the caller's stream; the call
+ * joins it back before returning control of the stream. */
 tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_t M, int32_t K,
                             int32_t N, tcu_precision p, double tol, const double *dC,
                             double *dA_val, double *dB_val, int flags, void *ws,

@@ -6,6 +6,8 @@
 // and its adjoint.  Every launch goes to the caller's stream.
 #include <string.h>
 
+#include <mutex>
+
 #include "internal.h"
 
 using namespace tcu;
@@ -62,13 +64,13 @@ size_t maxz(size_t a, size_t b) { return a > b ? a : b; }
 
 // Workspace layout:
 //   [status block][X: M*K f64][Y: K*N f64]
-//   [G: max(M*K, K*N) f64]                             (backward)
+//   [G: M*K f64][G2: K*N f64]                           (backward: dX, dY)
 //   [line maxima and exponents of operands A and B]     (mixed forms)
 //   [digit slices of operands A and B, TCU_MAX_SLICES each]
 // In the mixed forms "A" is the left operand of a product (X forward, W
 // for dX, X^T for dY) and "B" the right one (Y, Y^T, W).
 struct Layout {
-    size_t x = 0, y = 0, g = 0, mba = 0, mbb = 0, ea = 0, eb = 0, sa = 0, sb = 0, res = 0;
+    size_t x = 0, y = 0, g = 0, g2 = 0, mba = 0, mbb = 0, ea = 0, eb = 0, sa = 0, sb = 0, res = 0;
     size_t total = 0;
 };
 
@@ -82,7 +84,9 @@ Layout plan_layout(int32_t M, int32_t K, int32_t N, tcu_precision p, int flags) 
     off += align_up((size_t)K * (size_t)N * sizeof(double));
     if (bwd) {
         L.g = off;
-        off += align_up(maxz((size_t)M * K, (size_t)K * N) * sizeof(double));
+        off += align_up((size_t)M * (size_t)K * sizeof(double));
+        L.g2 = off;
+        off += align_up((size_t)K * (size_t)N * sizeof(double));
     }
     if (is_split(p)) {
         const size_t digit = p == TCU_PREC_SPLIT_BF16 ? 2 : 1;
@@ -196,6 +200,54 @@ hipError_t split_product(const SplitOperand &a, const SplitOperand &b, int m, in
         e = launch_gemm_split(m, n, k, S, bf16, sa, la, sb, lb, len_pad, ea, eb, C, ldc, s);
     return e;
 }
+
+// One relation's encoding on stream s: zero the matrix, scatter the records.
+hipError_t encode_one(const tcu_relation &R, int which, int rows, int cols, double *Z,
+                      StatusBlock *st, hipStream_t s) {
+    hipError_t e = launch_zero_f64(Z, (size_t)rows * cols, s);
+    if (e == hipSuccess) e = launch_encode(R, which, rows, cols, Z, st, which, s);
+    return e;
+}
+
+// The adjoint's second stream: one non-blocking stream (default priority) per
+// device, created on first use and kept for the life of the process.  Work
+// on it is ordered against the caller's stream by events only, so a call
+// stays stream-ordered with respect to the caller's stream.
+hipError_t side_stream(hipStream_t *out) {
+    static std::mutex mu;
+    static hipStream_t streams[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (streams[dev] == nullptr) {
+        e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            streams[dev] = nullptr;
+            return e;
+        }
+    }
+    *out = streams[dev];
+    return hipSuccess;
+}
+
+// Events of one adjoint call, destroyed when the call returns (the runtime
+// keeps a recorded event alive until the work it marks has run).
+struct CallEvents {
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    hipError_t create() {
+        for (hipEvent_t &e : ev) {
+            const hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+            if (r != hipSuccess) return r;
+        }
+        return hipSuccess;
+    }
+    ~CallEvents() {
+        for (hipEvent_t e : ev)
+            if (e != nullptr) (void)hipEventDestroy(e);
+    }
+};
 
 }  // namespace
 
@@ -326,13 +378,39 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
     const Layout L = plan_layout(M, K, N, p, TCU_WS_BACKWARD);
     if (!ws_ok(ws, ws_bytes, L.total)) return TCU_ERR_WORKSPACE;
     StatusBlock *st = at<StatusBlock>(ws, 0);
-    double *X = at<double>(ws, L.x), *Y = at<double>(ws, L.y), *G = at<double>(ws, L.g);
+    double *X = at<double>(ws, L.x), *Y = at<double>(ws, L.y);
+    double *G = at<double>(ws, L.g), *G2 = at<double>(ws, L.g2);
 
     if (dA_val == nullptr && dB_val == nullptr) return TCU_OK;
-    if (!(flags & TCU_BWD_SAVED_ENCODINGS)) {
+    const bool saved = (flags & TCU_BWD_SAVED_ENCODINGS) != 0;
+    // With both gradients, the gather of dA (memory-bound) and, when the
+    // encodings are rebuilt, the encoding of X run on a second stream beside
+    // the matrix products on the caller's stream:
+    //   caller: [encode Y] fork  dX = dC Y^T  ev_dx  ...wait ev_x  dY = X^T dC  wait ev_a  gather dB
+    //   side:        wait fork  [encode X] ev_x  wait ev_dx  gather dA  ev_a
+    // dX and dY live in separate buffers (G, G2), so nothing the two streams
+    // run at the same time touches the same memory.
+    const bool both = dA_val != nullptr && dB_val != nullptr;
+    hipStream_t side = nullptr;
+    CallEvents evs;
+    if (both) {
+        TCU_TRY(side_stream(&side));
+        TCU_TRY(evs.create());
+    }
+    hipEvent_t ev_fork = evs.ev[0], ev_x = evs.ev[1], ev_a = evs.ev[2];
+
+    if (!saved) {
         // activation checkpointing: the encodings are rebuilt from the records
         TCU_TRY(launch_clear_status(st, stream));
-        TCU_TRY(encode_both(*A, *B, M, K, N, X, Y, st, false, stream));
+        TCU_TRY(encode_one(*B, 1, K, N, Y, st, stream));
+        if (both) {
+            TCU_TRY(hipEventRecord(ev_fork, stream));
+            TCU_TRY(hipStreamWaitEvent(side, ev_fork, 0));
+            TCU_TRY(encode_one(*A, 0, M, K, X, st, side));
+            TCU_TRY(hipEventRecord(ev_x, side));
+        } else {
+            TCU_TRY(encode_one(*A, 0, M, K, X, st, stream));
+        }
     }
     if (dA_val != nullptr) {
         // dX = dC * Y^T (M x K), then dA.val[i] = dX[g_i, k_i]
@@ -343,18 +421,28 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
             const SplitOperand a{dC, M, N, N, 0}, b{Y, K, N, N, 0};
             TCU_TRY(split_product(a, b, M, K, N, S1, p, tol, ws, L, st, G, K, stream));
         }
-        TCU_TRY(launch_gather(*A, 0, M, K, G, dA_val, stream));
+        if (both) {
+            // ev_fork is free again once the side stream has waited for it
+            TCU_TRY(hipEventRecord(ev_fork, stream));
+            TCU_TRY(hipStreamWaitEvent(side, ev_fork, 0));
+            TCU_TRY(launch_gather(*A, 0, M, K, G, dA_val, side));
+            TCU_TRY(hipEventRecord(ev_a, side));
+        } else {
+            TCU_TRY(launch_gather(*A, 0, M, K, G, dA_val, stream));
+        }
     }
     if (dB_val != nullptr) {
+        if (both && !saved) TCU_TRY(hipStreamWaitEvent(stream, ev_x, 0));  // X is encoded
         // dY = X^T * dC (K x N), then dB.val[j] = dY[k_j, h_j]
         if (S2 == 0) {
-            TCU_TRY(launch_gemm_f64(1, 0, K, N, M, X, K, dC, N, G, N, stream));
+            TCU_TRY(launch_gemm_f64(1, 0, K, N, M, X, K, dC, N, G2, N, stream));
         } else {
             // X^T: K lines = columns of X, length M; dC: N lines = columns, length M
             const SplitOperand a{X, M, K, K, 1}, b{dC, M, N, N, 1};
-            TCU_TRY(split_product(a, b, K, N, M, S2, p, tol, ws, L, st, G, N, stream));
+            TCU_TRY(split_product(a, b, K, N, M, S2, p, tol, ws, L, st, G2, N, stream));
         }
-        TCU_TRY(launch_gather(*B, 1, K, N, G, dB_val, stream));
+        TCU_TRY(launch_gather(*B, 1, K, N, G2, dB_val, stream));
+        if (both) TCU_TRY(hipStreamWaitEvent(stream, ev_a, 0));  // join: dA is written
     }
     return TCU_OK;
 }

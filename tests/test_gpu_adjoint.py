@@ -82,6 +82,36 @@ def test_bwd_saved_encodings_match_checkpointing(unique):
     assert torch.equal(dA1, dA2) and torch.equal(dB1, dB2)
 
 
+@pytest.mark.parametrize("saved", [False, True])
+def test_bwd_stream_ordered_on_a_side_stream(saved):
+    """With both gradients the adjoint runs its dA gather (and, when
+    re-encoding, the encoding of X) on an internal stream and joins it back
+    to the caller's stream: work queued afterwards on the caller's stream
+    sees finished gradients, with no device-wide synchronisation between.
+    The gathers move values exactly, so the result matches a run on the
+    default stream bit for bit."""
+    dev = cuda_or_skip()
+    M, K, N = 640, 512, 768
+    A, B = wl.mm_query(M, K, N, seed=36, device=dev)
+    W = wl.draw_values("uniform", M * N, 36, 99, device=dev).reshape(M, N)
+    ref_a, ref_b, _ = ops.join_agg_bwd(A.group, A.key, A.val, B.key, B.group, B.val, M, K, N, W,
+                                       unique=True)
+    torch.cuda.synchronize(dev)
+    s = torch.cuda.Stream(device=dev)
+    s.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(s):
+        ws = None
+        if saved:
+            _, _, ws = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, M, K, N,
+                                        unique=True, for_backward=True)
+        dA, dB, _ = ops.join_agg_bwd(A.group, A.key, A.val, B.key, B.group, B.val, M, K, N, W,
+                                     ws=ws, unique=True, saved_encodings=saved)
+        # consumers on the same stream, right behind the call
+        cA, cB = dA.clone(), dB.clone()
+    s.synchronize()
+    assert torch.equal(cA, ref_a) and torch.equal(cB, ref_b)
+
+
 @pytest.mark.parametrize("checkpoint", [True, False])
 def test_autograd_checkpoint_modes_agree(checkpoint):
     dev = cuda_or_skip()

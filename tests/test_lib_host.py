@@ -52,7 +52,8 @@ def test_workspace_bytes(lib):
     align = lambda x: (x + 255) // 256 * 256
     assert fwd == 256 + align(M * K * 8) + align(K * N * 8)
     bwd = lib.tcu_workspace_bytes(C.byref(A), C.byref(B), M, K, N, 0, _lib.TCU_WS_BACKWARD)
-    assert bwd == fwd + align(max(M * K, K * N) * 8)
+    # backward: separate dX (M x K) and dY (K x N) buffers
+    assert bwd == fwd + align(M * K * 8) + align(K * N * 8)
     assert lib.tcu_workspace_bytes(C.byref(A), C.byref(B), 0, K, N, 0, 0) == 0
     assert lib.tcu_workspace_bytes(C.byref(A), C.byref(B), M, K, N, 7, 0) == 0
 
