@@ -5,6 +5,8 @@ W: nn, nt, tn or tt runs tcu_gemm_f64 on N x N operands (uniform [-1, 1));
    fp64, split_i8, split_bf16 or crt_i8 runs the forward operator on the MM-query
    tables of N x N records with log-uniform values (seed 3), tol 1e-12.
 N: matrix edge (default 4096).  R: repetitions (default 3).
+A fifth argument "calib" adds one plain 512 MiB device copy (runtime copy
+kernels), whose counter readings calibrate the memory counters of the pass.
 """
 import ctypes as C
 import sys
@@ -36,6 +38,11 @@ def main(argv):
         for _ in range(reps):
             ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, N, N, N,
                              precision=which, tol=1e-12, unique=True)
+    if len(argv) > 4 and argv[4] == "calib":
+        src = torch.empty(64 << 20, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)  # reads 512 MiB, writes 512 MiB
     torch.cuda.synchronize()
     print("done", which, N, reps, flush=True)
 
