@@ -159,40 +159,75 @@ __device__ inline int64_t slice_offset(int line, int t, int lines_pad) {
     return (((int64_t)kb * 2 + h) * lines_pad + line) * half + (t % half);
 }
 
-// Lines are rows: each thread handles 8 consecutive elements of one row and
-// writes 8 digits per slice; padding rows and columns get zero digits.
+// 16 consecutive digits of one line (positions t0 .. t0 + 15, t0 a multiple
+// of 16) at their slice-layout place: one 16-byte store for int8 (one half
+// k-step), two for BF16 (the two halves of one k-step).
+__device__ inline void store16(int8_t *slice, int line, int t0, int lines_pad,
+                               const int8_t (&d)[16]) {
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        w[q] = (uint32_t)(uint8_t)d[4 * q] | ((uint32_t)(uint8_t)d[4 * q + 1] << 8) |
+               ((uint32_t)(uint8_t)d[4 * q + 2] << 16) | ((uint32_t)(uint8_t)d[4 * q + 3] << 24);
+    *reinterpret_cast<uint4 *>(slice + slice_offset<int8_t>(line, t0, lines_pad)) =
+        make_uint4(w[0], w[1], w[2], w[3]);
+}
+__device__ inline void store16(uint16_t *slice, int line, int t0, int lines_pad,
+                               const uint16_t (&d)[16]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        uint4 v;
+        v.x = (uint32_t)d[8 * h] | ((uint32_t)d[8 * h + 1] << 16);
+        v.y = (uint32_t)d[8 * h + 2] | ((uint32_t)d[8 * h + 3] << 16);
+        v.z = (uint32_t)d[8 * h + 4] | ((uint32_t)d[8 * h + 5] << 16);
+        v.w = (uint32_t)d[8 * h + 6] | ((uint32_t)d[8 * h + 7] << 16);
+        *reinterpret_cast<uint4 *>(slice + slice_offset<uint16_t>(line, t0 + 8 * h, lines_pad)) = v;
+    }
+}
+
+// Lines are rows.  One workgroup per 64 lines x 64 positions (grid: len_pad /
+// 64, lines_pad / 64): the tile is read row-contiguously into padded LDS,
+// then thread (r, g) = (t % 64, t / 64) takes positions 16 g .. 16 g + 15 of
+// line l0 + r, so a wave's stores of one slice are one contiguous run per
+// slice-layout plane.  Padding rows and columns get zero digits.
 template <typename T, int S>
 __global__ void __launch_bounds__(kThreads)
 split_rows_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
                   const unsigned long long *__restrict__ maxbits, T *__restrict__ out,
                   int lines_pad, int len_pad, int *__restrict__ exps) {
-    const int groups = len_pad / 8;
-    const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (gid >= (int64_t)lines_pad * groups) return;
-    const int row = (int)(gid / groups);
-    const int c0 = (int)(gid % groups) * 8;
-    const bool live = row < rows;
-    const int e = live ? line_exponent(maxbits[row]) : 0;
-    if (live && c0 == 0) exps[row] = e;
-    T dig[S][8];
+    __shared__ double tile[64][64 + 2];  // [line][position]; the pad spreads lines over banks
+    const int p0 = blockIdx.x * 64, l0 = blockIdx.y * 64;
+    const int t = threadIdx.x;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int c = c0 + j;
-        double z = (live && c < cols) ? Z[(int64_t)row * ld + c] : 0.0;
+    for (int j = 0; j < 16; ++j) {
+        const int lr = (t >> 6) + 4 * j, pc = t & 63;
+        const int row = l0 + lr, c = p0 + pc;
+        tile[lr][pc] = (row < rows && c < cols) ? Z[(int64_t)row * ld + c] : 0.0;
+    }
+    __syncthreads();
+    const int r = t & 63, g = t >> 6;
+    const int line = l0 + r;
+    const bool live = line < rows;
+    const int e = live ? line_exponent(maxbits[line]) : 0;
+    if (live && blockIdx.x == 0 && g == 0) exps[line] = e;
+    T dig[S][16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        double z = tile[r][16 * g + j];
         if (!isfinite(z)) z = 0.0;
-        double r = ldexp(z, -e);
+        double rem = ldexp(z, -e);
 #pragma unroll
         for (int p = 0; p < S; ++p) {
-            const double t = ldexp(r, kDigitBits);
-            const double d = trunc(t);
+            const double tt = ldexp(rem, kDigitBits);
+            const double d = trunc(tt);
             dig[p][j] = to_digit<T>(d);
-            r = t - d;
+            rem = tt - d;
         }
     }
     const int64_t slice_stride = (int64_t)lines_pad * len_pad;
-    T *o = out + slice_offset<T>(row, c0, lines_pad);
 #pragma unroll
-    for (int p = 0; p < S; ++p) store8(o + (int64_t)p * slice_stride, dig[p]);
+    for (int p = 0; p < S; ++p)
+        store16(out + (int64_t)p * slice_stride, line, p0 + 16 * g, lines_pad, dig[p]);
 }
 
 // Lines are columns: a block turns a 64 x 64 tile of Z into S tiles of
@@ -246,8 +281,7 @@ hipError_t launch_split_s(const double *Z, int rows, int cols, int64_t ld, int a
                           const unsigned long long *maxbits, T *out, int lines_pad, int len_pad,
                           int *exps, hipStream_t s) {
     if (axis == 0) {
-        const int64_t work = (int64_t)lines_pad * (len_pad / 8);
-        const unsigned grid = (unsigned)((work + kThreads - 1) / kThreads);
+        dim3 grid(len_pad / 64, lines_pad / 64);
         split_rows_kernel<T, S><<<grid, kThreads, 0, s>>>(Z, rows, cols, ld, maxbits, out,
                                                           lines_pad, len_pad, exps);
     } else {
