@@ -215,8 +215,11 @@ tcu_status tcu_join_agg_fwd(const tcu_relation *A, const tcu_relation *B, int32_
  * guarantee with their own contraction length (N for dX, M for dY).  Needs a
  * workspace sized with TCU_WS_BACKWARD.  With both outputs, the gather of
  * dA_val (and, when re-encoding, the encoding of X) runs on the device's
- * internal stream beside the products on the caller's stream; the call
- * joins it back before returning control of the stream. */
+ * internal stream beside the products on the caller's stream; in the FP64
+ * form a dY product that fills more than one round of workgroups is cut
+ * into two row blocks, and the gather of the first block's dB_val entries
+ * joins that stream beside the second block's product.  The call joins the
+ * internal stream back before returning control of the stream. */
 tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_t M, int32_t K,
                             int32_t N, tcu_precision p, double tol, const double *dC,
                             double *dA_val, double *dB_val, int flags, void *ws,

@@ -388,6 +388,8 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
     // the matrix products on the caller's stream:
     //   caller: [encode Y] fork  dX = dC Y^T  ev_dx  ...wait ev_x  dY = X^T dC  wait ev_a  gather dB
     //   side:        wait fork  [encode X] ev_x  wait ev_dx  gather dA  ev_a
+    // (the FP64 dY product may be cut in two, its first part's dB gather
+    // joining the side stream; see below).
     // dX and dY live in separate buffers (G, G2), so nothing the two streams
     // run at the same time touches the same memory.
     const bool both = dA_val != nullptr && dB_val != nullptr;
@@ -434,15 +436,28 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
     if (dB_val != nullptr) {
         if (both && !saved) TCU_TRY(hipStreamWaitEvent(stream, ev_x, 0));  // X is encoded
         // dY = X^T * dC (K x N), then dB.val[j] = dY[k_j, h_j]
-        if (S2 == 0) {
+        // With both gradients, the FP64 product is cut into two row blocks
+        // when that costs no extra round of workgroups: the dB gather of the
+        // first block's records runs on the side stream beside the second
+        // block's product, and only the second block's gather stays behind.
+        const int k1 = (both && S2 == 0) ? gemm_f64_row_cut(K, N) : 0;
+        if (k1 > 0) {
+            TCU_TRY(launch_gemm_f64(1, 0, k1, N, M, X, K, dC, N, G2, N, stream));
+            TCU_TRY(hipEventRecord(ev_fork, stream));
+            TCU_TRY(hipStreamWaitEvent(side, ev_fork, 0));
+            TCU_TRY(launch_gather(*B, 1, K, N, G2, dB_val, side, 0, k1));
+            TCU_TRY(hipEventRecord(ev_a, side));
+            TCU_TRY(launch_gemm_f64(1, 0, K - k1, N, M, X + k1, K, dC, N, G2 + (size_t)k1 * N, N,
+                                    stream));
+        } else if (S2 == 0) {
             TCU_TRY(launch_gemm_f64(1, 0, K, N, M, X, K, dC, N, G2, N, stream));
         } else {
             // X^T: K lines = columns of X, length M; dC: N lines = columns, length M
             const SplitOperand a{X, M, K, K, 1}, b{dC, M, N, N, 1};
             TCU_TRY(split_product(a, b, K, N, M, S2, p, tol, ws, L, st, G2, N, stream));
         }
-        TCU_TRY(launch_gather(*B, 1, K, N, G2, dB_val, stream));
-        if (both) TCU_TRY(hipStreamWaitEvent(stream, ev_a, 0));  // join: dA is written
+        TCU_TRY(launch_gather(*B, 1, K, N, G2, dB_val, stream, k1, K));
+        if (both) TCU_TRY(hipStreamWaitEvent(stream, ev_a, 0));  // join: the side's gathers are done
     }
     return TCU_OK;
 }

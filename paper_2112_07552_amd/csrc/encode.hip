@@ -74,17 +74,18 @@ encode_kernel(int64_t n, const int32_t *__restrict__ grp, const int32_t *__restr
 
 __global__ void __launch_bounds__(kThreads)
 gather_kernel(int64_t n, const int32_t *__restrict__ grp, const int32_t *__restrict__ key,
-              int transpose, int rows, int cols, const double *__restrict__ src,
+              int transpose, int rows, int cols, int r0, int r1, const double *__restrict__ src,
               double *__restrict__ dst) {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
     const int g = grp[i], k = key[i];
     const int r = transpose ? k : g;
     const int c = transpose ? g : k;
-    double v = 0.0;
-    if ((unsigned)r < (unsigned)rows && (unsigned)c < (unsigned)cols)
-        v = src[(size_t)r * (size_t)cols + c];
-    dst[i] = v;
+    const bool valid = (unsigned)r < (unsigned)rows && (unsigned)c < (unsigned)cols;
+    // a launch covers the records whose row lies in [r0, r1); the one that
+    // starts at row 0 also writes the zeros of records outside the matrix
+    if (valid ? (r < r0 || r >= r1) : r0 != 0) return;
+    dst[i] = valid ? src[(size_t)r * (size_t)cols + c] : 0.0;
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -146,10 +147,11 @@ hipError_t launch_encode(const tcu_relation &R, int transpose, int rows, int col
 }
 
 hipError_t launch_gather(const tcu_relation &R, int transpose, int rows, int cols,
-                         const double *src, double *dst, hipStream_t s) {
+                         const double *src, double *dst, hipStream_t s, int r0, int r1) {
     if (R.n == 0) return hipSuccess;
+    if (r1 < 0) r1 = rows;
     gather_kernel<<<grid_for(R.n), kThreads, 0, s>>>(R.n, R.group, R.key, transpose, rows, cols,
-                                                     src, dst);
+                                                     r0, r1, src, dst);
     return hipGetLastError();
 }
 

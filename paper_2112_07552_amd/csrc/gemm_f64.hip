@@ -348,6 +348,28 @@ hipError_t launch(int m, int n, int k, const double *A, int64_t lda, const doubl
 
 }  // namespace
 
+int gemm_f64_row_cut(int m, int n) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        return 0;
+    // two workgroups per CU: each is 4 waves, and the kernel runs 2 waves per SIMD
+    const int64_t resident = 2 * (int64_t)cus;
+    const int64_t rt = (m + BM - 1) / BM, ct = (n + BN - 1) / BN;
+    auto rounds = [&](int64_t tiles) { return (tiles + resident - 1) / resident; };
+    const int64_t whole = rounds(rt * ct);
+    if (whole < 2) return 0;
+    // the most even cut among those that add no round
+    auto skew = [&](int64_t r) { return 2 * r > rt ? 2 * r - rt : rt - 2 * r; };
+    int64_t best = 0;
+    for (int64_t r = 1; r < rt; ++r) {
+        if (rounds(r * ct) + rounds((rt - r) * ct) != whole) continue;
+        if (best == 0 || skew(r) < skew(best)) best = r;
+    }
+    return (int)(best * BM);
+}
+
 hipError_t launch_gemm_f64(int trans_a, int trans_b, int m, int n, int k, const double *A,
                            int64_t lda, const double *B, int64_t ldb, double *C, int64_t ldc,
                            hipStream_t s, int accumulate) {

@@ -32,8 +32,12 @@ hipError_t launch_zero_f64(double *p, size_t n, hipStream_t s);
 hipError_t launch_clear_status(StatusBlock *st, hipStream_t s, uint32_t slices = 0);
 hipError_t launch_encode(const tcu_relation &R, int transpose, int rows, int cols, double *out,
                          StatusBlock *st, int which, hipStream_t s);
+// dst[i] = src[row_i, col_i] for the records whose row lies in [r0, r1)
+// (r1 < 0: all rows); the launch with r0 = 0 also writes 0 for records
+// outside the matrix.
 hipError_t launch_gather(const tcu_relation &R, int transpose, int rows, int cols,
-                         const double *src, double *dst, hipStream_t s);
+                         const double *src, double *dst, hipStream_t s, int r0 = 0,
+                         int r1 = -1);
 hipError_t launch_f64_to_i32(const double *src, int32_t *dst, size_t n, hipStream_t s);
 
 // split.hip: per-line max |z| (axis 0: rows, 1: columns) into maxbits (bit
@@ -63,6 +67,11 @@ int split_chunk_steps(int S, int digit_bf16);
 hipError_t launch_gemm_f64(int trans_a, int trans_b, int m, int n, int k, const double *A,
                            int64_t lda, const double *B, int64_t ldb, double *C, int64_t ldc,
                            hipStream_t s, int accumulate = 0);
+// Rows m1 (a multiple of the tile height, 0 < m1 < m) at which an m x n FP64
+// product can be cut into two launches that together take no more rounds of
+// concurrently resident workgroups than one launch; 0 when no such cut exists
+// or the product fills at most one round.
+int gemm_f64_row_cut(int m, int n);
 
 // dict.hip: dictionary encoding (ranks in the sorted union of two columns).
 size_t dict_workspace_bytes(int64_t n);

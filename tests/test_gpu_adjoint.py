@@ -112,6 +112,35 @@ def test_bwd_stream_ordered_on_a_side_stream(saved):
     assert torch.equal(cA, ref_a) and torch.equal(cB, ref_b)
 
 
+def test_bwd_cut_dy_product_matches_uncut(orc):
+    """dY = X^T W large enough for more than one round of GEMM workgroups
+    (K x N = 2200 x 4000 is 18 x 32 tiles of 128 x 128): with both gradients
+    the FP64 product is cut into two row blocks whose dB gathers run on two
+    streams.  Each entry of dY is the same dot product either way, so dB
+    equals the one-gradient call (one launch, one gather) bit for bit;
+    records outside the matrices get 0; sampled records match the oracle."""
+    dev = cuda_or_skip()
+    M, K, N = 64, 2200, 4000
+    A = wl.random_relation(100_000, M, K, 37, 1, device=dev, bad_fraction=0.01)
+    B = wl.random_relation(2_000_000, N, K, 37, 2, device=dev, bad_fraction=0.01)
+    W = wl.draw_values("uniform", M * N, 37, 99, device=dev).reshape(M, N)
+    _, _, ws = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, M, K, N,
+                                for_backward=True)
+    args = (A.group, A.key, A.val, B.key, B.group, B.val, M, K, N, W)
+    dA, dB, _ = ops.join_agg_bwd(*args, ws=ws, saved_encodings=True)
+    _, dB1, _ = ops.join_agg_bwd(*args, ws=ws, saved_encodings=True, need_a=False)
+    dA1, _, _ = ops.join_agg_bwd(*args, ws=ws, saved_encodings=True, need_b=False)
+    torch.cuda.synchronize(dev)
+    assert torch.equal(dB, dB1) and torch.equal(dA, dA1)
+    badB = ((B.group < 0) | (B.group >= N) | (B.key < 0) | (B.key >= K)).cpu().numpy()
+    assert badB.any() and np.all(dB.cpu().numpy()[badB] == 0.0)
+    rng = np.random.default_rng(37)
+    ia = rng.choice(A.n, 2000, replace=False).astype(np.int64)
+    ib = rng.choice(B.n, 4000, replace=False).astype(np.int64)
+    ea, eb = grad_errors(orc, A, B, W, M, K, N, dA, dB, ia, ib)
+    assert ea <= TOL and eb <= TOL, (ea, eb)
+
+
 @pytest.mark.parametrize("checkpoint", [True, False])
 def test_autograd_checkpoint_modes_agree(checkpoint):
     dev = cuda_or_skip()
