@@ -504,7 +504,7 @@ def main():
                          "profiler byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark measures the single-GPU path only (multi-GPU sharding is not implemented); --gpus must be 1"}))
         sys.exit(2)
 
     import numpy as np
