@@ -13,6 +13,7 @@ import torch
 
 from paper_2112_07552_amd import ops
 from paper_2112_07552_amd import workloads as wl
+from .paper_tables import error_table
 
 from .gpu_util import (TOL, abs_rel, cuda_or_skip, dense_relation_from_matrix, describe_worst,
                        err_cw, to_orc)
@@ -266,11 +267,12 @@ def test_fwd_2pow20_records(orc):
     assert sampled_checks(orc, A, B, Cg, N, N, N, seed=1, nrows=48) <= TOL
 
 
-@pytest.mark.parametrize("lo,hi", [(0, 2), (-2**7, 2**7), (-2**15, 2**15)])
+@pytest.mark.parametrize("lo,hi", [(lo, hi) for lo, hi, _ in error_table()[1] if hi <= 2**15])
 def test_fwd_integer_values_bit_exact(orc, lo, hi):
-    """Rows of the paper's MAPE table (Section 5.4.1, Table 'error'): with
+    """Rows of Table "error" (Section 5.4.1, read from tests/golden/): with
     integer values every partial sum is an exact integer, so the FP64 path
-    must be exact where the paper's 16-bit units were not (N = 2048)."""
+    must be exact where the paper's 16-bit units were not (N = 2048, the
+    table's smallest size)."""
     dev = cuda_or_skip()
     N = 2048
     A, B = wl.mm_query(N, N, N, seed=7, values="int", lo=lo, hi=hi, device=dev)

@@ -13,6 +13,7 @@ from paper_2112_07552_amd import ops
 from paper_2112_07552_amd import workloads as wl
 
 from .gpu_util import abs_rel, cuda_or_skip, err_cw, to_orc
+from .paper_tables import error_table
 
 pytestmark = pytest.mark.gpu
 
@@ -112,11 +113,11 @@ def test_split_dense_workload_2pow20(orc, precision):
 
 
 @pytest.mark.parametrize("precision", ALL_FORMS)
-@pytest.mark.parametrize("lo,hi", [(0, 2), (-2**15, 2**15)])
+@pytest.mark.parametrize("lo,hi", [(lo, hi) for lo, hi, _ in error_table()[1] if hi <= 2**15])
 def test_split_integer_values_exact(orc, precision, lo, hi):
     """Integer inputs below 2^15 need at most 3 digits; with 7 slices every
     nonzero digit pair is kept and all sums are exact integers, so C is
-    exact (the rows of the paper's MAPE table, Section 5.4.1)."""
+    exact (the rows of Table "error", Section 5.4.1, read from tests/golden/)."""
     dev = cuda_or_skip()
     N = 512
     A, B = wl.mm_query(N, N, N, seed=8, values="int", lo=lo, hi=hi, device=dev)

@@ -15,6 +15,8 @@ import torch
 
 from paper_2112_07552_amd import workloads as wl
 
+from .paper_tables import error_table
+
 U = 2.0 ** -53  # unit roundoff of binary64
 
 
@@ -127,11 +129,11 @@ def test_dense_tables_match_library_dgemm(orc, M, K, N):
     assert np.all(np.abs(C - ref) <= 2 * K * U * scale + 1e-300)
 
 
-@pytest.mark.parametrize("lo,hi", [(0, 2), (-2**7, 2**7), (-2**15, 2**15)])
+@pytest.mark.parametrize("lo,hi", [(lo, hi) for lo, hi, _ in error_table()[1] if hi <= 2**15])
 def test_integer_values_exact(orc, lo, hi):
-    """Integer-valued inputs (rows of the paper's MAPE table, Section 5.4.1):
-    every partial sum is an integer below 2^53, so C is exact; int64 matmul is
-    the exact reference."""
+    """Integer-valued inputs (the rows of Table "error", Section 5.4.1, read
+    from tests/golden/): every partial sum is an integer below 2^53, so C is
+    exact; int64 matmul is the exact reference."""
     M = K = N = 96
     A, B = wl.mm_query(M, K, N, seed=6, values="int", lo=lo, hi=hi)
     Xi = np.zeros((M, K), dtype=np.int64)
@@ -140,6 +142,35 @@ def test_integer_values_exact(orc, lo, hi):
     Yi[B.key.numpy(), B.group.numpy()] = B.val.numpy().astype(np.int64)
     C, _, _ = orc.join_agg(to_rel(orc, A), to_rel(orc, B), M, K, N)
     assert np.array_equal(C, (Xi @ Yi).astype(np.float64))
+
+
+def test_error_table_rows_against_exact_integers(orc):
+    """Every row of Table "error" (Section 5.4.1, tests/golden/): on integer
+    inputs of that range the oracle's MAPE against exact big-integer C is at
+    most the paper's figure at every size; below 2^15 it is 0, and for the
+    +-2^31 row (products up to 2^62, not representable in binary64) the
+    compensated dot product stays within a few units in the last place."""
+    sizes, rows = error_table()
+    assert sizes == [2048, 4096, 8192, 16384, 32768]
+    M = K = N = 40
+    for lo, hi, paper in rows:
+        A, B = wl.mm_query(M, K, N, seed=9, values="int", lo=lo, hi=hi)
+        Xo = np.zeros((M, K), dtype=object)
+        Yo = np.zeros((K, N), dtype=object)
+        for g, k, v in zip(A.group.tolist(), A.key.tolist(), A.val.tolist()):
+            Xo[g, k] = int(v)
+        for k, h, v in zip(B.key.tolist(), B.group.tolist(), B.val.tolist()):
+            Yo[k, h] = int(v)
+        exact = Xo.dot(Yo)                       # Python integers, exact
+        C, _, _ = orc.join_agg(to_rel(orc, A), to_rel(orc, B), M, K, N)
+        rel = [abs(Fraction(float(c)) - e) / abs(e)
+               for c, e in zip(C.ravel().tolist(), exact.ravel().tolist()) if e != 0]
+        mape = 100.0 * float(sum(rel) / len(rel))
+        assert all(mape <= p for p in paper)
+        if hi <= 2**15:
+            assert mape == 0.0
+        else:
+            assert max(rel) <= 4 * Fraction(U), float(max(rel))
 
 
 def test_lemma_q3_column_sums(orc):
