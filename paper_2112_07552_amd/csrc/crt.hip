@@ -57,11 +57,14 @@ typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 // The symmetric residues of four int32 sums as four int8 bytes of one word.
 // SMALL: every |x| <= 2^26; otherwise x is first replaced by the congruent
 // r1 = (x >> 16)(2^16 mod m) + (x & 0xffff), |r1| < 2^24 (c16 = 2^16 mod m;
-// checked exhaustively over all int32 x for each modulus).  Then
-// q = rint(x * (1/m)) in float is within
-// 0.57 of x / m, r = x - q m (24-bit multiply-add) lies within 0.57 m of 0,
-// and the symmetric range follows from d = r - lo (mod 2^16) with two
-// unsigned 16-bit minimums, min(d, d + m) then min(d, d - m), on two
+// checked exhaustively over all int32 x for each modulus).  Then the
+// quotient q, x * (1/m) rounded to an integer in float, is within 0.57 of
+// x / m.  It comes from one FMA: adding 1.5 * 2^23 to the product makes
+// the rounding land on integers, so the low 24 bits of the sum's encoding
+// are 2^22 + q.  The 24-bit multiply-add x - (2^22 + q) m then equals
+// r - 2^22 m with r = x - q m within 0.57 m of 0, and 2^22 m vanishes
+// modulo 2^16.  The symmetric range follows from d = r - lo (mod 2^16) with
+// two unsigned 16-bit minimums, min(d, d + m) then min(d, d - m), on two
 // residues per instruction.  (Checked exhaustively for |x| <= 2^26 and
 // every modulus.)
 template <bool SMALL>
@@ -70,8 +73,8 @@ __device__ inline uint32_t sym_mod32x4(const int (&x)[4], int m, int c16, float 
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int v = SMALL ? x[j] : __mul24(x[j] >> 16, c16) + (x[j] & 0xffff);
-        const int q = (int)rintf((float)v * inv);
-        r[j] = __mul24(q, -m) + v;
+        const int q22 = __float_as_int(fmaf((float)v, inv, 0x1.8p23f));  // low 24 bits: 2^22 + q
+        r[j] = __mul24(q22, -m) + v;
     }
     const unsigned short lo = (unsigned short)(-(m >> 1)), mm = (unsigned short)m;
     const u16x2 lo2 = {lo, lo}, m2 = {mm, mm};
@@ -116,6 +119,15 @@ __device__ inline Pieces pieces(double z, int shift) {
     return Pieces{(int)h, (int)mid, (int)fma(-mid, 0x1p18, t)};
 }
 
+// a * b + c with a and b taken as signed 24-bit integers, one instruction
+// (written out because the compiler turns two of them into two multiplies
+// and a three-way add); b is wave-uniform
+__device__ inline int mad24(int a, int b, int c) {
+    int d;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "s"(b), "v"(c));
+    return d;
+}
+
 // residues modulo m_i of 16 pieces, as one 16-byte vector
 __device__ inline uint4 residues16(const Pieces (&p)[16], const CrtConsts &cc, int i) {
     const int m = cc.mi[i], c18 = cc.c18[i], c36 = cc.c36[i];
@@ -127,7 +139,7 @@ __device__ inline uint4 residues16(const Pieces (&p)[16], const CrtConsts &cc, i
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const Pieces &z = p[4 * q + j];
-            x[j] = __mul24(z.z2, c36) + __mul24(z.z1, c18) + z.z0;
+            x[j] = mad24(z.z1, c18, mad24(z.z2, c36, z.z0));
         }
         w[q] = sym_mod32x4<true>(x, m, 0, inv);
     }
