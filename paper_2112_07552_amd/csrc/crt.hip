@@ -49,7 +49,7 @@ struct CrtConsts {
     float inv_f[kMaxMod];           // 1 / m_i rounded to float
     double w[kMaxMod][3];  // w_i = w2 2^80 + w1 2^40 + w0
     double Mp[3];          // M in the same limbs
-    double Md;             // M rounded to double
+    double inv_M;          // 1 / M rounded to double
 };
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
@@ -468,12 +468,15 @@ gemm_crt_kernel(int m, int n, int nblk, int tiles_m, int tiles_n, const int8_t *
 constexpr double kLimb = 1099511627776.0;  // 2^40
 
 // P from S = s2 2^80 + s1 2^40 + s0 (exact limb sums of r_i w_i):
-// q = round(S / M) (|P| < M / 4, so rounding errors cannot move q), the
-// limbs of S - q M exactly, balanced carries (|p0|, |p1| <= 2^39, so the sum
-// rounds only at the end), one double.
+// q = round(S / M), the limbs of S - q M exactly, balanced carries (|p0|,
+// |p1| <= 2^39, so the sum rounds only at the end), one double.  S / M lies
+// within 1/4 of the integer q (|P| < M / 4) and below 15 * 128 in magnitude;
+// the roundings of sd (absolute error below 2^40, against M > 2^100) and of
+// sd * (1/M) (relative error under 3 * 2^-53) move it by less than 1e-12, so
+// a multiply by the reciprocal gives the same q as the division.
 __device__ inline double crt_finish(double s0, double s1, double s2, const CrtConsts &cc) {
     const double sd = fma(s2, kLimb * kLimb, fma(s1, kLimb, s0));
-    const double q = rint(sd / cc.Md);
+    const double q = rint(sd * cc.inv_M);
     double p0 = fma(-q, cc.Mp[0], s0), p1 = fma(-q, cc.Mp[1], s1), p2 = fma(-q, cc.Mp[2], s2);
     double c = rint(p0 * (1.0 / kLimb));
     p0 = fma(-c, kLimb, p0);
@@ -577,7 +580,7 @@ CrtConsts make_consts(int L, int bits) {
     cc.Mp[0] = (double)(uint64_t)(M & mask);
     cc.Mp[1] = (double)(uint64_t)((M >> 40) & mask);
     cc.Mp[2] = (double)(uint64_t)(M >> 80);
-    cc.Md = (double)M;
+    cc.inv_M = 1.0 / (double)M;
     return cc;
 }
 

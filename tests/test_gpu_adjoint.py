@@ -141,6 +141,29 @@ def test_bwd_cut_dy_product_matches_uncut(orc):
     assert ea <= TOL and eb <= TOL, (ea, eb)
 
 
+def test_bwd_cut_dy_product_checkpointed_matches_uncut(orc):
+    """The cut dY product with the encodings rebuilt inside the call (X on
+    the internal stream, waited for before dY): dense tables with unique
+    cells encode deterministically, so both gradients match the
+    one-gradient calls bit for bit."""
+    dev = cuda_or_skip()
+    M, K, N = 96, 2200, 4000
+    A, B = wl.mm_query(M, K, N, seed=38, device=dev)
+    W = wl.draw_values("uniform", M * N, 38, 99, device=dev).reshape(M, N)
+    args = (A.group, A.key, A.val, B.key, B.group, B.val, M, K, N, W)
+    dA, dB, ws = ops.join_agg_bwd(*args, unique=True)
+    assert ops.sync_status(ws)[0] == 0
+    _, dB1, _ = ops.join_agg_bwd(*args, unique=True, need_a=False)
+    dA1, _, _ = ops.join_agg_bwd(*args, unique=True, need_b=False)
+    torch.cuda.synchronize(dev)
+    assert torch.equal(dB, dB1) and torch.equal(dA, dA1)
+    rng = np.random.default_rng(38)
+    ia = rng.choice(A.n, 2000, replace=False).astype(np.int64)
+    ib = rng.choice(B.n, 4000, replace=False).astype(np.int64)
+    ea, eb = grad_errors(orc, A, B, W, M, K, N, dA, dB, ia, ib)
+    assert ea <= TOL and eb <= TOL, (ea, eb)
+
+
 @pytest.mark.parametrize("checkpoint", [True, False])
 def test_autograd_checkpoint_modes_agree(checkpoint):
     dev = cuda_or_skip()
