@@ -161,11 +161,20 @@ crt_rows_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
     __shared__ double tile[64][64 + 2];  // [line][position]; the pad spreads lines over banks
     const int p0 = blockIdx.x * 64, l0 = blockIdx.y * 64;
     const int t = threadIdx.x;
+    // element offset of this thread's load j, advanced by 4 rows per load
+    // (a running 64-bit sum instead of a 64-bit product per load)
+    int64_t off = (int64_t)(l0 + (t >> 6)) * ld + p0 + (t & 63);
+    const int64_t step = 4 * ld;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const int lr = (t >> 6) + 4 * j, pc = t & 63;
         const int row = l0 + lr, c = p0 + pc;
-        tile[lr][pc] = (row < rows && c < cols) ? Z[(int64_t)row * ld + c] : 0.0;
+        // every lane loads (element 0 stands in outside the matrix), so the
+        // sixteen loads are in flight together instead of one branch each
+        const bool in = row < rows && c < cols;
+        const double v = Z[in ? off : 0];
+        tile[lr][pc] = in ? v : 0.0;
+        off += step;
     }
     __syncthreads();
     const int r = t & 63, g = t >> 6;
@@ -193,11 +202,12 @@ crt_cols_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
     const int e = col < cols ? line_exp(maxbits[col]) : 0;
     if (col < cols && blockIdx.x == 0 && g == 0) exps[col] = e;
     Pieces pc[16];
+    int64_t off = (int64_t)(p0 + 16 * g) * ld + col;  // advanced by one row per load
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int row = p0 + 16 * g + k;
-        pc[k] = pieces((row < rows && col < cols) ? Z[(int64_t)row * ld + col] : 0.0,
-                       cc.bits - e);
+        pc[k] = pieces((row < rows && col < cols) ? Z[off] : 0.0, cc.bits - e);
+        off += ld;
     }
     const int64_t plane = (int64_t)lines_pad * len_pad;
     int8_t *o = out + res_offset(col, p0 + 16 * g, lines_pad);
@@ -601,7 +611,8 @@ int crt_len_align() { return kCrtLenAlign; }
 hipError_t launch_crt_split(const double *Z, int rows, int cols, int64_t ld, int axis,
                             const unsigned long long *maxbits, int L, int bits, int8_t *out,
                             int lines_pad, int len_pad, int *exps, hipStream_t s) {
-    if (lines_pad % 64 || len_pad % 64) return hipErrorInvalidValue;
+    // the row kernel reads element 0 in place of positions outside the matrix
+    if (rows < 1 || cols < 1 || lines_pad % 64 || len_pad % 64) return hipErrorInvalidValue;
     const CrtConsts cc = make_consts(L, bits);
     const dim3 grid((unsigned)(len_pad / 64), (unsigned)(lines_pad / 64));
     if (axis == 0)

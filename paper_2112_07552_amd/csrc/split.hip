@@ -97,18 +97,20 @@ col_max_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
         double m[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         const double *z = Z + col;
         int r = r0;
+        int64_t off = (int64_t)r0 * ld;  // element offset of row r (a running sum)
         for (; r + 7 < r1; r += 8) {
             double v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = z[(int64_t)(r + u) * ld];
+            for (int u = 0; u < 8; ++u) v[u] = z[off + u * ld];
+            off += 8 * ld;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 bad |= !isfinite(v[u]);
                 m[u] = fmax(m[u], fabs(v[u]));
             }
         }
-        for (; r < r1; ++r) {
-            const double v = z[(int64_t)r * ld];
+        for (; r < r1; ++r, off += ld) {
+            const double v = z[off];
             bad |= !isfinite(v);
             m[0] = fmax(m[0], fabs(v));
         }
@@ -198,11 +200,19 @@ split_rows_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
     __shared__ double tile[64][64 + 2];  // [line][position]; the pad spreads lines over banks
     const int p0 = blockIdx.x * 64, l0 = blockIdx.y * 64;
     const int t = threadIdx.x;
+    // element offset of this thread's load j, advanced by 4 rows per load
+    int64_t off = (int64_t)(l0 + (t >> 6)) * ld + p0 + (t & 63);
+    const int64_t step = 4 * ld;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const int lr = (t >> 6) + 4 * j, pc = t & 63;
         const int row = l0 + lr, c = p0 + pc;
-        tile[lr][pc] = (row < rows && c < cols) ? Z[(int64_t)row * ld + c] : 0.0;
+        // every lane loads (element 0 stands in outside the matrix), so the
+        // sixteen loads are in flight together instead of one branch each
+        const bool in = row < rows && c < cols;
+        const double v = Z[in ? off : 0];
+        tile[lr][pc] = in ? v : 0.0;
+        off += step;
     }
     __syncthreads();
     const int r = t & 63, g = t >> 6;
@@ -246,9 +256,21 @@ split_cols_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
     const int col = c0 + tc;
     const int e = col < cols ? line_exponent(maxbits[col]) : 0;
     if (blockIdx.x == 0 && tr == 0 && col < cols) exps[col] = e;
-    for (int rr = tr; rr < kTile; rr += 4) {
-        const int row = r0 + rr;
-        double z = (row < rows && col < cols) ? Z[(int64_t)row * ld + col] : 0.0;
+    // all sixteen loads first, branch-free (element 0 stands in outside the
+    // matrix), so they are in flight together
+    double zv[kTile / 4];
+    int64_t off = (int64_t)(r0 + tr) * ld + col;  // advanced by 4 rows per load
+#pragma unroll
+    for (int u = 0; u < kTile / 4; ++u) {
+        const bool in = r0 + tr + 4 * u < rows && col < cols;
+        const double v = Z[in ? off : 0];
+        zv[u] = in ? v : 0.0;
+        off += 4 * ld;
+    }
+#pragma unroll
+    for (int u = 0; u < kTile / 4; ++u) {
+        const int rr = tr + 4 * u;
+        double z = zv[u];
         if (!isfinite(z)) z = 0.0;
         double r = ldexp(z, -e);
 #pragma unroll
@@ -327,7 +349,9 @@ hipError_t launch_line_max(const double *Z, int rows, int cols, int64_t ld, int 
 hipError_t launch_split(const double *Z, int rows, int cols, int64_t ld, int axis,
                         const unsigned long long *maxbits, int S, int digit_bf16, void *out,
                         int lines_pad, int len_pad, int *exps, hipStream_t s) {
-    if (lines_pad % 128 != 0 || len_pad % 64 != 0) return hipErrorInvalidValue;
+    // the row kernel reads element 0 in place of positions outside the matrix
+    if (rows < 1 || cols < 1 || lines_pad % 128 != 0 || len_pad % 64 != 0)
+        return hipErrorInvalidValue;
     if (digit_bf16)
         return launch_split_t<uint16_t>(Z, rows, cols, ld, axis, maxbits, S,
                                         static_cast<uint16_t *>(out), lines_pad, len_pad, exps,
