@@ -233,9 +233,14 @@ hipError_t side_stream(hipStream_t *out) {
 }
 
 // Events of one adjoint call, destroyed when the call returns (the runtime
-// keeps a recorded event alive until the work it marks has run).
+// keeps a recorded event alive until the work it marks has run).  Once work
+// has been forked to the internal stream, leaving the call without the
+// normal join (an early error return) still orders the caller's stream after
+// everything queued there, since that work writes the caller's buffers.
 struct CallEvents {
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    hipStream_t side = nullptr, caller = nullptr;
+    bool joined = false;
     hipError_t create() {
         for (hipEvent_t &e : ev) {
             const hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableTiming);
@@ -243,7 +248,19 @@ struct CallEvents {
         }
         return hipSuccess;
     }
+    void forked(hipStream_t s, hipStream_t c) {
+        side = s;
+        caller = c;
+    }
+    // the caller's stream waits for `e`, recorded after the side's last work
+    hipError_t join(hipEvent_t e) {
+        joined = true;
+        return hipStreamWaitEvent(caller, e, 0);
+    }
     ~CallEvents() {
+        if (side != nullptr && !joined && ev[2] != nullptr &&
+            hipEventRecord(ev[2], side) == hipSuccess)
+            (void)hipStreamWaitEvent(caller, ev[2], 0);
         for (hipEvent_t e : ev)
             if (e != nullptr) (void)hipEventDestroy(e);
     }
@@ -408,6 +425,7 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
         if (both) {
             TCU_TRY(hipEventRecord(ev_fork, stream));
             TCU_TRY(hipStreamWaitEvent(side, ev_fork, 0));
+            evs.forked(side, stream);
             TCU_TRY(encode_one(*A, 0, M, K, X, st, side));
             TCU_TRY(hipEventRecord(ev_x, side));
         } else {
@@ -427,6 +445,7 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
             // ev_fork is free again once the side stream has waited for it
             TCU_TRY(hipEventRecord(ev_fork, stream));
             TCU_TRY(hipStreamWaitEvent(side, ev_fork, 0));
+            evs.forked(side, stream);
             TCU_TRY(launch_gather(*A, 0, M, K, G, dA_val, side));
             TCU_TRY(hipEventRecord(ev_a, side));
         } else {
@@ -457,7 +476,7 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
             TCU_TRY(split_product(a, b, K, N, M, S2, p, tol, ws, L, st, G2, N, stream));
         }
         TCU_TRY(launch_gather(*B, 1, K, N, G2, dB_val, stream, k1, K));
-        if (both) TCU_TRY(hipStreamWaitEvent(stream, ev_a, 0));  // join: the side's gathers are done
+        if (both) TCU_TRY(evs.join(ev_a));  // the side's gathers are done
     }
     return TCU_OK;
 }
