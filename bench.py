@@ -67,6 +67,41 @@ def counter_traffic():
     return int(m.group(1))
 
 
+def sampled_errors(orc, RA, RB, W, N, Cm, dA, dB, seed, ncells, nrec=512):
+    """Errors of one forward + adjoint (C in Cm, gradients in dA, dB) against
+    the oracle on samples: the componentwise err_cw = |C - C*| / (|X||Y|) on
+    `ncells` random cells and on `nrec` random records of each gradient
+    (scaled by the oracle's gradient of |values| with |W|), the normwise ratio
+    |C - C*|_2 / |C*|_2 over the sampled cells, and the mean absolute
+    percentage error over the sampled cells with |C*| >= 1e-3 (|X||Y|)."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(seed)
+    cg = rng.integers(0, N, ncells).astype(np.int32)
+    ch = rng.integers(0, N, ncells).astype(np.int32)
+    RAa = orc.Rel(RA.group, RA.key, np.abs(RA.val))
+    RBa = orc.Rel(RB.group, RB.key, np.abs(RB.val))
+    vo, _ = orc.join_agg_cells(RA, RB, N, N, N, cg, ch)
+    so, _ = orc.join_agg_cells(RAa, RBa, N, N, N, cg, ch)
+    dev = Cm.device
+    c = Cm[torch.from_numpy(cg.astype(np.int64)).to(dev),
+           torch.from_numpy(ch.astype(np.int64)).to(dev)].cpu().numpy()
+    diff = np.abs(c - vo)
+    sig = np.abs(vo) >= 1e-3 * so
+    out = {"cells": ncells, "err_cw": float(np.max(diff / so)),
+           "normwise_sampled": float(np.linalg.norm(c - vo) / np.linalg.norm(vo)),
+           "mape_pct_sampled": float(100.0 * np.mean(diff[sig] / np.abs(vo[sig]))) if sig.any() else None,
+           "mape_cells": int(sig.sum()), "records": nrec}
+    Wn = W.cpu().numpy()
+    for name, R, g in (("dA", RA, dA), ("dB", RB, dB)):
+        idx = rng.choice(R.val.shape[0], nrec, replace=False).astype(np.int64)
+        ref = orc.grad(RA, RB, N, N, N, Wn, name[1], idx=idx)
+        scale = orc.grad(RAa, RBa, N, N, N, np.abs(Wn), name[1], idx=idx)
+        got = g[torch.from_numpy(idx).to(dev)].cpu().numpy()
+        out[f"err_cw_{name}"] = float(np.max(np.abs(got - ref) / scale))
+    return out
+
+
 def time_loop(fn, steps, warmup, stream):
     import torch
     for _ in range(warmup):
@@ -139,15 +174,6 @@ def bench_mixed(N, args, stream, log):
     W = wl.draw_values("uniform", N * N, 1003, 0, device=dev).reshape(N, N)
     RA = orc.Rel(A.group.cpu().numpy(), A.key.cpu().numpy(), A.val.cpu().numpy())
     RB = orc.Rel(B.group.cpu().numpy(), B.key.cpu().numpy(), B.val.cpu().numpy())
-    rng = np.random.default_rng(3)
-    cg = rng.integers(0, N, 512).astype(np.int32)
-    ch = rng.integers(0, N, 512).astype(np.int32)
-    vo, _ = orc.join_agg_cells(RA, RB, N, N, N, cg, ch)
-    so, _ = orc.join_agg_cells(orc.Rel(RA.group, RA.key, np.abs(RA.val)),
-                               orc.Rel(RB.group, RB.key, np.abs(RB.val)), N, N, N, cg, ch)
-
-    def err_of(Cm):
-        return float(np.max(np.abs(Cm.cpu().numpy()[cg, ch] - vo) / so))
 
     def run(precision, tol):
         relA = ops.make_relation(A.group, A.key, A.val, unique=True)
@@ -176,18 +202,20 @@ def bench_mixed(N, args, stream, log):
 
         t_fwd = time_loop(fwd, args.steps, args.warmup, stream)
         t_step = time_loop(step, args.steps, args.warmup, stream)
-        fwd()
+        step()
         st, info = ops.sync_status(ws)
         if st != 0:
             raise RuntimeError(f"mixed form status {st}")
-        return t_fwd, t_step, err_of(Cm), info["slices"]
+        errs = sampled_errors(orc, RA, RB, W, N, Cm, dA, dB, seed=3, ncells=512)
+        return t_fwd, t_step, errs["err_cw"], info["slices"], errs
 
     out = {"workload": f"MM query, dense {N}x{N} tables ({N * N} records each), values "
                        f"log-uniform on [1e-4, 1e4] with random sign, seed 3; forward and "
                        f"forward + adjoint"}
-    f64_fwd, f64_step, f64_err, _ = run("fp64", 0.0)
+    f64_fwd, f64_step, f64_err, _, f64_errs = run("fp64", 0.0)
     log(f"mixed workload fp64: fwd {f64_fwd:.3f} ms, fwd+adj {f64_step:.3f} ms, err {f64_err:.2e}")
-    out["fp64"] = {"ms_fwd": f64_fwd, "ms_fwd_adjoint": f64_step, "err_cw": f64_err}
+    out["fp64"] = {"ms_fwd": f64_fwd, "ms_fwd_adjoint": f64_step, "err_cw": f64_err,
+                   "errors": f64_errs}
     target = max(1e-12, f64_err)
     for precision in ("crt_i8", "split_i8", "split_bf16"):
         tol = 1e-12
@@ -204,13 +232,15 @@ def bench_mixed(N, args, stream, log):
             tol /= 128.0
         if best is None:
             continue
-        tol, t_fwd, t_step, err, S = best
+        tol, t_fwd, t_step, err, S, errs = best
         log(f"mixed workload {precision}: {'L' if precision == 'crt_i8' else 'S'}={S} "
             f"fwd {t_fwd:.3f} ms, fwd+adj {t_step:.3f} ms, err {err:.2e}")
         products = S if precision == "crt_i8" else S * (S + 1) // 2
         entry = {
             "tol": tol, "ms_fwd": t_fwd, "ms_fwd_adjoint": t_step, "err_cw": err,
-            "equal_accuracy": err <= target,
+            "errors": errs,
+            "equal_accuracy": err <= target and max(errs["err_cw_dA"], errs["err_cw_dB"]) <= max(
+                1e-12, f64_errs["err_cw_dA"], f64_errs["err_cw_dB"]),
             "speedup_fwd_vs_fp64": f64_fwd / t_fwd,
             "speedup_fwd_adjoint_vs_fp64": f64_step / t_step,
             "executed_ops_fwd": products * 2.0 * N ** 3,
@@ -588,22 +618,16 @@ def main():
     achieved = flops / (gemm_ms["nn"] * 1e-3) / 1e12
 
     result_err = None
+    errors = None
     if not args.no_check:
         from oracle import oracle as orc
-        fwd()
+        step()
         torch.cuda.synchronize()
         RA = orc.Rel(A.group.cpu().numpy(), A.key.cpu().numpy(), A.val.cpu().numpy())
         RB = orc.Rel(B.group.cpu().numpy(), B.key.cpu().numpy(), B.val.cpu().numpy())
-        RAa = orc.Rel(RA.group, RA.key, np.abs(RA.val))
-        RBa = orc.Rel(RB.group, RB.key, np.abs(RB.val))
-        rng = np.random.default_rng(0)
-        cg = rng.integers(0, N, 1024).astype(np.int32)
-        ch = rng.integers(0, N, 1024).astype(np.int32)
-        vo, _ = orc.join_agg_cells(RA, RB, N, N, N, cg, ch)
-        so, _ = orc.join_agg_cells(RAa, RBa, N, N, N, cg, ch)
-        Ch = Cm.cpu().numpy()
-        result_err = float(np.max(np.abs(Ch[cg, ch] - vo) / so))
-        log(f"err_cw on 1024 sampled cells: {result_err:.3e}")
+        errors = sampled_errors(orc, RA, RB, W, N, Cm, dA, dB, seed=0, ncells=1024)
+        result_err = errors["err_cw"]
+        log(f"errors of one step against the oracle: {errors}")
 
     mixed = None
     if not args.no_mixed:
@@ -674,6 +698,7 @@ def main():
         "checkpointed_elements_per_s": n_rec / (ms_ckpt * 1e-3),
         "ms_checkpointed": ms_ckpt,
         "err_cw_vs_oracle": result_err,
+        "errors_vs_oracle": errors,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_F64_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_F64_MFMA_TFLOPS,
                      "traffic": counter_traffic(),
