@@ -157,47 +157,69 @@ struct SplitOperand {
     int axis;
 };
 
-hipError_t split_product(const SplitOperand &a, const SplitOperand &b, int m, int n, int k,
-                         int S, tcu_precision p, double tol, void *ws, const Layout &L,
-                         StatusBlock *st, double *C, int64_t ldc, hipStream_t s) {
+// Plan of one mixed-form product: the slice count S (or modulus count, with
+// the truncation width `bits`), the padded contraction length and the padded
+// line counts of the two operands.
+struct MixedPlan {
+    int S = 0, bits = 0, len_pad = 0, la = 0, lb = 0;
+};
+
+hipError_t mixed_plan(int m, int n, int k, int S, tcu_precision p, double tol, MixedPlan *mp) {
+    mp->S = S;
     if (is_crt(p)) {
         int32_t bits = 0;
         const int nmod = crt_plan(k, tol, &bits);
         if (nmod != S) return hipErrorInvalidValue;  // the caller planned with the same k, tol
-        const int len_pad = (k + crt_len_align() - 1) / crt_len_align() * crt_len_align();
-        const int la = (int)pad256(m), lb = (int)pad256(n);
-        auto *mba = at<unsigned long long>(ws, L.mba);
-        auto *mbb = at<unsigned long long>(ws, L.mbb);
-        int *ea = at<int>(ws, L.ea), *eb = at<int>(ws, L.eb);
-        int8_t *sa = at<int8_t>(ws, L.sa), *sb = at<int8_t>(ws, L.sb);
-        hipError_t e = launch_line_max(a.Z, a.rows, a.cols, a.ld, a.axis, mba, st, s);
-        if (e == hipSuccess)
-            e = launch_crt_split(a.Z, a.rows, a.cols, a.ld, a.axis, mba, S, bits, sa, la, len_pad,
-                                 ea, s);
-        if (e == hipSuccess) e = launch_line_max(b.Z, b.rows, b.cols, b.ld, b.axis, mbb, st, s);
-        if (e == hipSuccess)
-            e = launch_crt_split(b.Z, b.rows, b.cols, b.ld, b.axis, mbb, S, bits, sb, lb, len_pad,
-                                 eb, s);
-        if (e == hipSuccess)
-            e = launch_gemm_crt(m, n, k, S, bits, sa, la, sb, lb, len_pad, at<int8_t>(ws, L.res),
-                                ea, eb, C, ldc, 0, s);
-        return e;
+        mp->bits = bits;
+        mp->len_pad = (k + crt_len_align() - 1) / crt_len_align() * crt_len_align();
+        mp->la = (int)pad256(m);
+        mp->lb = (int)pad256(n);
+    } else {
+        mp->len_pad = (int)pad64(k);
+        mp->la = (int)pad128(m);
+        mp->lb = (int)pad128(n);
     }
-    const int bf16 = p == TCU_PREC_SPLIT_BF16;
-    const int len_pad = (int)pad64(k);
-    const int la = (int)pad128(m), lb = (int)pad128(n);
-    auto *mba = at<unsigned long long>(ws, L.mba);
-    auto *mbb = at<unsigned long long>(ws, L.mbb);
-    int *ea = at<int>(ws, L.ea), *eb = at<int>(ws, L.eb);
-    void *sa = at<char>(ws, L.sa), *sb = at<char>(ws, L.sb);
-    hipError_t e = launch_line_max(a.Z, a.rows, a.cols, a.ld, a.axis, mba, st, s);
-    if (e == hipSuccess)
-        e = launch_split(a.Z, a.rows, a.cols, a.ld, a.axis, mba, S, bf16, sa, la, len_pad, ea, s);
-    if (e == hipSuccess) e = launch_line_max(b.Z, b.rows, b.cols, b.ld, b.axis, mbb, st, s);
-    if (e == hipSuccess)
-        e = launch_split(b.Z, b.rows, b.cols, b.ld, b.axis, mbb, S, bf16, sb, lb, len_pad, eb, s);
-    if (e == hipSuccess)
-        e = launch_gemm_split(m, n, k, S, bf16, sa, la, sb, lb, len_pad, ea, eb, C, ldc, s);
+    return hipSuccess;
+}
+
+// Line maxima, exponents and digit slices (or residues) of one operand of a
+// mixed-form product, into the workspace buffers of side A (second = false)
+// or side B; the two sides touch disjoint buffers (and the status block only
+// through atomics), so they may run on different streams.
+hipError_t mixed_prepare(const SplitOperand &o, bool second, const MixedPlan &mp, tcu_precision p,
+                         void *ws, const Layout &L, StatusBlock *st, hipStream_t s) {
+    auto *mb = at<unsigned long long>(ws, second ? L.mbb : L.mba);
+    int *ex = at<int>(ws, second ? L.eb : L.ea);
+    const int lines = second ? mp.lb : mp.la;
+    hipError_t e = launch_line_max(o.Z, o.rows, o.cols, o.ld, o.axis, mb, st, s);
+    if (e != hipSuccess) return e;
+    if (is_crt(p))
+        return launch_crt_split(o.Z, o.rows, o.cols, o.ld, o.axis, mb, mp.S, mp.bits,
+                                at<int8_t>(ws, second ? L.sb : L.sa), lines, mp.len_pad, ex, s);
+    return launch_split(o.Z, o.rows, o.cols, o.ld, o.axis, mb, mp.S, p == TCU_PREC_SPLIT_BF16,
+                        at<char>(ws, second ? L.sb : L.sa), lines, mp.len_pad, ex, s);
+}
+
+// The narrow products of both prepared operands and their FP64 combination.
+hipError_t mixed_multiply(int m, int n, int k, const MixedPlan &mp, tcu_precision p, void *ws,
+                          const Layout &L, double *C, int64_t ldc, hipStream_t s) {
+    const int *ea = at<int>(ws, L.ea), *eb = at<int>(ws, L.eb);
+    if (is_crt(p))
+        return launch_gemm_crt(m, n, k, mp.S, mp.bits, at<int8_t>(ws, L.sa), mp.la,
+                               at<int8_t>(ws, L.sb), mp.lb, mp.len_pad, at<int8_t>(ws, L.res), ea,
+                               eb, C, ldc, 0, s);
+    return launch_gemm_split(m, n, k, mp.S, p == TCU_PREC_SPLIT_BF16, at<char>(ws, L.sa), mp.la,
+                             at<char>(ws, L.sb), mp.lb, mp.len_pad, ea, eb, C, ldc, s);
+}
+
+hipError_t split_product(const SplitOperand &a, const SplitOperand &b, int m, int n, int k,
+                         int S, tcu_precision p, double tol, void *ws, const Layout &L,
+                         StatusBlock *st, double *C, int64_t ldc, hipStream_t s) {
+    MixedPlan mp;
+    hipError_t e = mixed_plan(m, n, k, S, p, tol, &mp);
+    if (e == hipSuccess) e = mixed_prepare(a, false, mp, p, ws, L, st, s);
+    if (e == hipSuccess) e = mixed_prepare(b, true, mp, p, ws, L, st, s);
+    if (e == hipSuccess) e = mixed_multiply(m, n, k, mp, p, ws, L, C, ldc, s);
     return e;
 }
 
@@ -232,7 +254,7 @@ hipError_t side_stream(hipStream_t *out) {
     return hipSuccess;
 }
 
-// Events of one adjoint call, destroyed when the call returns (the runtime
+// Events of one call, destroyed when the call returns (the runtime
 // keeps a recorded event alive until the work it marks has run).  Once work
 // has been forked to the internal stream, leaving the call without the
 // normal join (an early error return) still orders the caller's stream after
@@ -369,11 +391,11 @@ tcu_status tcu_join_agg_fwd(const tcu_relation *A, const tcu_relation *B, int32_
     TCU_TRY(encode_both(*A, *B, M, K, N, X, Y, st, false, stream));
     if (S == 0) {
         TCU_TRY(launch_gemm_f64(0, 0, M, N, K, X, K, Y, N, C, N, stream));
-    } else {
-        // X: M lines (rows) of length K; Y: N lines (columns) of length K
-        const SplitOperand a{X, M, K, K, 0}, b{Y, K, N, N, 1};
-        TCU_TRY(split_product(a, b, M, N, K, S, p, tol, ws, L, st, C, N, stream));
+        return TCU_OK;
     }
+    // X: M lines (rows) of length K; Y: N lines (columns) of length K
+    const SplitOperand a{X, M, K, K, 0}, b{Y, K, N, N, 1};
+    TCU_TRY(split_product(a, b, M, N, K, S, p, tol, ws, L, st, C, N, stream));
     return TCU_OK;
 }
 

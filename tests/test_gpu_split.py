@@ -190,3 +190,26 @@ def test_split_adjoint_within_bound(orc, precision):
     bB = tol * M * np.abs(X).max(axis=0)[kB] * np.abs(Wn).max(axis=0)[hB]
     assert np.all(np.abs(dA.cpu().numpy() - ga) <= bA)
     assert np.all(np.abs(dB.cpu().numpy() - gb) <= bB)
+
+
+@pytest.mark.parametrize("precision", ALL_FORMS)
+def test_mixed_fwd_stream_ordered(orc, precision):
+    """The mixed forms' forward on a non-default stream: work queued behind
+    the call on the caller's stream sees the finished C, bit for bit the same
+    as on the default stream (dense tables with unique cells encode
+    deterministically), and C meets the guaranteed bound."""
+    dev = cuda_or_skip()
+    M, K, N = 300, 700, 260
+    A, B = wl.mm_query(M, K, N, seed=39, values="loguniform", device=dev)
+    args = (A.group, A.key, A.val, B.key, B.group, B.val, M, K, N)
+    ref, _, _ = ops.join_agg_fwd(*args, precision=precision, tol=1e-12, unique=True)
+    torch.cuda.synchronize(dev)
+    s = torch.cuda.Stream(device=dev)
+    s.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(s):
+        Cg, _, ws = ops.join_agg_fwd(*args, precision=precision, tol=1e-12, unique=True)
+        got = Cg.clone()  # a consumer on the same stream, right behind the call
+    s.synchronize()
+    assert ops.sync_status(ws)[0] == 0
+    assert torch.equal(got, ref)
+    bound_check(orc, A, B, M, K, N, got.cpu().numpy(), 1e-12)
