@@ -324,6 +324,54 @@ def bench_queries(stream, log, steps, warmup):
     return out
 
 
+def bench_multiway(stream, log, steps, warmup):
+    """The multi-way join of Section 3.2 (query Q2).  The table conversion
+    nonzero() over an 8192 x 8192 FP64 matrix with 1% nonzeros, HBM-bound:
+    two passes of 8 B per cell read, 8 B per nonzero written (row, column);
+    the call reads the count back to the host, as the next join needs it.
+    Q2 end to end (dictionaries, first join, conversion, second join) at
+    4096 tuples per table with 512 distinct ID1 and ID2 values."""
+    import torch
+    from paper_2112_07552_amd import ops
+    from paper_2112_07552_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    out = {}
+    n = 8192
+    u = wl.uniform01(wl.stream_key(82, 0), torch.arange(n * n, device=dev))
+    M = torch.where(u < 0.01, u + 0.5, torch.zeros_like(u)).reshape(n, n)
+    del u
+    r, _, _ = ops.nonzero(M, capacity=1 << 20)
+    nnz = r.numel()
+
+    def nz():
+        ops.nonzero(M, capacity=nnz)
+
+    ms = time_loop(nz, steps, warmup, stream)
+    moved = 2 * 8 * n * n + 8 * nnz
+    out["nonzero_8192x8192_1pct"] = {"ms": ms, "nonzero": nnz, "bytes": moved,
+                                     "GB_per_s": moved / (ms * 1e-3) / 1e9,
+                                     "frac_of_hbm_peak": moved / (ms * 1e-3) / 8e12}
+    log(f"multiway: nonzero {n}x{n} 1%: {ms:.3f} ms, {moved / (ms * 1e-3) / 1e9:.0f} GB/s")
+    del M
+    t = 4096
+    a1 = wl.id_column(t, 512, 83, 1, device=dev)
+    b1 = wl.id_column(t, 512, 83, 2, device=dev)
+    b2 = wl.id_column(t, 512, 83, 3, device=dev)
+    c2 = wl.id_column(t, 512, 83, 4, device=dev)
+    pa, _, C3 = ops.join3(a1, b1, b2, c2)
+    triples = int(C3.count_nonzero())
+
+    def q2():
+        ops.join3(a1, b1, b2, c2)
+
+    ms = time_loop(q2, max(2, steps // 4), 1, stream)
+    out["q2_4096_tuples_512_ids"] = {"ms": ms, "ab_pairs": int(pa.numel()),
+                                     "result_triples": triples}
+    log(f"multiway: Q2 4096 tuples: {ms:.3f} ms, {pa.numel()} pairs, {triples} triples")
+    return out
+
+
 def bench_bsr(stream, log, steps, warmup):
     """The block-sparse form (16 x 16 tiles, empty tiles skipped) against
     the dense form on Q1 pair counts with one record per tuple (Section 5.2,
@@ -636,6 +684,7 @@ def main():
     if not args.no_queries:
         queries = bench_queries(stream, log, args.steps, args.warmup)
         queries["block_sparse"] = bench_bsr(stream, log, args.steps, args.warmup)
+        queries["multiway"] = bench_multiway(stream, log, args.steps, args.warmup)
     large = None
     if args.large:
         large = bench_large(stream, log)

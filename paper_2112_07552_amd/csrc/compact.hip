@@ -23,24 +23,56 @@ constexpr int kThreads = 256;
 constexpr int kPerThread = 16;
 constexpr int kChunk = kThreads * kPerThread;  // cells per workgroup
 
-__device__ inline double cell(const double *__restrict__ M, int64_t i, int64_t cols,
-                              int64_t ld) {
-    return M[(i / cols) * ld + i % cols];
+// Row and column of flat cell index i, cols >= 1: the quotient from a
+// multiply by the reciprocal, then corrected by one either way.  i < 2^43
+// (the launch covers at most 2^31 chunks of 4096 cells), so i is exact in a
+// double and the product is within 2^-8 of i / cols.
+__device__ inline void row_col(int64_t i, int64_t cols, double inv_cols, int64_t &r, int64_t &c) {
+    r = (int64_t)((double)i * inv_cols);
+    c = i - r * cols;
+    if (c < 0) { --r; c += cols; }
+    if (c >= cols) { ++r; c -= cols; }
 }
 
-// Cells of chunk b: [b * kChunk, min((b+1) * kChunk, total)); thread t reads
-// the cells b * kChunk + j * kThreads + t (coalesced across the workgroup).
+// The kPerThread cells of this thread, read before any is used: cell j is
+// b * kChunk + j * kThreads + t.  Every lane loads (cell 0 stands in past the
+// end, total > 0), so the loads are in flight together; contiguous matrices
+// (ld == cols, a uniform branch) need no row/column split.
+__device__ inline void load_cells(const double *__restrict__ M, int64_t total, int64_t cols,
+                                  int64_t ld, double (&v)[kPerThread]) {
+    const int64_t base = (int64_t)blockIdx.x * kChunk + threadIdx.x;
+    if (ld == cols) {
+#pragma unroll
+        for (int j = 0; j < kPerThread; ++j) {
+            const int64_t i = base + (int64_t)j * kThreads;
+            const bool in = i < total;
+            const double x = M[in ? i : 0];
+            v[j] = in ? x : 0.0;
+        }
+    } else {
+        const double inv = 1.0 / (double)cols;
+#pragma unroll
+        for (int j = 0; j < kPerThread; ++j) {
+            const int64_t i = base + (int64_t)j * kThreads;
+            const bool in = i < total;
+            int64_t r, c;
+            row_col(in ? i : 0, cols, inv, r, c);
+            const double x = M[r * ld + c];
+            v[j] = in ? x : 0.0;
+        }
+    }
+}
+
+// Pass 1: nonzeros per chunk of kChunk cells (coalesced across the workgroup).
 __global__ void __launch_bounds__(kThreads)
 nz_count_kernel(const double *__restrict__ M, int64_t total, int64_t cols, int64_t ld,
                 unsigned *__restrict__ counts) {
     __shared__ unsigned wave_sum[kThreads / 64];
-    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    double v[kPerThread];
+    load_cells(M, total, cols, ld, v);
     unsigned c = 0;
-#pragma unroll 4
-    for (int j = 0; j < kPerThread; ++j) {
-        const int64_t i = base + (int64_t)j * kThreads + threadIdx.x;
-        if (i < total && cell(M, i, cols, ld) != 0.0) ++c;
-    }
+#pragma unroll
+    for (int j = 0; j < kPerThread; ++j) c += v[j] != 0.0;
     // wave reduction by lane shuffles
     for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
     if ((threadIdx.x & 63) == 0) wave_sum[threadIdx.x >> 6] = c;
@@ -90,9 +122,12 @@ nz_write_kernel(const double *__restrict__ M, int64_t total, int64_t cols, int64
     const int64_t base = (int64_t)blockIdx.x * kChunk;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     unsigned long long pos = offsets[blockIdx.x];
+    const double inv_cols = 1.0 / (double)cols;
+    double v[kPerThread];
+    load_cells(M, total, cols, ld, v);
     for (int j = 0; j < kPerThread; ++j) {
         const int64_t i = base + (int64_t)j * kThreads + threadIdx.x;
-        const bool nz = i < total && cell(M, i, cols, ld) != 0.0;
+        const bool nz = v[j] != 0.0;  // cells past the end read as 0
         const unsigned long long mask = __ballot(nz);
         if (lane == 0) wave_cnt[wave] = (unsigned)__popcll(mask);
         __syncthreads();
@@ -104,7 +139,8 @@ nz_write_kernel(const double *__restrict__ M, int64_t total, int64_t cols, int64
             const unsigned long long lower = lane ? (mask & ((1ull << lane) - 1ull)) : 0ull;
             const unsigned long long p = pos + before + (unsigned)__popcll(lower);
             if ((int64_t)p < capacity) {
-                const int64_t r = i / cols, c = i % cols;
+                int64_t r, c;
+                row_col(i, cols, inv_cols, r, c);
                 out_row[p] = (int32_t)r;
                 out_col[p] = (int32_t)c;
                 if (out_key != nullptr) out_key[p] = col_map[c];

@@ -40,6 +40,21 @@ def test_nonzero_leading_dimension():
     assert r.tolist() == [3, 49] and c.tolist() == [7, 39]
 
 
+@pytest.mark.parametrize("rows,cols,ld,density", [(3001, 1999, 2500, 0.05), (70000, 1, 3, 0.5),
+                                                  (5, 1_000_003, 1_000_010, 0.001)])
+def test_nonzero_strided_views(rows, cols, ld, density):
+    """Views whose leading dimension exceeds their width take the row/column
+    split of each flat index (a reciprocal multiply, corrected): cells and
+    order bit-exact against numpy, including one-column and very wide views."""
+    dev = cuda_or_skip()
+    u = wl.uniform01(wl.stream_key(81, rows), torch.arange(rows * ld, device=dev))
+    big = torch.where(u < density, u + 0.5, torch.zeros_like(u)).reshape(rows, ld)
+    view = big[:, :cols]
+    r, c, _ = ops.nonzero(view)
+    er, ec = np.nonzero(view.cpu().numpy())
+    assert np.array_equal(r.cpu().numpy(), er) and np.array_equal(c.cpu().numpy(), ec)
+
+
 @pytest.mark.parametrize("na,nb,nc,d1,d2", [(300, 400, 350, 20, 15), (2048, 2048, 2048, 128, 128),
                                              (1000, 50, 1000, 1000, 1000), (64, 64, 0, 4, 4)])
 def test_three_way_join_matches_oracle(orc, na, nb, nc, d1, d2):
