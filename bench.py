@@ -422,6 +422,23 @@ def bench_bsr(stream, log, steps, warmup):
          "dense_flops": 2.0 * nodes * nodes * 64}
     log(f"bsr graph 2^16 nodes: {r['ms_bsr']:.3f} ms")
     out["graph_65536_nodes"] = r
+    # the cost model's choice next to the crossover (Q1, 4096 tuples)
+    choice = {}
+    for k in (1024, 2048):
+        ida = wl.id_column(4096, k, 72, 1, device=dev)
+        idb = wl.id_column(4096, k, 72, 2, device=dev)
+        _, ka, kb = ops.dict_encode(ida, idb)
+        K = int(max(ka.max(), kb.max())) + 1
+        t = torch.arange(4096, dtype=torch.int32, device=dev)
+        args = (t, ka, None, kb, t, None, 4096, K, 4096)
+        c = {"K": K,
+             "ms_dense": time_loop(lambda: ops.join_agg_fwd(*args, unique=True), steps, warmup, stream),
+             "ms_bsr": time_loop(lambda: ops.join_agg_bsr(*args, unique=True), steps, warmup, stream),
+             "picked": "block_sparse" if ops.block_sparse_preferred(*args) else "dense"}
+        c["picked_faster"] = (c["picked"] == "block_sparse") == (c["ms_bsr"] < c["ms_dense"])
+        log(f"bsr choice q1 n=4096 k={k}: " + ", ".join(f"{a} {b}" for a, b in c.items()))
+        choice[f"q1_n4096_k{k}"] = c
+    out["cost_model_choice"] = choice
     return out
 
 

@@ -280,6 +280,22 @@ size_t tcu_join_agg_bsr_workspace_bytes(const tcu_relation *A, const tcu_relatio
 tcu_status tcu_join_agg_bsr(const tcu_relation *A, const tcu_relation *B, int32_t M, int32_t K,
                             int32_t N, double *C, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* The choice between the dense FP64 operator (tcu_join_agg_fwd) and the
+ * block-sparse one (tcu_join_agg_bsr), after the paper's switch to TCU-SpMM
+ * when the encodings are sparse (Section 4.2.4) and its cost model's
+ * comparison of estimated times (Section 4.3).  Host only, no device call.
+ * Returns 1 when the block-sparse form is predicted faster, 0 when the dense
+ * one is, TCU_ERR_ARG on bad arguments.  The model, with constants measured
+ * on MI355X on Q1 pair counts (one record per tuple, n = 4096 and 8192,
+ * 32 to 16384 distinct keys):
+ *   dense        2 M N K / (70 TFLOP/s) + 16 B per cell of X and Y / (3 TB/s)
+ *   block-sparse 0.62 ms + 1.7 ns per 16 x 16 tile of C
+ *                + 0.14 ns per pair of stored tiles meeting on a key tile,
+ * with stored tiles estimated as min(records, tiles of the grid) per side
+ * and meetings as their product over the key tiles (keys spread evenly). */
+int tcu_block_sparse_preferred(const tcu_relation *A, const tcu_relation *B, int32_t M,
+                               int32_t K, int32_t N);
+
 /* ---- Matrix-to-table conversion (Section 3.2: multi-way joins) ----------
  *
  * nonzero(M): the cells (i, j) of a dense rows x cols FP64 matrix (leading

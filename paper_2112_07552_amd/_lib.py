@@ -39,7 +39,8 @@ EXPORTS = (
     "tcu_workspace_bytes", "tcu_split_slices", "tcu_crt_plan", "tcu_split", "tcu_encode", "tcu_gemm_f64",
     "tcu_join_agg_fwd", "tcu_join_agg_bwd", "tcu_dict_workspace_bytes", "tcu_dict_encode",
     "tcu_join_agg_row_workspace_bytes", "tcu_join_agg_row",
-    "tcu_join_agg_bsr_workspace_bytes", "tcu_join_agg_bsr", "tcu_nonzero_workspace_bytes",
+    "tcu_join_agg_bsr_workspace_bytes", "tcu_join_agg_bsr", "tcu_block_sparse_preferred",
+    "tcu_nonzero_workspace_bytes",
     "tcu_nonzero", "tcu_gemm_f64_host", "tcu_sync_status",
     "tcu_status_str", "tcu_version",
 )
@@ -107,6 +108,8 @@ def load():
     L.tcu_join_agg_bsr_workspace_bytes.restype = C.c_size_t
     L.tcu_join_agg_bsr.argtypes = [rel_p, rel_p, i32, i32, i32, vp, vp, C.c_size_t, vp]
     L.tcu_join_agg_bsr.restype = C.c_int
+    L.tcu_block_sparse_preferred.argtypes = [rel_p, rel_p, i32, i32, i32]
+    L.tcu_block_sparse_preferred.restype = C.c_int
     L.tcu_nonzero_workspace_bytes.argtypes = [i64, i64]
     L.tcu_nonzero_workspace_bytes.restype = C.c_size_t
     L.tcu_nonzero.argtypes = [vp, i64, i64, i64, vp, vp, vp, vp, i64, C.POINTER(C.c_int64), vp,

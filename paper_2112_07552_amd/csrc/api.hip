@@ -6,6 +6,7 @@
 // and its adjoint.  Every launch goes to the caller's stream.
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 
 #include "internal.h"
@@ -550,6 +551,18 @@ tcu_status tcu_join_agg_bsr(const tcu_relation *A, const tcu_relation *B, int32_
     if (A->n > 0x7fffffffLL || B->n > 0x7fffffffLL) return TCU_ERR_ARG;
     if (!ws_ok(ws, ws_bytes, bsr_workspace_bytes(A->n, B->n, M, K, N))) return TCU_ERR_WORKSPACE;
     return hip_status(run_join_agg_bsr(*A, *B, M, K, N, C, ws, stream));
+}
+
+int tcu_block_sparse_preferred(const tcu_relation *A, const tcu_relation *B, int32_t M,
+                               int32_t K, int32_t N) {
+    if (!relation_ok(A) || !relation_ok(B) || !shapes_ok(M, K, N)) return TCU_ERR_ARG;
+    const double tm = (M + 15) / 16, tk = (K + 15) / 16, tn = (N + 15) / 16;
+    const double dense_ms = 2.0 * M * (double)N * K / 70e12 * 1e3 +
+                            16.0 * ((double)M * K + (double)K * N) / 3e12 * 1e3;
+    const double ta = std::min((double)A->n, tm * tk), tb = std::min((double)B->n, tk * tn);
+    const double meetings = ta * tb / tk;
+    const double bsr_ms = 0.62 + 1.7e-6 * tm * tn + 1.4e-7 * meetings;
+    return bsr_ms < dense_ms ? 1 : 0;
 }
 
 size_t tcu_nonzero_workspace_bytes(int64_t rows, int64_t cols) {

@@ -307,6 +307,28 @@ def join_agg_bsr(a_group, a_key, a_val, b_key, b_group, b_val, M: int, K: int, N
     return Cm, ws
 
 
+def block_sparse_preferred(a_group, a_key, a_val, b_key, b_group, b_val, M: int, K: int,
+                           N: int) -> bool:
+    """The library's cost-model choice (Sections 4.2.4, 4.3): True when the
+    block-sparse operator is predicted faster than the dense FP64 one."""
+    A = make_relation(a_group, a_key, a_val)
+    B = make_relation(b_group, b_key, b_val)
+    r = int(_lib.load().tcu_block_sparse_preferred(C.byref(A), C.byref(B), M, K, N))
+    if r < 0:
+        check(r, "tcu_block_sparse_preferred")
+    return r == 1
+
+
+def join_agg_auto(a_group, a_key, a_val, b_key, b_group, b_val, M: int, K: int, N: int,
+                  unique: bool = False) -> Tuple[torch.Tensor, str]:
+    """The operator in the form the cost model picks: returns (C [M, N] FP64,
+    "block_sparse" or "dense")."""
+    args = (a_group, a_key, a_val, b_key, b_group, b_val, M, K, N)
+    if block_sparse_preferred(*args):
+        return join_agg_bsr(*args, unique=unique)[0], "block_sparse"
+    return join_agg_fwd(*args, unique=unique)[0], "dense"
+
+
 def nonzero(M: torch.Tensor, col_map: Optional[torch.Tensor] = None,
             capacity: Optional[int] = None):
     """The matrix-to-table conversion of Section 3.2: (rows, cols, keys) of

@@ -120,3 +120,27 @@ def test_bsr_local_graph(orc):
     assert ops.sync_status(ws)[0] == 0
     Ec, Fc = wl.Relation(*[t.cpu() for t in E]), wl.Relation(*[t.cpu() for t in F])
     assert check_rows(orc, Ec, Fc, nodes, nodes, 64, Cg.cpu().numpy()) <= TOL
+
+
+@pytest.mark.parametrize("n,k,form", [(4096, 64, "dense"), (4096, 4096, "block_sparse")])
+def test_auto_choice_matches_both_forms(orc, n, k, form):
+    """join_agg_auto takes the form the cost model picks (dense for few
+    distinct keys, block-sparse for many) and returns the Q1 pair counts
+    exactly: equal to the other form's, and to the oracle on sampled rows."""
+    dev = cuda_or_skip()
+    ida = wl.id_column(n, k, 73, 1, device=dev)
+    idb = wl.id_column(n, k, 73, 2, device=dev)
+    _, ka, kb = ops.dict_encode(ida, idb)
+    K = int(max(ka.max(), kb.max())) + 1
+    t = torch.arange(n, dtype=torch.int32, device=dev)
+    args = (t, ka, None, kb, t, None, n, K, n)
+    Cg, picked = ops.join_agg_auto(*args, unique=True)
+    assert picked == form
+    Cd, _, _ = ops.join_agg_fwd(*args, unique=True)
+    Cb, _ = ops.join_agg_bsr(*args, unique=True)
+    assert torch.equal(Cg, Cd) and torch.equal(Cg, Cb)
+    rows = np.arange(0, n, 97, dtype=np.int32)
+    RA = orc.Rel(t.cpu().numpy(), ka.cpu().numpy(), None)
+    RB = orc.Rel(t.cpu().numpy(), kb.cpu().numpy(), None)
+    Co, _, _ = orc.join_agg(RA, RB, n, K, n, rows=rows)
+    assert np.array_equal(Cg.cpu().numpy()[rows], Co)

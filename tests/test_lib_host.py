@@ -199,3 +199,34 @@ def test_queries_bsr_nonzero_host_argument_errors(lib):
     assert lib.tcu_dict_encode(None, 5, None, 0, None, None, None, C.byref(cnt), dev, 1 << 20,
                                None) == _lib.TCU_ERR_ARG
     assert lib.tcu_dict_workspace_bytes(-3) == 0
+
+
+def test_block_sparse_choice_host_only(lib):
+    """The dense / block-sparse cost model (Sections 4.2.4, 4.3) runs on the
+    host only.  For Q1 pair counts (one record per tuple, n tuples per side)
+    it must pick the dense form while few distinct keys make the encodings
+    dense, the block-sparse form once the key domain is large, switch only
+    once as K grows, and agree with the winners measured on MI355X at the
+    calibration points next to the switch."""
+    fake = C.c_void_p(0x1000)  # never dereferenced
+
+    def rel(n):
+        return _lib.tcu_relation(n, fake, fake, None, _lib.TCU_F64, 0)
+
+    def pick(n, K):
+        a, b = rel(n), rel(n)
+        return lib.tcu_block_sparse_preferred(C.byref(a), C.byref(b), n, K, n)
+
+    for n in (4096, 8192, 16384):
+        picks = [pick(n, K) for K in (32, 128, 512, 1024, 2048, 4096, 16384, 1 << 20)]
+        assert picks[0] == 0 and picks[-1] == 1
+        assert picks == sorted(picks)  # one switch, dense -> block-sparse
+    # measured on MI355X (dense ms / block-sparse ms): n = 4096: K = 1024
+    # 0.53 / 0.77, K = 2006 1.19 / 0.75; n = 8192: K = 512 1.01 / 1.47,
+    # K = 1024 1.95 / 1.22
+    assert pick(4096, 1024) == 0 and pick(4096, 2006) == 1
+    assert pick(8192, 512) == 0 and pick(8192, 1024) == 1
+    bad = rel(-1)
+    good = rel(10)
+    assert lib.tcu_block_sparse_preferred(C.byref(bad), C.byref(good), 4, 4, 4) == _lib.TCU_ERR_ARG
+    assert lib.tcu_block_sparse_preferred(C.byref(good), C.byref(good), 0, 4, 4) == _lib.TCU_ERR_ARG
