@@ -487,13 +487,30 @@ def bench_ooc(stream, log, N=32768, dev_gb=24):
             "max_abs_diff_4x4_vs_device": sample}
 
 
+# Device bytes per N^2 at the large workload's peak: the two tables (int32
+# group and key, FP32 value: 24), W, C, dA and dB (32), and the residue form's
+# workspace with backward (X, Y, dX, dY: 32; operand residues, 15 planes per
+# side: 30; product residues, 15 planes: 15).
+LARGE_BYTES_PER_N2 = 24 + 32 + 32 + 30 + 15
+
+
+def large_n_max():
+    """The largest multiple of 256 whose footprint fits in 0.9 of the free
+    device memory."""
+    import math
+    import torch
+    free, _ = torch.cuda.mem_get_info()
+    return int(math.isqrt(int(0.9 * free) // LARGE_BYTES_PER_N2)) // 256 * 256
+
+
 def bench_large(stream, log, N=32768):
-    """2^30 records per table (N = 32768, the paper's largest MM query), FP32
-    values N(0,1) with 5% x1e3 outliers (seed 4).  One forward and one
-    forward + adjoint with checkpointing (the adjoint re-encodes) in the two
-    mixed int8 forms (digit slices, residues) at tol = 1e-12 and in the FP64
-    form, each timed once after one untimed run; errors on a 64 x 64 block of
-    C against the oracle."""
+    """The mixed forms at scale: N^2 records per table (default N = 32768,
+    2^30, the paper's largest MM query; N = 0 takes the largest size that
+    fits, large_n_max()), FP32 values N(0,1) with 5% x1e3 outliers (seed 4).
+    One forward and one forward + adjoint with checkpointing (the adjoint
+    re-encodes) in the two mixed int8 forms (digit slices, residues) at
+    tol = 1e-12 and in the FP64 form, each timed once after one untimed run;
+    errors on a 64 x 64 block of C against the oracle."""
     import numpy as np
     import torch
     from oracle import oracle as orc
@@ -501,6 +518,10 @@ def bench_large(stream, log, N=32768):
     from paper_2112_07552_amd import workloads as wl
 
     dev = torch.device("cuda:0")
+    n_max = large_n_max()
+    if N == 0:
+        N = n_max
+    log(f"large: N = {N} (largest that fits: {n_max}, at {LARGE_BYTES_PER_N2} bytes per N^2)")
     log(f"large: generating 2 x {N * N} records")
     A, B = wl.mm_query(N, N, N, seed=4, values="mixture", dtype=torch.float32, device=dev)
     W = wl.draw_values("uniform", N * N, 1004, 0, device=dev).reshape(N, N)
@@ -513,7 +534,8 @@ def bench_large(stream, log, N=32768):
     dB = torch.empty(N * N, dtype=torch.float64, device=dev)
     out = {"workload": f"MM query, dense {N}x{N} tables ({N * N} records each), FP32 values "
                        f"N(0,1) with 5% x1e3 outliers, seed 4; adjoint with checkpointing "
-                       f"(re-encoding)", "records_per_table": N * N}
+                       f"(re-encoding)", "records_per_table": N * N, "N": N, "n_max": n_max,
+           "footprint_bytes": LARGE_BYTES_PER_N2 * N * N}
     rng = np.random.default_rng(4)
     rows = np.sort(rng.choice(N, 64, replace=False))
     cols = np.sort(rng.choice(N, 64, replace=False))
@@ -591,6 +613,8 @@ def main():
                     help="also time the largest workload: 2^30 records per table, FP32 "
                          "mixture values, mixed int8 form vs FP64 form, forward + adjoint "
                          "with checkpointing")
+    ap.add_argument("--large-n", type=int, default=32768,
+                    help="edge of the --large workload (0: the largest that fits in memory)")
     ap.add_argument("--ooc", action="store_true",
                     help="also time the 32768^3 FP64 product over pinned host memory through "
                          "a 24 GB device budget (blocked, pipelined) against the HBM-resident one")
@@ -704,7 +728,7 @@ def main():
         queries["multiway"] = bench_multiway(stream, log, args.steps, args.warmup)
     large = None
     if args.large:
-        large = bench_large(stream, log)
+        large = bench_large(stream, log, args.large_n)
     ooc = None
     if args.ooc:
         ooc = bench_ooc(stream, log)
