@@ -140,9 +140,11 @@ hipError_t encode_both(const tcu_relation &A, const tcu_relation &B, int32_t M, 
                        hipStream_t s) {
     tcu_relation a = A, b = B;
     if (count_only) { a.val = nullptr; b.val = nullptr; }
+    // each matrix is zeroed right before its scatter, so its freshly written
+    // lines are still in the caches when the random 8-byte stores land
     hipError_t e = launch_zero_f64(X, (size_t)M * K, s);
-    if (e == hipSuccess) e = launch_zero_f64(Y, (size_t)K * N, s);
     if (e == hipSuccess) e = launch_encode(a, 0, M, K, X, st, 0, s);
+    if (e == hipSuccess) e = launch_zero_f64(Y, (size_t)K * N, s);
     if (e == hipSuccess) e = launch_encode(b, 1, K, N, Y, st, 1, s);
     return e;
 }
