@@ -391,14 +391,23 @@ tcu_status tcu_join_agg_fwd(const tcu_relation *A, const tcu_relation *B, int32_
         TCU_TRY(launch_gemm_f64(0, 0, M, N, K, X, K, Y, N, C, N, stream));
         TCU_TRY(launch_f64_to_i32(C, count, (size_t)M * N, stream));
     }
-    TCU_TRY(encode_both(*A, *B, M, K, N, X, Y, st, false, stream));
     if (S == 0) {
+        TCU_TRY(encode_both(*A, *B, M, K, N, X, Y, st, false, stream));
         TCU_TRY(launch_gemm_f64(0, 0, M, N, K, X, K, Y, N, C, N, stream));
         return TCU_OK;
     }
+    // Mixed forms: each operand is encoded and at once reduced to its line
+    // maxima and slices or residues, which read it while it is still in the
+    // caches; then the other operand.
     // X: M lines (rows) of length K; Y: N lines (columns) of length K
     const SplitOperand a{X, M, K, K, 0}, b{Y, K, N, N, 1};
-    TCU_TRY(split_product(a, b, M, N, K, S, p, tol, ws, L, st, C, N, stream));
+    MixedPlan mp;
+    TCU_TRY(mixed_plan(M, N, K, S, p, tol, &mp));
+    TCU_TRY(encode_one(*A, 0, M, K, X, st, stream));
+    TCU_TRY(mixed_prepare(a, false, mp, p, ws, L, st, stream));
+    TCU_TRY(encode_one(*B, 1, K, N, Y, st, stream));
+    TCU_TRY(mixed_prepare(b, true, mp, p, ws, L, st, stream));
+    TCU_TRY(mixed_multiply(M, N, K, mp, p, ws, L, C, N, stream));
     return TCU_OK;
 }
 
