@@ -228,8 +228,10 @@ __device__ inline void tile_coords(int tiles_m, int tiles_n, int &tm, int &tn) {
 
 // A_KC: op(A)'s contraction index is contiguous (trans_a == 0).
 // B_KC: op(B)'s contraction index is contiguous (trans_b == 1).
-// FULL: every tile is whole (m, n multiples of 128, k of 16) and both
-// operands allow 16-byte loads; the loads and stores then carry no guards.
+// FULL: every tile is whole (edge tiles moved back inside the matrix, k a
+// multiple of 16) and both operands allow 16-byte loads; the loads then
+// carry no guards, and the stores only skip the cells a moved tile shares
+// with its neighbour.
 template <bool A_KC, bool B_KC, bool FULL>
 __global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
 gemm_f64_kernel(int m, int n, int k, const double *__restrict__ A, int64_t lda,
@@ -241,7 +243,11 @@ gemm_f64_kernel(int m, int n, int k, const double *__restrict__ A, int64_t lda,
     const int tiles_m = (m + BM - 1) / BM, tiles_n = (n + BN - 1) / BN;
     int tm, tn;
     tile_coords(tiles_m, tiles_n, tm, tn);
-    const int m0 = tm * BM, n0 = tn * BN;
+    // the cells this tile owns start at (rlo, clo); on the whole-tile path a
+    // tile that would run past an edge is moved back to end at m (or n), so
+    // it stays whole and in bounds, and stores only the cells it owns
+    const int rlo = tm * BM, clo = tn * BN;
+    const int m0 = FULL ? min(rlo, m - BM) : rlo, n0 = FULL ? min(clo, n - BN) : clo;
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wm = wave & 1, wn = wave >> 1;
@@ -316,7 +322,7 @@ gemm_f64_kernel(int m, int n, int k, const double *__restrict__ A, int64_t lda,
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int row = m0 + wm * WM + a * 16 + j + 4 * i;
-                if (FULL || (row < m && col < n)) {
+                if (FULL ? (row >= rlo && col >= clo) : (row < m && col < n)) {
                     double *dst = C + (int64_t)row * ldc + col;
                     *dst = accumulate ? *dst + acc[a][b][i] : acc[a][b][i];
                 }
@@ -331,11 +337,15 @@ hipError_t launch(int m, int n, int k, const double *A, int64_t lda, const doubl
     const int tiles = ((m + BM - 1) / BM) * ((n + BN - 1) / BN);
     const int vec_a = (lda % 2 == 0) && (((uintptr_t)A & 15) == 0);
     const int vec_b = (ldb % 2 == 0) && (((uintptr_t)B & 15) == 0);
-    // whole tiles, 16-byte loads, and every lane's byte offset inside a
-    // stage's panel below 2^32
+    // the whole-tile path: 16-byte loads, k a multiple of the stage depth,
+    // every lane's byte offset inside a stage's panel below 2^32, and m, n
+    // at least one tile, so that edge tiles can be moved back to end at m
+    // and n (a move along an operand's contiguous index must keep 16-byte
+    // alignment: m, n even there)
     const int64_t span_a = (A_KC ? (int64_t)BM * lda : (int64_t)BK * lda) * 8;
     const int64_t span_b = (B_KC ? (int64_t)BN * ldb : (int64_t)BK * ldb) * 8;
-    const bool full = vec_a && vec_b && m % BM == 0 && n % BN == 0 && k % BK == 0 && k > 0 &&
+    const bool full = vec_a && vec_b && m >= BM && n >= BN && k % BK == 0 && k > 0 &&
+                      (A_KC || m % 2 == 0) && (B_KC || n % 2 == 0) &&
                       span_a < ((int64_t)1 << 32) && span_b < ((int64_t)1 << 32);
     if (full)
         gemm_f64_kernel<A_KC, B_KC, true><<<tiles, THREADS, 0, s>>>(m, n, k, A, lda, B, ldb, C,

@@ -89,7 +89,10 @@ GEMM_SHAPES = [(1, 1, 1), (17, 33, 5), (128, 128, 16), (129, 255, 130), (300, 20
                # whole tiles (m, n multiples of 128, k of 16): the unguarded
                # path, whose loop takes two 16-deep stages per iteration, with
                # 3, 4, 5 and 65 stages
-               (256, 128, 48), (256, 384, 64), (128, 256, 80), (384, 128, 1040)]
+               (256, 128, 48), (256, 384, 64), (128, 256, 80), (384, 128, 1040),
+               # ragged m, n (even, at least one tile) with k a multiple of 16:
+               # the unguarded path with the edge tiles moved back inside
+               (300, 200, 64), (130, 258, 32), (1000, 520, 96), (254, 1030, 48)]
 
 
 @pytest.mark.parametrize("m,n,k", GEMM_SHAPES)
