@@ -229,9 +229,9 @@ __device__ inline void tile_coords(int tiles_m, int tiles_n, int &tm, int &tn) {
 // A_KC: op(A)'s contraction index is contiguous (trans_a == 0).
 // B_KC: op(B)'s contraction index is contiguous (trans_b == 1).
 // FULL: every tile is whole (edge tiles moved back inside the matrix, k a
-// multiple of 16) and both operands allow 16-byte loads; the loads then
-// carry no guards, and the stores only skip the cells a moved tile shares
-// with its neighbour.
+// multiple of 16: the launcher adds a partial last stage separately) and
+// both operands allow 16-byte loads; the loads then carry no guards, and the
+// stores only skip the cells a moved tile shares with its neighbour.
 template <bool A_KC, bool B_KC, bool FULL>
 __global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
 gemm_f64_kernel(int m, int n, int k, const double *__restrict__ A, int64_t lda,
@@ -337,20 +337,29 @@ hipError_t launch(int m, int n, int k, const double *A, int64_t lda, const doubl
     const int tiles = ((m + BM - 1) / BM) * ((n + BN - 1) / BN);
     const int vec_a = (lda % 2 == 0) && (((uintptr_t)A & 15) == 0);
     const int vec_b = (ldb % 2 == 0) && (((uintptr_t)B & 15) == 0);
-    // the whole-tile path: 16-byte loads, k a multiple of the stage depth,
+    // the whole-tile path: 16-byte loads, at least one whole stage of k,
     // every lane's byte offset inside a stage's panel below 2^32, and m, n
     // at least one tile, so that edge tiles can be moved back to end at m
     // and n (a move along an operand's contiguous index must keep 16-byte
     // alignment: m, n even there)
     const int64_t span_a = (A_KC ? (int64_t)BM * lda : (int64_t)BK * lda) * 8;
     const int64_t span_b = (B_KC ? (int64_t)BN * ldb : (int64_t)BK * ldb) * 8;
-    const bool full = vec_a && vec_b && m >= BM && n >= BN && k % BK == 0 && k > 0 &&
+    const bool full = vec_a && vec_b && m >= BM && n >= BN && k >= BK &&
                       (A_KC || m % 2 == 0) && (B_KC || n % 2 == 0) &&
                       span_a < ((int64_t)1 << 32) && span_b < ((int64_t)1 << 32);
-    if (full)
-        gemm_f64_kernel<A_KC, B_KC, true><<<tiles, THREADS, 0, s>>>(m, n, k, A, lda, B, ldb, C,
+    if (full) {
+        // the whole 16-deep stages of k on the whole-tile path; a last
+        // partial stage (k % 16 terms) is added to C by a guarded launch
+        const int kf = k / BK * BK;
+        gemm_f64_kernel<A_KC, B_KC, true><<<tiles, THREADS, 0, s>>>(m, n, kf, A, lda, B, ldb, C,
                                                                     ldc, vec_a, vec_b, accumulate);
-    else
+        if (kf < k) {
+            const double *At = A_KC ? A + kf : A + (int64_t)kf * lda;
+            const double *Bt = B_KC ? B + kf : B + (int64_t)kf * ldb;
+            gemm_f64_kernel<A_KC, B_KC, false><<<tiles, THREADS, 0, s>>>(
+                m, n, k - kf, At, lda, Bt, ldb, C, ldc, vec_a, vec_b, 1);
+        }
+    } else
         gemm_f64_kernel<A_KC, B_KC, false><<<tiles, THREADS, 0, s>>>(m, n, k, A, lda, B, ldb, C,
                                                                      ldc, vec_a, vec_b, accumulate);
     return hipGetLastError();

@@ -92,7 +92,9 @@ GEMM_SHAPES = [(1, 1, 1), (17, 33, 5), (128, 128, 16), (129, 255, 130), (300, 20
                (256, 128, 48), (256, 384, 64), (128, 256, 80), (384, 128, 1040),
                # ragged m, n (even, at least one tile) with k a multiple of 16:
                # the unguarded path with the edge tiles moved back inside
-               (300, 200, 64), (130, 258, 32), (1000, 520, 96), (254, 1030, 48)]
+               (300, 200, 64), (130, 258, 32), (1000, 520, 96), (254, 1030, 48),
+               # ... and a partial last stage of k (k not a multiple of 16)
+               (300, 200, 67), (130, 258, 17), (256, 384, 1041), (1000, 520, 97), (128, 128, 31)]
 
 
 @pytest.mark.parametrize("m,n,k", GEMM_SHAPES)
