@@ -23,7 +23,11 @@ def pinned_uniform(rows, cols, seed):
 
 
 @pytest.mark.parametrize("m,n,k,block", [(700, 500, 900, 128), (257, 129, 1000, 128),
-                                         (1000, 300, 1, 256), (130, 140, 150, 0)])
+                                         (1000, 300, 1, 256), (130, 140, 150, 0),
+                                         # edge blocks 188 x 244 wide with k blocks of
+                                         # 256 and 132: tiles moved back inside, adding
+                                         # into C
+                                         (700, 500, 900, 256), (700, 500, 900, 384)])
 def test_host_gemm_matches_oracle(orc, m, n, k, block):
     cuda_or_skip()
     A, B = pinned_uniform(m, k, m + k), pinned_uniform(k, n, n + k + 1)
