@@ -27,9 +27,12 @@
 //  * Tiles are numbered so that each of the 8 XCDs (workgroup w runs on XCD
 //    w mod 8) owns a contiguous run of tiles, grouped 8 tile-rows deep, so
 //    the A and B panels a run needs stay in that XCD's L2.
-//  * Whole-tile launches (the common case) run a main loop whose address
-//    arithmetic is all scalar (see the whole-tile path below): busy matrix
-//    cores leave vector-ALU instructions few issue slots.
+//  * Whole-tile launches (the common case: m, n >= 128, k >= 16, 16-byte
+//    aligned operands; edge tiles are moved back inside the matrix and a
+//    partial last stage of k is added by a second, guarded launch) run a
+//    main loop whose address arithmetic is all scalar (see the whole-tile
+//    path below): busy matrix cores leave vector-ALU instructions few issue
+//    slots.
 #include "internal.h"
 
 namespace tcu {
