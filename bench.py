@@ -156,6 +156,30 @@ PEAK_I8_MFMA_TOPS = 5000.0     # MI355X dense int8 matrix peak
 PEAK_BF16_MFMA_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
 
 
+PEAK_PROBE_KINDS = {"fp64_tflops": 0, "i8_random_bytes_tops": 1, "i8_constant_bytes_tops": 2}
+
+
+def measured_peaks(stream, log, iters=2048, reps=5):
+    """Matrix-core rates measured on this chip by register-only loops (FP64
+    16x16x4; int8 32x32x32 on uniformly random bytes, the residue form's
+    operand statistics, and on near-constant bytes), in TFLOP/s or TOPS:
+    the ceilings the roofline fractions are also read against."""
+    import torch
+    from paper_2112_07552_amd import _lib
+
+    L = _lib.load()
+    out_buf = torch.empty(L.tcu_mfma_peak_out_bytes(), dtype=torch.uint8, device="cuda:0")
+    sp = C.c_void_p(stream.cuda_stream)
+    res = {}
+    for name, kind in PEAK_PROBE_KINDS.items():
+        def probe(kind=kind):
+            _lib.check(L.tcu_mfma_peak(kind, iters, C.c_void_p(out_buf.data_ptr()), sp), "peak")
+        ms = time_loop(probe, reps, 1, stream)
+        res[name] = L.tcu_mfma_peak_ops(kind, iters) / (ms * 1e-3) / 1e12
+        log(f"measured peak {name}: {res[name]:.1f}")
+    return res
+
+
 def bench_mixed(N, args, stream, log):
     """Mixed-precision form on log-uniform values (|x| = 10^(-4+8u), random
     sign, seed 3), N^2 records per table: the FP64 form and the split forms
@@ -706,6 +730,8 @@ def main():
     flops = 2.0 * N * N * N
     achieved = flops / (gemm_ms["nn"] * 1e-3) / 1e12
 
+    peaks = measured_peaks(stream, log)
+
     result_err = None
     errors = None
     if not args.no_check:
@@ -792,9 +818,12 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_F64_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_F64_MFMA_TFLOPS,
                      "traffic": counter_traffic(),
+                     "measured_peak": peaks["fp64_tflops"],
+                     "frac_of_measured": achieved / peaks["fp64_tflops"],
                      "kernel": "gemm_f64_kernel<true,false,true> (NN, forward)",
                      "kernel_ms": gemm_ms},
         "cpu_baseline": cpu,
+        "measured_peaks": peaks,
         "mixed": mixed,
         "queries": queries,
         "large": large,

@@ -225,6 +225,20 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
                             double *dA_val, double *dB_val, int flags, void *ws,
                             size_t ws_bytes, hipStream_t stream);
 
+/* Measured matrix-core peaks, the rates the roofline is read against beside
+ * the published ones (not a step of the method).  One launch of a
+ * register-only loop: kind 0 runs FP64 16x16x4 MFMAs, kind 1 int8 32x32x32
+ * MFMAs on uniformly random bytes (the residue form's operands), kind 2
+ * int8 on near-constant bytes; iters >= 1 rounds of eight independent
+ * instructions per wave, 2048 workgroups of 256 threads.  out: device
+ * buffer of at least tcu_mfma_peak_out_bytes() bytes (per-thread checksums).
+ * tcu_mfma_peak_ops(kind, iters) is the launch's operation count (FLOPs or
+ * integer ops), to divide by the launch's duration.  Asynchronous on the
+ * stream; TCU_ERR_ARG for a bad kind, iters < 1 or a NULL buffer. */
+size_t tcu_mfma_peak_out_bytes(void);
+double tcu_mfma_peak_ops(int kind, int32_t iters);
+tcu_status tcu_mfma_peak(int kind, int32_t iters, void *out, hipStream_t stream);
+
 /* Dictionary encoding for the encodings of Section 3.1: dom(ID) is the union
  * of two columns' values, with k distinct values v_1 < ... < v_k (sorted,
  * signed 64-bit).  codes_a[i] = the rank of a[i] in that list (0-based), and

@@ -41,7 +41,8 @@ EXPORTS = (
     "tcu_join_agg_row_workspace_bytes", "tcu_join_agg_row",
     "tcu_join_agg_bsr_workspace_bytes", "tcu_join_agg_bsr", "tcu_block_sparse_preferred",
     "tcu_nonzero_workspace_bytes",
-    "tcu_nonzero", "tcu_gemm_f64_host", "tcu_sync_status",
+    "tcu_nonzero", "tcu_gemm_f64_host", "tcu_mfma_peak_out_bytes", "tcu_mfma_peak_ops",
+    "tcu_mfma_peak", "tcu_sync_status",
     "tcu_status_str", "tcu_version",
 )
 
@@ -118,6 +119,12 @@ def load():
     L.tcu_gemm_f64_host.argtypes = [i32, i32, i32, vp, i64, vp, i64, vp, i64, vp, C.c_size_t,
                                     i64, vp]
     L.tcu_gemm_f64_host.restype = C.c_int
+    L.tcu_mfma_peak_out_bytes.argtypes = []
+    L.tcu_mfma_peak_out_bytes.restype = C.c_size_t
+    L.tcu_mfma_peak_ops.argtypes = [C.c_int, i32]
+    L.tcu_mfma_peak_ops.restype = f64
+    L.tcu_mfma_peak.argtypes = [C.c_int, i32, vp, vp]
+    L.tcu_mfma_peak.restype = C.c_int
     L.tcu_sync_status.argtypes = [vp, vp, C.POINTER(tcu_status_info)]
     L.tcu_sync_status.restype = C.c_int
     L.tcu_status_str.argtypes = [C.c_int]

@@ -515,6 +515,18 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
     return TCU_OK;
 }
 
+size_t tcu_mfma_peak_out_bytes(void) { return mfma_peak_out_bytes(); }
+
+double tcu_mfma_peak_ops(int kind, int32_t iters) {
+    if (kind < 0 || kind > 2 || iters < 1) return 0.0;
+    return mfma_peak_ops(kind, iters);
+}
+
+tcu_status tcu_mfma_peak(int kind, int32_t iters, void *out, hipStream_t stream) {
+    if (kind < 0 || kind > 2 || iters < 1 || out == nullptr) return TCU_ERR_ARG;
+    return hip_status(launch_mfma_peak(kind, iters, out, stream));
+}
+
 size_t tcu_dict_workspace_bytes(int64_t n) {
     if (n < 0 || n > 0x7fffffffLL) return 0;
     return dict_workspace_bytes(n);

@@ -105,6 +105,12 @@ hipError_t run_gemm_f64_host(int m, int n, int k, const double *A, int64_t lda, 
                              int64_t ldb, double *C, int64_t ldc, void *dev_buf,
                              size_t dev_bytes, int64_t block, hipStream_t s);
 
+// peak.hip: register-only matrix-core loops (kind 0: FP64 16x16x4; 1: int8
+// 32x32x32 on hashed random bytes; 2: int8 on near-constant bytes).
+double mfma_peak_ops(int kind, int iters);
+size_t mfma_peak_out_bytes();
+hipError_t launch_mfma_peak(int kind, int iters, void *out, hipStream_t s);
+
 // crt.hip: the CRT form.  Residues of each line's `bits`-bit truncation
 // modulo the first L moduli, int8, in the slice layout with lines_pad a
 // multiple of 256; the GEMM writes per-modulus residues of the product into

@@ -230,3 +230,18 @@ def test_block_sparse_choice_host_only(lib):
     good = rel(10)
     assert lib.tcu_block_sparse_preferred(C.byref(bad), C.byref(good), 4, 4, 4) == _lib.TCU_ERR_ARG
     assert lib.tcu_block_sparse_preferred(C.byref(good), C.byref(good), 0, 4, 4) == _lib.TCU_ERR_ARG
+
+
+def test_mfma_peak_host_only(lib):
+    """The peak probe's operation counts and argument checks need no GPU:
+    2048 workgroups of four waves, eight instructions per wave and round."""
+    assert lib.tcu_mfma_peak_out_bytes() >= 2048 * 256 * 8
+    waves = 2048 * 4 * 8
+    assert lib.tcu_mfma_peak_ops(0, 3) == waves * 3 * 2.0 * 16 * 16 * 4
+    assert lib.tcu_mfma_peak_ops(1, 3) == waves * 3 * 2.0 * 32 * 32 * 32
+    assert lib.tcu_mfma_peak_ops(2, 1) == lib.tcu_mfma_peak_ops(1, 1)
+    assert lib.tcu_mfma_peak_ops(3, 1) == 0.0 and lib.tcu_mfma_peak_ops(0, 0) == 0.0
+    fake = C.c_void_p(0x1000)  # never dereferenced
+    assert lib.tcu_mfma_peak(3, 1, fake, None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_mfma_peak(0, 0, fake, None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_mfma_peak(1, 4, None, None) == _lib.TCU_ERR_ARG
