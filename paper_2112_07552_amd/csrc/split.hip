@@ -82,7 +82,7 @@ row_max_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
 // Max |z| per column: threads own columns, blocks own chunks of rows, and the
 // partial maxima meet in an atomic max on the (monotone) bit patterns of the
 // non-negative doubles.  maxbits must be zero beforehand.
-constexpr int kColChunk = 128;
+constexpr int kColChunk = 64;
 
 __global__ void __launch_bounds__(kThreads)
 col_max_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
