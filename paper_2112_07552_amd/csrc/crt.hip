@@ -501,7 +501,10 @@ __device__ inline double crt_finish(double s0, double s1, double s2, const CrtCo
 // 32) / 8) + row % 4 -- the order in which one lane of the int8 MFMA holds a
 // column of its 32 x 32 block.  A thread takes 8 bytes (8 rows of one column:
 // rows 32 rb + 8 j + 4 h + (0..3) for j = 2 (q % 2) + (0, 1), h = q / 2) from
-// each modulus plane; a wave reads 512 contiguous bytes per modulus.
+// each modulus plane; a wave reads 512 contiguous bytes per modulus.  The
+// modulus count L is a template argument, so that both loops over the
+// planes unroll fully and the residues stay in fixed registers.
+template <int L>
 __global__ void __launch_bounds__(kThreads)
 crt_reconstruct_kernel(int m, int n, const int8_t *__restrict__ res, int64_t plane, CrtConsts cc,
                        const int *__restrict__ ex, const int *__restrict__ ey,
@@ -515,23 +518,19 @@ crt_reconstruct_kernel(int m, int n, const int8_t *__restrict__ res, int64_t pla
 #pragma unroll
     for (int j = 0; j < 8; ++j) s[j][0] = s[j][1] = s[j][2] = 0.0;
     // all of this thread's residue loads first (independent, in flight
-    // together); planes past L read as zero residues
-    uint2 vr[kMaxMod];
+    // together)
+    uint2 vr[L];
 #pragma unroll
-    for (int i = 0; i < kMaxMod; ++i)
-        vr[i] = i < cc.L ? *reinterpret_cast<const uint2 *>(base + (int64_t)i * plane)
-                         : make_uint2(0u, 0u);
+    for (int i = 0; i < L; ++i) vr[i] = *reinterpret_cast<const uint2 *>(base + (int64_t)i * plane);
 #pragma unroll
-    for (int i = 0; i < kMaxMod; ++i) {
-        if (i < cc.L) {  // uniform; keeps the loop fully unrolled
-            const uint2 v = vr[i];
+    for (int i = 0; i < L; ++i) {
+        const uint2 v = vr[i];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const double r = (double)(int8_t)((j < 4 ? v.x : v.y) >> (8 * (j & 3)));
-                s[j][0] = fma(r, cc.w[i][0], s[j][0]);  // exact: |r w| < 2^47, sums < 2^51
-                s[j][1] = fma(r, cc.w[i][1], s[j][1]);
-                s[j][2] = fma(r, cc.w[i][2], s[j][2]);
-            }
+        for (int j = 0; j < 8; ++j) {
+            const double r = (double)(int8_t)((j < 4 ? v.x : v.y) >> (8 * (j & 3)));
+            s[j][0] = fma(r, cc.w[i][0], s[j][0]);  // exact: |r w| < 2^47, sums < 2^51
+            s[j][1] = fma(r, cc.w[i][1], s[j][1]);
+            s[j][2] = fma(r, cc.w[i][2], s[j][2]);
         }
     }
     const int ec = ey[col] - 2 * cc.bits;
@@ -546,6 +545,27 @@ crt_reconstruct_kernel(int m, int n, const int8_t *__restrict__ res, int64_t pla
         }
     }
 }
+
+typedef void (*ReconstructLaunch)(dim3, hipStream_t, int, int, const int8_t *, int64_t,
+                                  const CrtConsts &, const int *, const int *, double *, int64_t,
+                                  int);
+
+template <int L>
+void reconstruct_launch(dim3 grid, hipStream_t s, int m, int n, const int8_t *res, int64_t plane,
+                        const CrtConsts &cc, const int *ex, const int *ey, double *C, int64_t ldc,
+                        int accumulate) {
+    crt_reconstruct_kernel<L><<<grid, kThreads, 0, s>>>(m, n, res, plane, cc, ex, ey, C, ldc,
+                                                        accumulate);
+}
+
+// indexed by the modulus count, 1 .. kMaxMod
+constexpr ReconstructLaunch kReconstruct[kMaxMod + 1] = {
+    nullptr,
+    reconstruct_launch<1>,  reconstruct_launch<2>,  reconstruct_launch<3>,  reconstruct_launch<4>,
+    reconstruct_launch<5>,  reconstruct_launch<6>,  reconstruct_launch<7>,  reconstruct_launch<8>,
+    reconstruct_launch<9>,  reconstruct_launch<10>, reconstruct_launch<11>, reconstruct_launch<12>,
+    reconstruct_launch<13>, reconstruct_launch<14>, reconstruct_launch<15>};
+static_assert(kMaxMod == 15, "one reconstruction instance per modulus count");
 
 // ------------------------------------------------------------- host side
 typedef unsigned __int128 u128;
@@ -650,8 +670,7 @@ hipError_t launch_gemm_crt(int m, int n, int k, int L, int bits, const int8_t *x
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 grid((unsigned)((n + kThreads / 4 - 1) / (kThreads / 4)), (unsigned)((m + 31) / 32));
-    crt_reconstruct_kernel<<<grid, kThreads, 0, s>>>(m, n, res, plane_res, cc, ex, ey, C, ldc,
-                                                     accumulate);
+    kReconstruct[L](grid, s, m, n, res, plane_res, cc, ex, ey, C, ldc, accumulate);
     return hipGetLastError();
 }
 
