@@ -81,3 +81,38 @@ def test_crt_plan_limits():
         ops.crt_plan(131072, 1e-12)   # int32 sums would no longer be exact
     with pytest.raises(ops.TcuError):
         ops.crt_plan(100, 1e-17)      # beyond 53-bit inputs
+
+
+# one tolerance per modulus count the plan can pick (K = 1 reaches L = 2,
+# K = 257 the counts 3 .. 15): the reconstruction has one kernel instance per
+# count, and each must rebuild the truncated product
+_L_SWEEP = [(1, 0.1)] + [(257, t) for t in (0.1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-7, 1e-8, 1e-9,
+                                            1e-10, 1e-11, 1e-13, 1e-14, 1e-15)]
+
+
+@pytest.mark.parametrize("K,tol", _L_SWEEP)
+def test_crt_every_modulus_count(orc, K, tol):
+    dev = cuda_or_skip()
+    M, N = 70, 90
+    A, B = wl.mm_query(M, K, N, seed=K + 7, values="loguniform", device=dev)
+    Cg, _, ws = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, M, K, N,
+                                 precision="crt_i8", tol=tol, unique=True)
+    st, info = ops.sync_status(ws)
+    L, bits = ops.crt_plan(K, tol)
+    assert st == 0 and info["slices"] == L
+    RA, RB = to_orc(orc, A), to_orc(orc, B)
+    X, _ = orc.encode_A(RA, M, K)
+    Y, _ = orc.encode_B(RB, K, N)
+    T = orc.trunc_product(X, Y, bits)
+    C = Cg.cpu().numpy()
+    assert np.all(np.abs(C - T) <= 2.0 ** -50 * np.abs(T))
+    Co, _, _ = orc.join_agg(RA, RB, M, K, N)
+    bound = tol * K * np.outer(np.abs(X).max(axis=1), np.abs(Y).max(axis=0))
+    assert np.all(np.abs(C - Co) <= bound)
+
+
+def test_crt_sweep_covers_every_count():
+    """The sweep above reaches every modulus count from 2 to the maximum
+    (the plan never picks one modulus); host-side plan only."""
+    counts = sorted(ops.crt_plan(K, tol)[0] for K, tol in _L_SWEEP)
+    assert counts == list(range(2, 16))
