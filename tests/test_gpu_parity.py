@@ -82,6 +82,38 @@ def test_encode_duplicates_float_and_skips(orc):
     assert np.all(np.abs(X.cpu().numpy() - Xo) <= bound)
 
 
+@pytest.mark.parametrize("off", [0, 1, 2, 3])
+@pytest.mark.parametrize("values", [True, False])
+def test_encode_alignment_tail_and_skips(orc, off, values):
+    """Columns at any 4-byte offset and any length (10_007 - off records),
+    with and without values: the oracle's bits (integer values, so sums of
+    duplicates are exact) and a count of every out-of-range record."""
+    dev = cuda_or_skip()
+    R = wl.random_relation(10_007, 50, 61, 5 + off, 1, values="int", lo=-1000, hi=1000,
+                           device=dev, bad_fraction=0.02)
+    g, k = R.group[off:], R.key[off:]
+    v = R.val[off:] if values else None
+    ws = ops.alloc_workspace(256, dev)
+    X = ops.encode(g, k, v, 50, 61, ws=ws)
+    st, info = ops.sync_status(ws)
+    Xo, skipped = orc.encode(g.cpu().numpy(), k.cpu().numpy(),
+                             v.cpu().numpy() if values else None, 50, 61)
+    assert skipped > 0 and info["skipped_a"] == skipped
+    assert np.array_equal(X.cpu().numpy(), Xo)
+    Xt = ops.encode(g, k, v, 61, 50, transpose=True)
+    assert np.array_equal(Xt.cpu().numpy(), Xo.T)
+
+
+@pytest.mark.parametrize("off", [0, 2])
+def test_encode_unique_float32_offsets(orc, off):
+    dev = cuda_or_skip()
+    R = wl.dense_relation(61, 50, 8, 1, device=dev, dtype=torch.float32)
+    g, k, v = R.group[off:], R.key[off:], R.val[off:]
+    X = ops.encode(g, k, v, 50, 61, unique=True)  # groups are the 50 columns
+    Xo, _ = orc.encode(g.cpu().numpy(), k.cpu().numpy(), v.cpu().to(torch.float64).numpy(), 50, 61)
+    assert np.array_equal(X.cpu().numpy(), Xo)
+
+
 # -------------------------------------------------------------------- gemm --
 
 GEMM_SHAPES = [(1, 1, 1), (17, 33, 5), (128, 128, 16), (129, 255, 130), (300, 200, 67),
