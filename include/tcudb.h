@@ -16,7 +16,8 @@
  *  - Array pointers are DEVICE pointers owned by the caller.  The library never
  *    allocates, frees or keeps caller memory.  Its only global state is one
  *    internal non-blocking stream per device (tcu_join_agg_bwd), created on
- *    first use and kept for the life of the process.
+ *    first use and kept for the life of the process, and the device array
+ *    that tcu_join_agg_fwd_noalloc uses as its workspace.
  *  - Work is enqueued on the caller's stream and is asynchronous unless a call
  *    says otherwise; results are valid once the stream has reached that point.
  *    Work a call puts on an internal stream is ordered after the caller's
@@ -203,6 +204,28 @@ tcu_status tcu_gemm_f64(int trans_a, int trans_b, int32_t m, int32_t n, int32_t 
 tcu_status tcu_join_agg_fwd(const tcu_relation *A, const tcu_relation *B, int32_t M, int32_t K,
                             int32_t N, tcu_precision p, double tol, double *C, int32_t *count,
                             void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * forward of tcu_join_agg_fwd with the same arguments and results, whose
+ * workspace is the library's own device array of TCU_NOALLOC_MAX_BYTES
+ * bytes instead of a caller buffer.  Each device the library runs on holds
+ * one such array from module load until the process ends.  The call itself
+ * allocates nothing (no hipMalloc, no library routine that allocates).
+ * Returns TCU_ERR_WORKSPACE, launching nothing, when these shapes and this
+ * precision need more than TCU_NOALLOC_MAX_BYTES (tcu_workspace_bytes with
+ * flags 0 tells), e.g. beyond M = K = N = 2048 in the FP64 form.
+ * status: NULL, or a 256-byte aligned device buffer of 256 bytes that
+ *    receives the call's status block, which tcu_sync_status(status, ...)
+ *    then reads (out-of-range records, non-finite values).
+ * All calls on one device share its array and leave their contents in it:
+ * calls that may overlap on one device (different streams, or host threads
+ * without ordering) race and give wrong results.  Every call clears and
+ * rewrites what it reads, so ordered calls are independent. */
+#define TCU_NOALLOC_MAX_BYTES ((64u << 20) + (64u << 10))
+tcu_status tcu_join_agg_fwd_noalloc(const tcu_relation *A, const tcu_relation *B, int32_t M,
+                                    int32_t K, int32_t N, tcu_precision p, double tol, double *C,
+                                    int32_t *count, void *status, hipStream_t stream);
 
 /* Step a4, the adjoint of the operator for L = sum_{g,h} dC[g,h] C[g,h]:
  *   dA_val[i] = sum_{b: b.k == a_i.k} dC[a_i.g, b.h] * b.w = (dC Y^T)[a_i.g, a_i.k]

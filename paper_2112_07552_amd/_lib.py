@@ -33,11 +33,12 @@ TCU_WS_BACKWARD = 1
 TCU_WS_COUNT = 2
 
 TCU_REL_UNIQUE_CELLS = 1
+TCU_NOALLOC_MAX_BYTES = (64 << 20) + (64 << 10)
 TCU_BWD_SAVED_ENCODINGS = 1
 
 EXPORTS = (
     "tcu_workspace_bytes", "tcu_split_slices", "tcu_crt_plan", "tcu_split", "tcu_encode", "tcu_gemm_f64",
-    "tcu_join_agg_fwd", "tcu_join_agg_bwd", "tcu_dict_workspace_bytes", "tcu_dict_encode",
+    "tcu_join_agg_fwd", "tcu_join_agg_fwd_noalloc", "tcu_join_agg_bwd", "tcu_dict_workspace_bytes", "tcu_dict_encode",
     "tcu_join_agg_row_workspace_bytes", "tcu_join_agg_row",
     "tcu_join_agg_bsr_workspace_bytes", "tcu_join_agg_bsr", "tcu_block_sparse_preferred",
     "tcu_nonzero_workspace_bytes",
@@ -93,6 +94,9 @@ def load():
     L.tcu_join_agg_fwd.argtypes = [rel_p, rel_p, i32, i32, i32, C.c_int, f64, vp, vp, vp,
                                    C.c_size_t, vp]
     L.tcu_join_agg_fwd.restype = C.c_int
+    L.tcu_join_agg_fwd_noalloc.argtypes = [rel_p, rel_p, i32, i32, i32, C.c_int, f64, vp, vp,
+                                           vp, vp]
+    L.tcu_join_agg_fwd_noalloc.restype = C.c_int
     L.tcu_join_agg_bwd.argtypes = [rel_p, rel_p, i32, i32, i32, C.c_int, f64, vp, vp, vp,
                                    C.c_int, vp, C.c_size_t, vp]
     L.tcu_join_agg_bwd.restype = C.c_int

@@ -370,6 +370,16 @@ tcu_status tcu_gemm_f64(int trans_a, int trans_b, int32_t m, int32_t n, int32_t 
 tcu_status tcu_join_agg_fwd(const tcu_relation *A, const tcu_relation *B, int32_t M, int32_t K,
                             int32_t N, tcu_precision p, double tol, double *C, int32_t *count,
                             void *ws, size_t ws_bytes, hipStream_t stream) {
+    return join_agg_fwd_ws(A, B, M, K, N, p, tol, C, count, ws, ws_bytes, stream);
+}
+
+}  // extern "C"
+
+// The forward on a given workspace: the body of tcu_join_agg_fwd, shared with
+// tcu_join_agg_fwd_noalloc (whose workspace is the library's own device array).
+tcu_status tcu::join_agg_fwd_ws(const tcu_relation *A, const tcu_relation *B, int32_t M,
+                                int32_t K, int32_t N, tcu_precision p, double tol, double *C,
+                                int32_t *count, void *ws, size_t ws_bytes, hipStream_t stream) {
     if (!relation_ok(A) || !relation_ok(B) || !shapes_ok(M, K, N) || C == nullptr)
         return TCU_ERR_ARG;
     if (!precision_ok(p)) return TCU_ERR_ARG;
@@ -410,6 +420,13 @@ tcu_status tcu_join_agg_fwd(const tcu_relation *A, const tcu_relation *B, int32_
     TCU_TRY(mixed_multiply(M, N, K, mp, p, ws, L, C, N, stream));
     return TCU_OK;
 }
+
+size_t tcu::join_agg_fwd_ws_bytes(int32_t M, int32_t K, int32_t N, tcu_precision p) {
+    if (!shapes_ok(M, K, N) || !precision_ok(p)) return 0;
+    return plan_layout(M, K, N, p, 0).total;
+}
+
+extern "C" {
 
 tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_t M, int32_t K,
                             int32_t N, tcu_precision p, double tol, const double *dC,

@@ -27,6 +27,13 @@ constexpr size_t kAlign = 256;
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// api.hip: the body of tcu_join_agg_fwd on a given workspace, and the
+// workspace bytes it needs (0 for invalid shapes or precision).
+tcu_status join_agg_fwd_ws(const tcu_relation *A, const tcu_relation *B, int32_t M, int32_t K,
+                           int32_t N, tcu_precision p, double tol, double *C, int32_t *count,
+                           void *ws, size_t ws_bytes, hipStream_t stream);
+size_t join_agg_fwd_ws_bytes(int32_t M, int32_t K, int32_t N, tcu_precision p);
+
 // encode.hip
 hipError_t launch_zero_f64(double *p, size_t n, hipStream_t s);
 hipError_t launch_clear_status(StatusBlock *st, hipStream_t s, uint32_t slices = 0);

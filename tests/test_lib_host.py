@@ -245,3 +245,23 @@ def test_mfma_peak_host_only(lib):
     assert lib.tcu_mfma_peak(3, 1, fake, None) == _lib.TCU_ERR_ARG
     assert lib.tcu_mfma_peak(0, 0, fake, None) == _lib.TCU_ERR_ARG
     assert lib.tcu_mfma_peak(1, 4, None, None) == _lib.TCU_ERR_ARG
+
+
+def test_noalloc_rejects_before_touching_the_device(lib):
+    A, B = rel(10), rel(10)
+    cbuf = C.c_void_p(0x2000)
+    # shapes whose workspace exceeds the library's array: refused on the host
+    assert lib.tcu_join_agg_fwd_noalloc(C.byref(A), C.byref(B), 4096, 4096, 4096, 0, 0.0, cbuf,
+                                        None, None, None) == _lib.TCU_ERR_WORKSPACE
+    # invalid shapes, precision and a misaligned status buffer
+    assert lib.tcu_join_agg_fwd_noalloc(C.byref(A), C.byref(B), 0, 4, 4, 0, 0.0, cbuf, None,
+                                        None, None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_join_agg_fwd_noalloc(C.byref(A), C.byref(B), 4, 4, 4, 9, 0.0, cbuf, None,
+                                        None, None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_join_agg_fwd_noalloc(C.byref(A), C.byref(B), 4, 4, 4, 0, 0.0, cbuf, None,
+                                        C.c_void_p(0x1010), None) == _lib.TCU_ERR_ARG
+    # the largest FP64 shape it holds
+    need = lib.tcu_workspace_bytes(C.byref(A), C.byref(B), 2048, 2048, 2048, 0, 0)
+    assert need <= _lib.TCU_NOALLOC_MAX_BYTES
+    assert lib.tcu_workspace_bytes(C.byref(A), C.byref(B), 2200, 2048, 2200, 0, 0) > \
+        _lib.TCU_NOALLOC_MAX_BYTES
