@@ -528,3 +528,128 @@ int orc_trunc_product(int32_t M, int32_t K, int32_t N, const double *X, const do
     free(ex); free(ey); free(xi); free(yt);
     return used;
 }
+
+/*
+ * The certificate of a mixed-form product C = X Y: the plan of step a0
+ * (Section 4.2.1's feasibility test, which reads the operands' magnitudes to
+ * choose the narrow type, retargeted), written from its definition and
+ * without the rounding margins a device evaluation adds.
+ * X is M x K and Y is K x N, row-major FP64.  Per line (row g of X, column h
+ * of Y):
+ *   e = the exponent with 2^(e - 1) <= max |z| < 2^e (0 for a zero line),
+ *   q = floor(|z| 2^(7 - e)) for every entry, 0 <= q <= 127,
+ *   s = sum over the line of |z| 2^-e (compensated sum, one final rounding);
+ * per cell:
+ *   T[g,h] = sum_k qX[g,k] qY[k,h] (exact), r = 2^14 (s_g + s_h), or r = 0
+ *   when s_g or s_h is 0 (an all-zero line: every term of the cell is 0).
+ * need_bits = max over cells of the smallest b >= 1 with r <= 2^b tcrt T,
+ * need_slices = max over cells of the smallest S in 1..8 with
+ *   r + (S - 1) 2^14 K <= 2^(7S) tdig[S] T  (9 when no S meets it);
+ * a cell with T = 0 needs 0 when r = 0 and 255 of each otherwise.
+ * umax[0], umax[1]: the largest s over the rows of X and the columns of Y.
+ * T_out (M x N) and s_out (M + N: rows, then columns) may be NULL.
+ * Returns -1 for non-finite inputs, else the number of threads used.
+ */
+static double line_sum_scaled(const double *z, int64_t n, int64_t stride, int e) {
+    double hi = 0.0, lo = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double s, err;
+        two_sum(hi, fabs(z[i * stride]), &s, &err);
+        hi = s;
+        lo += err;
+    }
+    return ldexp(hi + lo, -e);
+}
+
+static int line_exponent_of(const double *z, int64_t n, int64_t stride, int *bad) {
+    double mx = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double v = z[i * stride];
+        if (!isfinite(v)) *bad = 1;
+        else if (fabs(v) > mx) mx = fabs(v);
+    }
+    int e = 0;
+    if (mx > 0.0) frexp(mx, &e);
+    return e;
+}
+
+int orc_certificate(int32_t M, int32_t K, int32_t N, const double *X, const double *Y,
+                    double tcrt, const double *tdig, uint32_t *need_bits, uint32_t *need_slices,
+                    double *umax, int64_t *T_out, double *s_out, int threads) {
+    int *ex = (int *)malloc(sizeof(int) * (size_t)(M > 0 ? M : 1));
+    int *ey = (int *)malloc(sizeof(int) * (size_t)(N > 0 ? N : 1));
+    double *sx = (double *)malloc(sizeof(double) * (size_t)(M > 0 ? M : 1));
+    double *sy = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+    int32_t *qx = (int32_t *)malloc(sizeof(int32_t) * ((size_t)M * (size_t)K + 1));
+    int32_t *qyt = (int32_t *)malloc(sizeof(int32_t) * ((size_t)K * (size_t)N + 1));
+    if (!ex || !ey || !sx || !sy || !qx || !qyt) {
+        free(ex); free(ey); free(sx); free(sy); free(qx); free(qyt);
+        return -2;
+    }
+    int bad = 0;
+    umax[0] = umax[1] = 0.0;
+    for (int32_t g = 0; g < M; ++g) {
+        const double *row = X + (size_t)g * K;
+        ex[g] = line_exponent_of(row, K, 1, &bad);
+        sx[g] = line_sum_scaled(row, K, 1, ex[g]);
+        if (sx[g] > umax[0]) umax[0] = sx[g];
+        for (int32_t k = 0; k < K; ++k)
+            qx[(size_t)g * K + k] = (int32_t)floor(ldexp(fabs(row[k]), 7 - ex[g]));
+    }
+    for (int32_t h = 0; h < N; ++h) {
+        ey[h] = line_exponent_of(Y + h, K, N, &bad);
+        sy[h] = line_sum_scaled(Y + h, K, N, ey[h]);
+        if (sy[h] > umax[1]) umax[1] = sy[h];
+        for (int32_t k = 0; k < K; ++k)
+            qyt[(size_t)h * K + k] = (int32_t)floor(ldexp(fabs(Y[(size_t)k * N + h]), 7 - ey[h]));
+    }
+    if (bad) {
+        free(ex); free(ey); free(sx); free(sy); free(qx); free(qyt);
+        return -1;
+    }
+    if (s_out != NULL) {
+        memcpy(s_out, sx, sizeof(double) * (size_t)M);
+        memcpy(s_out + M, sy, sizeof(double) * (size_t)N);
+    }
+    uint32_t nb = 0, ns = 0;
+    int used = 1;
+#pragma omp parallel num_threads(threads) reduction(max : nb, ns)
+    {
+#pragma omp single
+        used = omp_get_num_threads();
+#pragma omp for schedule(dynamic, 4)
+        for (int32_t g = 0; g < M; ++g) {
+            for (int32_t h = 0; h < N; ++h) {
+                int64_t T = 0;
+                for (int32_t k = 0; k < K; ++k)
+                    T += (int64_t)qx[(size_t)g * K + k] * (int64_t)qyt[(size_t)h * K + k];
+                if (T_out != NULL) T_out[(size_t)g * N + h] = T;
+                const long double r = (sx[g] > 0.0 && sy[h] > 0.0)
+                                          ? 16384.0L * ((long double)sx[g] + (long double)sy[h])
+                                          : 0.0L;
+                uint32_t cb, cs;
+                if (T == 0) {
+                    cb = cs = r > 0.0L ? 255u : 0u;
+                } else {
+                    const long double tT = (long double)tcrt * (long double)T;
+                    cb = 1;
+                    while (cb < 254 && r > ldexpl(tT, (int)cb)) ++cb;
+                    cs = 9;
+                    for (int S = 1; S <= 8; ++S) {
+                        const long double lhs = r + (long double)(S - 1) * 16384.0L * K;
+                        if (lhs <= ldexpl((long double)tdig[S] * (long double)T, 7 * S)) {
+                            cs = (uint32_t)S;
+                            break;
+                        }
+                    }
+                }
+                if (cb > nb) nb = cb;
+                if (cs > ns) ns = cs;
+            }
+        }
+    }
+    *need_bits = nb;
+    *need_slices = ns;
+    free(ex); free(ey); free(sx); free(sy); free(qx); free(qyt);
+    return used;
+}

@@ -71,6 +71,10 @@ def lib():
         L.orc_trunc_product.argtypes = [C.c_int32, C.c_int32, C.c_int32, _f64p, _f64p, C.c_int,
                                         _f64p, C.c_int]
         L.orc_trunc_product.restype = C.c_int
+        L.orc_certificate.argtypes = [C.c_int32, C.c_int32, C.c_int32, _f64p, _f64p, C.c_double,
+                                      _f64p, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                      _f64p, _i64p, _f64p, C.c_int]
+        L.orc_certificate.restype = C.c_int
         _lib = L
     return _lib
 
@@ -274,3 +278,32 @@ def trunc_product(X, Y, bits: int, threads: Optional[int] = None):
         raise MemoryError("oracle: allocation failed")
     return out
 
+
+
+def certificate(X, Y, tcrt: float, tdig, with_detail: bool = False,
+                threads: Optional[int] = None):
+    """The certificate of the mixed-form product X Y (oracle.c,
+    orc_certificate): returns (need_bits, need_slices, (umax_x, umax_y)) and,
+    with_detail, also T (M x N int64) and the normalised line sums (rows of
+    X, then columns of Y).  tdig: 9 tolerances indexed by the digit count
+    (entry 0 unused)."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    M, K = X.shape
+    K2, N = Y.shape
+    assert K == K2
+    td = np.ascontiguousarray(tdig, dtype=np.float64)
+    assert td.shape == (9,)
+    nb, ns = C.c_uint32(0), C.c_uint32(0)
+    umax = np.zeros(2)
+    T = np.empty((M, N), dtype=np.int64) if with_detail else None
+    sums = np.empty(M + N) if with_detail else None
+    r = lib().orc_certificate(M, K, N, _p(X, _f64p), _p(Y, _f64p), float(tcrt), _p(td, _f64p),
+                              C.byref(nb), C.byref(ns), _p(umax, _f64p), _p(T, _i64p),
+                              _p(sums, _f64p), threads or threads_default())
+    if r == -1:
+        raise FloatingPointError("oracle.certificate: non-finite input")
+    if r < 0:
+        raise MemoryError("oracle: allocation failed")
+    out = (nb.value, ns.value, (float(umax[0]), float(umax[1])))
+    return out + (T, sums) if with_detail else out
