@@ -1,21 +1,30 @@
 """Benchmark of the join-aggregate-as-GEMM operator (TCUDB, Section 5.4.1
 workload: the matrix multiplication query over dense synthetic tables).
 
-One step = one pass of the whole path over one batch of resident input:
-forward (encode A -> X, encode B -> Y, C = X Y) plus the adjoint
-(dX = W Y^T, dY = X^T W, gathers to the records), FP64, N x N x N with
-N^2 records per table.  The tables store matrices, so their cells are
-unique (declared to the library); the adjoint reuses the forward's X and Y
-(saved activations, which fit easily in HBM).  The checkpointed variant
-(re-encoding in the adjoint) is timed and reported beside it.  Prints one
-JSON line.
+Headline (`value`): the largest workload on one GPU, the paper's largest MM
+query: 2^30 records per table (N = 32768), FP32 values drawn from N(0,1)
+with 5% of them multiplied by 1e3 (seed 4).  One step = the forward
+(encode A -> X, encode B -> Y, certified plan, C = X Y) plus the adjoint
+with activation checkpointing (X and Y re-encoded from the records, dX =
+W Y^T and dY = X^T W, gathers to the records), in the residue form (int8
+residues on the matrix cores, Chinese-remainder reconstruction in FP64)
+with the per-cell guarantee |C - C*| <= 1e-12 (|X||Y|).  The FP64 form on
+the same step is the comparator.  Inputs are resident in HBM.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--n 4096]
+The other legs of the same JSON line: the 2^24-record workloads (FP64 on
+U[-1,1), seed 2; every mixed form on log-uniform values, seed 3), the
+forward at 2^14 and 2^20 records (seeds 0 and 1), the library FP64 GEMM
+ceiling (torch.matmul), measured matrix-core rates, and the query family.
+
+The dominant kernel's duration is measured inside the timed steps: the
+library records HIP events around every launch of its matrix-core product
+kernels on the stream each launch runs on (tcu_trace_launches).
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--legs all]
 """
 import argparse
 import ctypes as C
 import json
-import math
 import os
 import sys
 import time
@@ -24,16 +33,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_F64_MFMA_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
+# MI355X published dense peaks
+PEAK_F64_MFMA_TFLOPS = 78.6
+PEAK_I8_MFMA_TOPS = 5000.0
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
+TOL = 1e-12
+
+METRIC = "elements/sec fwd & fwd+adjoint at 1 GPU; % HBM/MFMA roofline; err vs FP64"
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_gemm_f64_mm_query_4096.md")
-GEMM_SOURCE = os.path.join(ROOT, "paper_2112_07552_amd", "csrc", "gemm_f64.hip")
 
 
 def code_digest(path):
@@ -48,58 +59,98 @@ def code_digest(path):
     return hashlib.sha256("\n".join(ln for ln in lines if ln).encode()).hexdigest()
 
 
-def counter_traffic():
-    """HBM bytes per NN launch from the committed counter summary, or None.
-
-    The summary records FETCH_SIZE and WRITE_SIZE per dispatch, already
-    scaled by the plain-copy calibration, and the code digest (code_digest)
-    of the kernel source they were taken with; changed code makes the figure
-    stale, so it is not reported."""
+def counter_traffic(summary, key, source):
+    """HBM bytes per launch of one kernel from a committed counter summary
+    under profiles/ (a line `traffic: <key>=<bytes> code_sha256=<digest>`,
+    FETCH_SIZE + WRITE_SIZE scaled by the plain-copy calibration), or None
+    when the summary is missing or was taken with different kernel code."""
     import re
     try:
-        text = open(COUNTERS_FILE).read()
-        src = code_digest(GEMM_SOURCE)
+        text = open(os.path.join(ROOT, "profiles", summary)).read()
+        src = code_digest(os.path.join(ROOT, "paper_2112_07552_amd", "csrc", source))
     except OSError:
         return None
-    m = re.search(r"traffic: nn_bytes=(\d+) code_sha256=([0-9a-f]{64})", text)
+    m = re.search(rf"traffic: {key}=(\d+) code_sha256=([0-9a-f]{{64}})", text)
     if not m or m.group(2) != src:
         return None
     return int(m.group(1))
 
 
-def sampled_errors(orc, RA, RB, W, N, Cm, dA, dB, seed, ncells, nrec=512):
-    """Errors of one forward + adjoint (C in Cm, gradients in dA, dB) against
-    the oracle on samples: the componentwise err_cw = |C - C*| / (|X||Y|) on
-    `ncells` random cells and on `nrec` random records of each gradient
-    (scaled by the oracle's gradient of |values| with |W|), the normwise ratio
-    |C - C*|_2 / |C*|_2 over the sampled cells, and the mean absolute
-    percentage error over the sampled cells with |C*| >= 1e-3 (|X||Y|)."""
-    import numpy as np
-    import torch
-    rng = np.random.default_rng(seed)
-    cg = rng.integers(0, N, ncells).astype(np.int32)
-    ch = rng.integers(0, N, ncells).astype(np.int32)
-    RAa = orc.Rel(RA.group, RA.key, np.abs(RA.val))
-    RBa = orc.Rel(RB.group, RB.key, np.abs(RB.val))
-    vo, _ = orc.join_agg_cells(RA, RB, N, N, N, cg, ch)
-    so, _ = orc.join_agg_cells(RAa, RBa, N, N, N, cg, ch)
-    dev = Cm.device
-    c = Cm[torch.from_numpy(cg.astype(np.int64)).to(dev),
-           torch.from_numpy(ch.astype(np.int64)).to(dev)].cpu().numpy()
-    diff = np.abs(c - vo)
-    sig = np.abs(vo) >= 1e-3 * so
-    out = {"cells": ncells, "err_cw": float(np.max(diff / so)),
-           "normwise_sampled": float(np.linalg.norm(c - vo) / np.linalg.norm(vo)),
-           "mape_pct_sampled": float(100.0 * np.mean(diff[sig] / np.abs(vo[sig]))) if sig.any() else None,
-           "mape_cells": int(sig.sum()), "records": nrec}
-    Wn = W.cpu().numpy()
-    for name, R, g in (("dA", RA, dA), ("dB", RB, dB)):
-        idx = rng.choice(R.val.shape[0], nrec, replace=False).astype(np.int64)
-        ref = orc.grad(RA, RB, N, N, N, Wn, name[1], idx=idx)
-        scale = orc.grad(RAa, RBa, N, N, N, np.abs(Wn), name[1], idx=idx)
-        got = g[torch.from_numpy(idx).to(dev)].cpu().numpy()
-        out[f"err_cw_{name}"] = float(np.max(np.abs(got - ref) / scale))
-    return out
+class Hip:
+    """HIP events through the runtime library torch has loaded."""
+
+    def __init__(self):
+        self.rt = C.CDLL("libamdhip64.so")
+        self.rt.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
+        self.rt.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+        self.rt.hipEventDestroy.argtypes = [C.c_void_p]
+
+    def event(self):
+        ev = C.c_void_p()
+        if self.rt.hipEventCreate(C.byref(ev)) != 0:
+            raise RuntimeError("hipEventCreate failed")
+        return ev.value
+
+    def elapsed_ms(self, a, b):
+        ms = C.c_float()
+        if self.rt.hipEventElapsedTime(C.byref(ms), C.c_void_p(a), C.c_void_p(b)) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return float(ms.value)
+
+    def destroy(self, ev):
+        self.rt.hipEventDestroy(C.c_void_p(ev))
+
+
+class LaunchTrace:
+    """Records of the library's matrix-core, encode and gather launches made
+    inside a `with` block (tcu_trace_launches), with their durations."""
+
+    def __init__(self, hip, capacity=512):
+        from paper_2112_07552_amd import _lib
+        self.hip, self.L = hip, _lib.load()
+        self.recs = (_lib.tcu_launch_record * capacity)()
+        for r in self.recs:
+            r.begin, r.end = hip.event(), hip.event()
+        self.count = C.c_int32(0)
+        self.capacity = capacity
+
+    def __enter__(self):
+        from paper_2112_07552_amd import _lib
+        _lib.check(self.L.tcu_trace_launches(self.recs, self.capacity, C.byref(self.count)),
+                   "tcu_trace_launches")
+        return self
+
+    def __exit__(self, *exc):
+        self.L.tcu_trace_launches(None, 0, None)
+        return False
+
+    def launches(self, kernel):
+        """[(ms, ops, m, n, k, planes)] of the recorded launches of one kernel
+        (call after the stream has finished the work)."""
+        out = []
+        for r in self.recs[:min(self.count.value, self.capacity)]:
+            if r.kernel == kernel:
+                out.append((self.hip.elapsed_ms(r.begin, r.end), r.ops, r.m, r.n, r.k, r.planes))
+        return out
+
+    def close(self):
+        for r in self.recs:
+            self.hip.destroy(r.begin)
+            self.hip.destroy(r.end)
+
+
+def launch_stats(launches, per_unit, unit_name):
+    """Average duration and rate over recorded launches: `per_unit` is what
+    one unit of `ops` is (e.g. 1 FLOP, 1 byte)."""
+    if not launches:
+        return None
+    ms = sum(x[0] for x in launches)
+    ops = sum(x[1] for x in launches)
+    shapes = sorted({(x[2], x[3], x[4], x[5]) for x in launches})
+    return {"launches": len(launches), "avg_ms": ms / len(launches),
+            "avg_ops_per_launch": ops / len(launches),
+            f"achieved_{unit_name}": ops / (ms * 1e-3) / per_unit,
+            "shapes_m_n_k_planes": [list(s) for s in shapes]}
 
 
 def time_loop(fn, steps, warmup, stream):
@@ -117,53 +168,426 @@ def time_loop(fn, steps, warmup, stream):
     return start.elapsed_time(end) / steps  # ms
 
 
-def cpu_baseline(A, B, N, W, target_s=20.0):
-    """The FP64 oracle (as it stands) on a bounded sample of the same step:
-    forward rows of C for S groups, and the adjoint for the S*N records of A
-    in those groups plus S*N records of B.  Elements/s = S*N / time."""
+class Operator:
+    """One workload's relations and buffers, and the C-ABI calls of a step
+    on the current stream (argument marshalling only)."""
+
+    def __init__(self, A, B, W, M, K, N, stream):
+        import torch
+        from paper_2112_07552_amd import _lib, ops
+        self.L, self.ops, self._lib = _lib.load(), ops, _lib
+        self.A, self.B, self.W = A, B, W
+        self.M, self.K, self.N = M, K, N
+        self.relA = ops.make_relation(A.group, A.key, A.val, unique=True)
+        self.relB = ops.make_relation(B.group, B.key, B.val, unique=True)
+        dev = A.group.device
+        self.C = torch.empty((M, N), dtype=torch.float64, device=dev)
+        self.dA = torch.empty(A.n, dtype=torch.float64, device=dev)
+        self.dB = torch.empty(B.n, dtype=torch.float64, device=dev)
+        self.sp = C.c_void_p(stream.cuda_stream)
+        self.ws = None
+        self.prec = None
+
+    def use(self, precision, backward=True):
+        import torch
+        self.ws = None
+        torch.cuda.empty_cache()
+        nb = self.ops.workspace_bytes(self.relA, self.relB, self.M, self.K, self.N, precision,
+                                      backward=backward)
+        self.ws = self.ops.alloc_workspace(nb, self.A.group.device)
+        self.prec = self.ops.PRECISIONS[precision]
+        self.precision = precision
+        return nb
+
+    def fwd(self):
+        self._lib.check(self.L.tcu_join_agg_fwd(
+            C.byref(self.relA), C.byref(self.relB), self.M, self.K, self.N, self.prec, TOL,
+            C.c_void_p(self.C.data_ptr()), None, C.c_void_p(self.ws.data_ptr()),
+            self.ws.numel(), self.sp), "fwd")
+
+    def bwd(self, saved):
+        flags = self._lib.TCU_BWD_SAVED_ENCODINGS if saved else 0
+        self._lib.check(self.L.tcu_join_agg_bwd(
+            C.byref(self.relA), C.byref(self.relB), self.M, self.K, self.N, self.prec, TOL,
+            C.c_void_p(self.W.data_ptr()), C.c_void_p(self.dA.data_ptr()),
+            C.c_void_p(self.dB.data_ptr()), flags, C.c_void_p(self.ws.data_ptr()),
+            self.ws.numel(), self.sp), "bwd")
+
+    def step(self, saved=False):
+        self.fwd()
+        self.bwd(saved)
+
+    def status(self):
+        st, info = self.ops.sync_status(self.ws)
+        if st != 0:
+            raise RuntimeError(f"{self.precision}: device status {st}: {info}")
+        return info
+
+    def release(self):
+        import torch
+        self.ws = None
+        torch.cuda.empty_cache()
+
+
+def timed_with_trace(hip, fn, steps, warmup, stream, capacity=512):
+    """ms per call of fn over `steps` timed calls after `warmup`, with the
+    library's launches inside the timed calls recorded."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    tr = LaunchTrace(hip, capacity)
+    with tr:
+        ms = time_loop(fn, steps, 0, stream)
+    torch.cuda.synchronize()
+    return ms, tr
+
+
+def block_reference(A, B, W, N, R, seed):
+    """The oracle on an R x R block of C of the N x N x N workload (rows,
+    columns and keys drawn at random), with the value gradients of the A
+    records in (rows x keys) and the B records in (keys x columns): 3 R^2 N
+    multiply-adds, a fraction R^2 / N^2 of one forward + adjoint step.
+    The records are selected on the device (selection, no arithmetic of the
+    operator) and copied to the host.  Returns the reference, its scales
+    (the same sums of absolute values, untimed) and the oracle's time."""
     import numpy as np
+    import torch
     from oracle import oracle as orc
 
-    RA = orc.Rel(A.group.cpu().numpy(), A.key.cpu().numpy(), A.val.cpu().numpy())
-    RB = orc.Rel(B.group.cpu().numpy(), B.key.cpu().numpy(), B.val.cpu().numpy())
-    Wn = W.cpu().numpy()
-    ga = RA.group
+    dev = A.group.device
+    rng = np.random.default_rng(seed)
+    pick = lambda: np.sort(rng.choice(N, R, replace=False))
+    rows, cols, keys = pick(), pick(), pick()
 
-    def run(S):
-        rows = np.arange(S, dtype=np.int32)
-        ia = np.nonzero(ga < S)[0].astype(np.int64)
-        ib = np.arange(S * N, dtype=np.int64)
+    def lut(sel):
+        t = torch.full((N,), -1, dtype=torch.int64, device=dev)
+        t[torch.as_tensor(sel, device=dev)] = torch.arange(R, device=dev)
+        return t
+
+    lr, lc, lk = lut(rows), lut(cols), lut(keys)
+    ga, ka = lr[A.group.long()], lk[A.key.long()]
+    hb, kb = lc[B.group.long()], lk[B.key.long()]
+
+    def take(mask, *cols_):
+        idx = torch.nonzero(mask).flatten()
+        return [c[idx].cpu().numpy() for c in cols_] + [idx.cpu().numpy()]
+
+    f64 = lambda v: v.to(torch.float64)
+    # forward block: A records with g in rows, B records with h in cols
+    a_g, a_k, a_v, _ = take(ga >= 0, ga, A.key, f64(A.val))
+    b_h, b_k, b_v, _ = take(hb >= 0, hb, B.key, f64(B.val))
+    # dA: A records in rows x keys against B records with k in keys
+    sa_g, sa_k, sa_v, ia = take((ga >= 0) & (ka >= 0), ga, ka, f64(A.val))
+    bk_h, bk_k, bk_v, _ = take(kb >= 0, B.group, kb, f64(B.val))
+    # dB: B records in keys x cols against A records with k in keys
+    sb_h, sb_k, sb_v, ib = take((hb >= 0) & (kb >= 0), hb, kb, f64(B.val))
+    ak_g, ak_k, ak_v, _ = take(ka >= 0, A.group, ka, f64(A.val))
+    Wr = W[torch.as_tensor(rows, device=dev)].cpu().numpy()
+    Wc = W[:, torch.as_tensor(cols, device=dev)].contiguous().cpu().numpy()
+    del ga, ka, hb, kb
+    torch.cuda.empty_cache()
+    i32 = lambda x: x.astype(np.int32)
+    Rel = orc.Rel
+    fa, fb = Rel(i32(a_g), i32(a_k), a_v), Rel(i32(b_h), i32(b_k), b_v)
+    ga_, gb_ = Rel(i32(sa_g), i32(sa_k), sa_v), Rel(i32(bk_h), i32(bk_k), bk_v)
+    da_, db_ = Rel(i32(ak_g), i32(ak_k), ak_v), Rel(i32(sb_h), i32(sb_k), sb_v)
+    absr = lambda r: Rel(r.group, r.key, np.abs(r.val))
+    t0 = time.perf_counter()
+    Cb, _, used = orc.join_agg(fa, fb, R, N, R)
+    gA = orc.grad(ga_, gb_, R, R, N, Wr, "A")
+    gB = orc.grad(da_, db_, N, R, R, Wc, "B")
+    t_oracle = time.perf_counter() - t0
+    Sb, _, _ = orc.join_agg(absr(fa), absr(fb), R, N, R)
+    sA = orc.grad(absr(ga_), absr(gb_), R, R, N, np.abs(Wr), "A")
+    sB = orc.grad(absr(da_), absr(db_), N, R, R, np.abs(Wc), "B")
+    return {"rows": rows, "cols": cols, "C": Cb, "S": Sb, "ia": ia, "gA": gA, "sA": sA,
+            "ib": ib, "gB": gB, "sB": sB, "oracle_s": t_oracle, "threads": int(used),
+            "R": R}
+
+
+def block_errors(ref, Cm, dA, dB):
+    import numpy as np
+    import torch
+    dev = Cm.device
+    blk = Cm[torch.as_tensor(ref["rows"], device=dev)][:, torch.as_tensor(ref["cols"], device=dev)]
+    e = {"C": float(np.max(np.abs(blk.cpu().numpy() - ref["C"]) / ref["S"]))}
+    ga = dA[torch.as_tensor(ref["ia"], device=dev)].cpu().numpy()
+    gb = dB[torch.as_tensor(ref["ib"], device=dev)].cpu().numpy()
+    e["dA"] = float(np.max(np.abs(ga - ref["gA"]) / ref["sA"]))
+    e["dB"] = float(np.max(np.abs(gb - ref["gB"]) / ref["sB"]))
+    e["max"] = max(e.values())
+    e["cells"], e["records_A"], e["records_B"] = int(ref["C"].size), len(ref["ia"]), len(ref["ib"])
+    return e
+
+
+def leg_headline(args, stream, hip):
+    """2^30 records per table (N = 32768, FP32 mixture values, seed 4): the
+    residue form's forward + checkpointed adjoint (the headline), its
+    forward alone, the FP64 form's step as the comparator, errors of both on
+    the oracle's block, and the oracle's own rate on that block."""
+    import torch
+    from paper_2112_07552_amd import _lib
+    from paper_2112_07552_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    N = args.n5
+    log(f"headline: generating 2 x {N * N} records (N = {N})")
+    A, B = wl.mm_query(N, N, N, seed=4, values="mixture", dtype=torch.float32, device=dev)
+    W = wl.draw_values("uniform", N * N, 1004, 0, device=dev).reshape(N, N)
+    torch.cuda.synchronize()
+    out = {"workload": f"MM query, dense {N}x{N} tables ({N * N} records each, random order, "
+                       f"unique cells), FP32 values N(0,1) with 5% x1e3 outliers, seed 4; "
+                       f"dC = U[-1,1) seed 1004; step = forward + adjoint with "
+                       f"checkpointing (X, Y re-encoded)",
+           "N": N, "records_per_table": N * N}
+    ref = None
+    if not args.no_check:
+        log(f"headline: oracle on a {args.block} x {args.block} block")
+        ref = block_reference(A, B, W, N, args.block, seed=4)
+        log(f"headline: oracle block took {ref['oracle_s']:.1f} s on {ref['threads']} threads")
+    op = Operator(A, B, W, N, N, N, stream)
+    # residue form
+    ws_bytes = op.use("crt_i8")
+    log(f"headline: residue form, workspace {ws_bytes / 2**30:.1f} GiB")
+    ms_step, tr = timed_with_trace(hip, op.step, args.steps, args.warmup, stream)
+    info = op.status()
+    log(f"headline: residue form step {ms_step:.1f} ms, plan of the last product {info}")
+    crt = {"ms_fwd_adjoint_checkpointed": ms_step,
+           "fwd_adjoint_elements_per_s": N * N / (ms_step * 1e-3),
+           "tol": TOL, "plan_last_product": info}
+    gemm = launch_stats(tr.launches(_lib.TCU_KERNEL_GEMM_CRT), 1e12, "tops")
+    crt["kernels"] = {
+        "gemm_crt": gemm,
+        "certify": launch_stats(tr.launches(_lib.TCU_KERNEL_CERTIFY), 1e12, "tops"),
+        "encode": launch_stats(tr.launches(_lib.TCU_KERNEL_ENCODE), 1e9, "gbs"),
+        "gather": launch_stats(tr.launches(_lib.TCU_KERNEL_GATHER), 1e9, "gbs")}
+    tr.close()
+    ms_fwd = time_loop(op.fwd, max(2, args.steps // 2), 1, stream)
+    crt["ms_fwd"] = ms_fwd
+    crt["fwd_elements_per_s"] = N * N / (ms_fwd * 1e-3)
+    if ref is not None:
+        op.step()
+        op.status()
+        crt["errors_block"] = block_errors(ref, op.C, op.dA, op.dB)
+        log(f"headline: residue form errors {crt['errors_block']}")
+    out["crt_i8"] = crt
+    # FP64 comparator
+    op.use("fp64")
+    ms64 = time_loop(op.step, args.fp64_steps, 1, stream)
+    op.status()
+    f64 = {"ms_fwd_adjoint_checkpointed": ms64,
+           "fwd_adjoint_elements_per_s": N * N / (ms64 * 1e-3),
+           "tflops_fwd_adjoint": 6.0 * N ** 3 / (ms64 * 1e-3) / 1e12}
+    if ref is not None:
+        f64["errors_block"] = block_errors(ref, op.C, op.dA, op.dB)
+        log(f"headline: fp64 errors {f64['errors_block']}")
+    log(f"headline: fp64 step {ms64:.1f} ms")
+    out["fp64"] = f64
+    crt["speedup_fwd_adjoint_vs_fp64"] = ms64 / ms_step
+    if ref is not None:
+        crt["equal_accuracy"] = crt["errors_block"]["max"] <= max(TOL, f64["errors_block"]["max"])
+        R = ref["R"]
+        out["cpu_baseline"] = {
+            "value": R * R / ref["oracle_s"], "unit": "elements/s", "cores": ref["threads"],
+            "kind": "oracle",
+            "sample": f"the FP64 oracle on a {R} x {R} block of C of this workload plus the "
+                      f"value gradients of the {len(ref['ia'])} A records in {R} groups x {R} "
+                      f"keys and of the {len(ref['ib'])} B records in {R} keys x {R} groups: "
+                      f"3 R^2 N = {3 * R * R * N:.3g} multiply-adds, the fraction R^2/N^2 of "
+                      f"one forward + adjoint step, {ref['oracle_s']:.1f} s; elements/s = "
+                      f"records per table / extrapolated step time"}
+    op.release()
+    del op, A, B, W
+    torch.cuda.empty_cache()
+    out["gemm_crt"] = gemm
+    return out
+
+
+def leg_2pow24_fp64(args, stream, hip):
+    """2^24 records per table, U[-1,1) FP64 values (seed 2): the FP64 form's
+    forward + adjoint with saved encodings and with checkpointing, the
+    forward alone, the FP64 GEMM launches inside the timed steps, errors on
+    an oracle sample, and the library FP64 GEMM (rocBLAS through
+    torch.matmul) on the same shape as the ceiling."""
+    import numpy as np
+    import torch
+    from oracle import sample
+    from paper_2112_07552_amd import _lib
+    from paper_2112_07552_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    N = 4096
+    A, B = wl.mm_query(N, N, N, seed=2, device=dev)
+    W = wl.draw_values("uniform", N * N, 1002, 0, device=dev).reshape(N, N)
+    op = Operator(A, B, W, N, N, N, stream)
+    op.use("fp64")
+    out = {"workload": f"MM query, dense {N}x{N} tables ({N * N} records each), U[-1,1) FP64, "
+                       f"seed 2; dC = U[-1,1) seed 1002"}
+    ms_step, tr = timed_with_trace(hip, lambda: op.step(saved=True), args.steps, args.warmup,
+                                   stream)
+    out["ms_fwd_adjoint_saved"] = ms_step
+    out["fwd_adjoint_elements_per_s"] = N * N / (ms_step * 1e-3)
+    out["tflops_fwd_adjoint"] = 6.0 * N ** 3 / (ms_step * 1e-3) / 1e12
+    launches = tr.launches(_lib.TCU_KERNEL_GEMM_F64)
+    nn = [x for x in launches if x[2:5] == (N, N, N)]
+    out["kernels"] = {"gemm_f64_all": launch_stats(launches, 1e12, "tflops"),
+                      "encode": launch_stats(tr.launches(_lib.TCU_KERNEL_ENCODE), 1e9, "gbs"),
+                      "gather": launch_stats(tr.launches(_lib.TCU_KERNEL_GATHER), 1e9, "gbs")}
+    tr.close()
+    ms_ck, tr2 = timed_with_trace(hip, lambda: op.step(saved=False), args.steps, args.warmup,
+                                  stream)
+    tr2.close()
+    out["ms_fwd_adjoint_checkpointed"] = ms_ck
+    out["checkpointed_elements_per_s"] = N * N / (ms_ck * 1e-3)
+    ms_fwd, trf = timed_with_trace(hip, op.fwd, args.steps, args.warmup, stream)
+    out["ms_fwd"] = ms_fwd
+    out["fwd_elements_per_s"] = N * N / (ms_fwd * 1e-3)
+    out["tflops_fwd"] = 2.0 * N ** 3 / (ms_fwd * 1e-3) / 1e12
+    fwd_nn = trf.launches(_lib.TCU_KERNEL_GEMM_F64)
+    out["kernels"]["gemm_f64_nn_forward"] = launch_stats(fwd_nn, 1e12, "tflops")
+    trf.close()
+    op.status()
+    if not args.no_check:
+        op.step(saved=True)
+        ref = sample.reference(*_orc_rels(A, B), N, N, N, W.cpu().numpy(), rows=64, cells=2048,
+                               records=1024, seed=2)
+        out["errors_sample"] = sample.errors(ref, op.C.cpu().numpy(), op.dA.cpu().numpy(),
+                                             op.dB.cpu().numpy())
+        log(f"2^24 fp64: errors {out['errors_sample']}")
+    op.release()
+    # the library FP64 GEMM on the same shape: the ceiling, never on the path
+    X = torch.rand((N, N), dtype=torch.float64, device=dev)
+    Y = torch.rand((N, N), dtype=torch.float64, device=dev)
+    Z = torch.empty((N, N), dtype=torch.float64, device=dev)
+    ms_lib = time_loop(lambda: torch.matmul(X, Y, out=Z), args.steps, args.warmup, stream)
+    out["library_dgemm"] = {"call": "torch.matmul float64 (rocBLAS / hipBLASLt)",
+                            "ms": ms_lib,
+                            "tflops": 2.0 * N ** 3 / (ms_lib * 1e-3) / 1e12}
+    log(f"2^24 fp64: step {ms_step:.3f} ms, fwd {ms_fwd:.3f} ms, library DGEMM {ms_lib:.3f} ms")
+    del X, Y, Z, op, A, B, W
+    torch.cuda.empty_cache()
+    return out
+
+
+def _orc_rels(A, B):
+    import torch
+    from oracle import oracle as orc
+    f = lambda R: orc.Rel(R.group.cpu().numpy(), R.key.cpu().numpy(),
+                          R.val.cpu().to(torch.float64).numpy())
+    return f(A), f(B)
+
+
+def leg_2pow24_mixed(args, stream, hip):
+    """2^24 records per table, values log-uniform in magnitude on [1e-4, 1e4]
+    with random sign (seed 3): every form's forward and forward + adjoint
+    (saved encodings), its plan, the dominant kernel's launches, and errors
+    on the oracle's sample (512 whole rows of C, 4096 cells, Freivalds over
+    all of C, 4096 + 4096 gradient records)."""
+    import torch
+    from oracle import sample
+    from paper_2112_07552_amd import _lib
+    from paper_2112_07552_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    N = 4096
+    A, B = wl.mm_query(N, N, N, seed=3, values="loguniform", device=dev)
+    W = wl.draw_values("uniform", N * N, 1003, 0, device=dev).reshape(N, N)
+    out = {"workload": f"MM query, dense {N}x{N} tables ({N * N} records each), values "
+                       f"log-uniform on [1e-4, 1e4] with random sign, seed 3; dC = U[-1,1) "
+                       f"seed 1003; forward and forward + adjoint (saved encodings)"}
+    ref = None
+    if not args.no_check:
         t0 = time.perf_counter()
-        _, _, used = orc.join_agg(RA, RB, N, N, N, rows=rows)
-        orc.grad(RA, RB, N, N, N, Wn, "A", idx=ia)
-        orc.grad(RA, RB, N, N, N, Wn, "B", idx=ib)
-        return time.perf_counter() - t0, used
+        ref = sample.reference(*_orc_rels(A, B), N, N, N, W.cpu().numpy(), seed=3)
+        out["oracle_sample_s"] = time.perf_counter() - t0
+        log(f"2^24 mixed: oracle sample {out['oracle_sample_s']:.1f} s")
+    op = Operator(A, B, W, N, N, N, stream)
+    kernel = {"fp64": (_lib.TCU_KERNEL_GEMM_F64, 1e12, "tflops"),
+              "crt_i8": (_lib.TCU_KERNEL_GEMM_CRT, 1e12, "tops"),
+              "split_i8": (_lib.TCU_KERNEL_GEMM_SPLIT, 1e12, "tops"),
+              "split_bf16": (_lib.TCU_KERNEL_GEMM_SPLIT, 1e12, "tflops")}
+    for precision in ("fp64", "crt_i8", "split_i8", "split_bf16"):
+        op.use(precision)
+        ms_fwd, trf = timed_with_trace(hip, op.fwd, args.steps, args.warmup, stream)
+        trf.close()
+        ms_step, tr = timed_with_trace(hip, lambda: op.step(saved=True), args.steps,
+                                       args.warmup, stream)
+        info = op.status()
+        kid, unit, name = kernel[precision]
+        e = {"ms_fwd": ms_fwd, "ms_fwd_adjoint": ms_step,
+             "fwd_elements_per_s": N * N / (ms_fwd * 1e-3),
+             "fwd_adjoint_elements_per_s": N * N / (ms_step * 1e-3),
+             "effective_fp64_tflops_fwd": 2.0 * N ** 3 / (ms_fwd * 1e-3) / 1e12,
+             "plan_last_product": info,
+             "dominant_kernel": launch_stats(tr.launches(kid), unit, name)}
+        if precision != "fp64":
+            e["certify_kernel"] = launch_stats(tr.launches(_lib.TCU_KERNEL_CERTIFY), 1e12, "tops")
+        tr.close()
+        if ref is not None:
+            op.step(saved=True)
+            op.status()
+            e["errors_sample"] = sample.errors(ref, op.C.cpu().numpy(), op.dA.cpu().numpy(),
+                                               op.dB.cpu().numpy())
+        log(f"2^24 mixed {precision}: fwd {ms_fwd:.3f} ms, fwd+adj {ms_step:.3f} ms, "
+            f"plan {info}, errors {e.get('errors_sample')}")
+        out[precision] = e
+    base = out["fp64"]
+    for precision in ("crt_i8", "split_i8", "split_bf16"):
+        e = out[precision]
+        e["speedup_fwd_vs_fp64"] = base["ms_fwd"] / e["ms_fwd"]
+        e["speedup_fwd_adjoint_vs_fp64"] = base["ms_fwd_adjoint"] / e["ms_fwd_adjoint"]
+        if ref is not None:
+            e["equal_accuracy"] = e["errors_sample"]["max"] <= max(
+                TOL, base["errors_sample"]["max"])
+    op.release()
+    del op, A, B, W
+    torch.cuda.empty_cache()
+    return out
 
-    S = 4
-    t, used = run(S)
-    for _ in range(3):  # rescale until the sample takes about target_s
-        if t >= 0.6 * target_s or S >= N:
-            break
-        S = int(min(N, max(S + 1, S * target_s / max(t, 1e-3))))
-        t, used = run(S)
-    return {"value": S * N / t, "unit": "elements/s", "cores": int(used), "kind": "oracle",
-            "sample": f"forward rows g<{S} of C plus the value gradient of the {S * N} A "
-                      f"records in those groups and of {S * N} B records "
-                      f"({S}/{N} of one step), {t:.1f} s"}
 
+def leg_forward_small(args, stream, hip, N, seed):
+    """The FP64 forward at N^2 records per table (U[-1,1), the given seed):
+    time, rate, the encode kernel's algorithmic bandwidth, and the error
+    against the whole oracle C."""
+    import numpy as np
+    import torch
+    from oracle import oracle as orc
+    from paper_2112_07552_amd import _lib
+    from paper_2112_07552_amd import workloads as wl
 
-PEAK_I8_MFMA_TOPS = 5000.0     # MI355X dense int8 matrix peak
-PEAK_BF16_MFMA_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
+    dev = torch.device("cuda:0")
+    A, B = wl.mm_query(N, N, N, seed=seed, device=dev)
+    op = Operator(A, B, A.val[:1].reshape(1, 1), N, N, N, stream)
+    op.use("fp64", backward=False)
+    steps = max(args.steps, 50)
+    ms, tr = timed_with_trace(hip, op.fwd, steps, args.warmup, stream, capacity=4 * steps)
+    out = {"workload": f"MM query, dense {N}x{N} tables ({N * N} records each), U[-1,1) FP64, "
+                       f"seed {seed}; forward",
+           "ms_fwd": ms, "fwd_elements_per_s": N * N / (ms * 1e-3),
+           "encode": launch_stats(tr.launches(_lib.TCU_KERNEL_ENCODE), 1e9, "gbs"),
+           "gemm_f64": launch_stats(tr.launches(_lib.TCU_KERNEL_GEMM_F64), 1e12, "tflops")}
+    tr.close()
+    op.status()
+    if not args.no_check:
+        RA, RB = _orc_rels(A, B)
+        Co, _, _ = orc.join_agg(RA, RB, N, N, N)
+        So, _, _ = orc.join_agg(orc.Rel(RA.group, RA.key, np.abs(RA.val)),
+                                orc.Rel(RB.group, RB.key, np.abs(RB.val)), N, N, N)
+        out["err_cw_full"] = float(np.max(np.abs(op.C.cpu().numpy() - Co) / So))
+    log(f"forward N={N}: {ms:.4f} ms, err {out.get('err_cw_full')}")
+    op.release()
+    return out
 
 
 PEAK_PROBE_KINDS = {"fp64_tflops": 0, "i8_random_bytes_tops": 1, "i8_constant_bytes_tops": 2}
 
 
-def measured_peaks(stream, log, iters=2048, reps=5):
-    """Matrix-core rates measured on this chip by register-only loops (FP64
-    16x16x4; int8 32x32x32 on uniformly random bytes, the residue form's
-    operand statistics, and on near-constant bytes), in TFLOP/s or TOPS:
-    the ceilings the roofline fractions are also read against."""
+def measured_peaks(stream, iters=2048, reps=5):
+    """Matrix-core rates of register-only loops on this chip (FP64 16x16x4;
+    int8 32x32x32 on uniformly random bytes, the residue form's operand
+    statistics, and on near-constant bytes), TFLOP/s or TOPS: context for
+    the published peaks, which the roofline fractions use."""
     import torch
     from paper_2112_07552_amd import _lib
 
@@ -178,109 +602,6 @@ def measured_peaks(stream, log, iters=2048, reps=5):
         res[name] = L.tcu_mfma_peak_ops(kind, iters) / (ms * 1e-3) / 1e12
         log(f"measured peak {name}: {res[name]:.1f}")
     return res
-
-
-def bench_mixed(N, args, stream, log):
-    """Mixed-precision form on log-uniform values (|x| = 10^(-4+8u), random
-    sign, seed 3), N^2 records per table: the FP64 form and the split forms
-    at equal accuracy.  The slice count starts at the a-priori plan for
-    tol = 1e-12 and grows (refinement by further digit diagonals) until the
-    measured componentwise error against the oracle on sampled cells is at
-    most max(1e-12, the FP64 form's error)."""
-    import numpy as np
-    import torch
-    from oracle import oracle as orc
-    from paper_2112_07552_amd import _lib, ops
-    from paper_2112_07552_amd import workloads as wl
-
-    dev = torch.device("cuda:0")
-    A, B = wl.mm_query(N, N, N, seed=3, values="loguniform", device=dev)
-    W = wl.draw_values("uniform", N * N, 1003, 0, device=dev).reshape(N, N)
-    RA = orc.Rel(A.group.cpu().numpy(), A.key.cpu().numpy(), A.val.cpu().numpy())
-    RB = orc.Rel(B.group.cpu().numpy(), B.key.cpu().numpy(), B.val.cpu().numpy())
-
-    def run(precision, tol):
-        relA = ops.make_relation(A.group, A.key, A.val, unique=True)
-        relB = ops.make_relation(B.group, B.key, B.val, unique=True)
-        ws = ops.alloc_workspace(ops.workspace_bytes(relA, relB, N, N, N, precision,
-                                                     backward=True), dev)
-        Cm = torch.empty((N, N), dtype=torch.float64, device=dev)
-        dA = torch.empty(N * N, dtype=torch.float64, device=dev)
-        dB = torch.empty(N * N, dtype=torch.float64, device=dev)
-        L = _lib.load()
-        sp = C.c_void_p(stream.cuda_stream)
-        prec = ops.PRECISIONS[precision]
-
-        def fwd():
-            _lib.check(L.tcu_join_agg_fwd(C.byref(relA), C.byref(relB), N, N, N, prec, tol,
-                                          C.c_void_p(Cm.data_ptr()), None,
-                                          C.c_void_p(ws.data_ptr()), ws.numel(), sp), "fwd")
-
-        def step():
-            fwd()
-            _lib.check(L.tcu_join_agg_bwd(C.byref(relA), C.byref(relB), N, N, N, prec, tol,
-                                          C.c_void_p(W.data_ptr()), C.c_void_p(dA.data_ptr()),
-                                          C.c_void_p(dB.data_ptr()),
-                                          _lib.TCU_BWD_SAVED_ENCODINGS,
-                                          C.c_void_p(ws.data_ptr()), ws.numel(), sp), "bwd")
-
-        t_fwd = time_loop(fwd, args.steps, args.warmup, stream)
-        t_step = time_loop(step, args.steps, args.warmup, stream)
-        step()
-        st, info = ops.sync_status(ws)
-        if st != 0:
-            raise RuntimeError(f"mixed form status {st}")
-        errs = sampled_errors(orc, RA, RB, W, N, Cm, dA, dB, seed=3, ncells=512)
-        return t_fwd, t_step, errs["err_cw"], info["slices"], errs
-
-    out = {"workload": f"MM query, dense {N}x{N} tables ({N * N} records each), values "
-                       f"log-uniform on [1e-4, 1e4] with random sign, seed 3; forward and "
-                       f"forward + adjoint"}
-    f64_fwd, f64_step, f64_err, _, f64_errs = run("fp64", 0.0)
-    log(f"mixed workload fp64: fwd {f64_fwd:.3f} ms, fwd+adj {f64_step:.3f} ms, err {f64_err:.2e}")
-    out["fp64"] = {"ms_fwd": f64_fwd, "ms_fwd_adjoint": f64_step, "err_cw": f64_err,
-                   "errors": f64_errs}
-    target = max(1e-12, f64_err)
-    for precision in ("crt_i8", "split_i8", "split_bf16"):
-        tol = 1e-12
-        best = None
-        for _ in range(4):
-            try:
-                res = run(precision, tol)
-            except _lib.TcuError:
-                break
-            best = (tol,) + res
-            if res[2] <= target:
-                break
-            # refine: one more digit diagonal (slice forms), 7 more bits (CRT)
-            tol /= 128.0
-        if best is None:
-            continue
-        tol, t_fwd, t_step, err, S, errs = best
-        log(f"mixed workload {precision}: {'L' if precision == 'crt_i8' else 'S'}={S} "
-            f"fwd {t_fwd:.3f} ms, fwd+adj {t_step:.3f} ms, err {err:.2e}")
-        products = S if precision == "crt_i8" else S * (S + 1) // 2
-        entry = {
-            "tol": tol, "ms_fwd": t_fwd, "ms_fwd_adjoint": t_step, "err_cw": err,
-            "errors": errs,
-            "equal_accuracy": err <= target and max(errs["err_cw_dA"], errs["err_cw_dB"]) <= max(
-                1e-12, f64_errs["err_cw_dA"], f64_errs["err_cw_dB"]),
-            "speedup_fwd_vs_fp64": f64_fwd / t_fwd,
-            "speedup_fwd_adjoint_vs_fp64": f64_step / t_step,
-            "executed_ops_fwd": products * 2.0 * N ** 3,
-            # whole-forward rates: executed narrow-matrix-core operations, and
-            # the FP64-equivalent 2MNK per second
-            "executed_ops_per_s_fwd": products * 2.0 * N ** 3 / (t_fwd * 1e-3),
-            "effective_fp64_tflops_fwd": 2.0 * N ** 3 / (t_fwd * 1e-3) / 1e12,
-            "fwd_elements_per_s": N * N / (t_fwd * 1e-3),
-            "fwd_adjoint_elements_per_s": N * N / (t_step * 1e-3),
-        }
-        if precision == "crt_i8":
-            entry["moduli"], entry["bits"] = ops.crt_plan(N, tol)
-        else:
-            entry["slices"] = S
-        out[precision] = entry
-    return out
 
 
 def bench_queries(stream, log, steps, warmup):
@@ -511,325 +832,90 @@ def bench_ooc(stream, log, N=32768, dev_gb=24):
             "max_abs_diff_4x4_vs_device": sample}
 
 
-# Device bytes per N^2 at the large workload's peak: the two tables (int32
-# group and key, FP32 value: 24), W, C, dA and dB (32), and the residue form's
-# workspace with backward (X, Y, dX, dY: 32; operand residues, 15 planes per
-# side: 30; product residues, 15 planes: 15).
-LARGE_BYTES_PER_N2 = 24 + 32 + 32 + 30 + 15
-
-
-def large_n_max():
-    """The largest multiple of 256 whose footprint fits in 0.9 of the free
-    device memory."""
-    import math
-    import torch
-    free, _ = torch.cuda.mem_get_info()
-    return int(math.isqrt(int(0.9 * free) // LARGE_BYTES_PER_N2)) // 256 * 256
-
-
-def bench_large(stream, log, N=32768):
-    """The mixed forms at scale: N^2 records per table (default N = 32768,
-    2^30, the paper's largest MM query; N = 0 takes the largest size that
-    fits, large_n_max()), FP32 values N(0,1) with 5% x1e3 outliers (seed 4).
-    One forward and one forward + adjoint with checkpointing (the adjoint
-    re-encodes) in the two mixed int8 forms (digit slices, residues) at
-    tol = 1e-12 and in the FP64 form, each timed once after one untimed run;
-    errors on a 64 x 64 block of C against the oracle."""
-    import numpy as np
-    import torch
-    from oracle import oracle as orc
-    from paper_2112_07552_amd import _lib, ops
-    from paper_2112_07552_amd import workloads as wl
-
-    dev = torch.device("cuda:0")
-    n_max = large_n_max()
-    if N == 0:
-        N = n_max
-    log(f"large: N = {N} (largest that fits: {n_max}, at {LARGE_BYTES_PER_N2} bytes per N^2)")
-    log(f"large: generating 2 x {N * N} records")
-    A, B = wl.mm_query(N, N, N, seed=4, values="mixture", dtype=torch.float32, device=dev)
-    W = wl.draw_values("uniform", N * N, 1004, 0, device=dev).reshape(N, N)
-    relA = ops.make_relation(A.group, A.key, A.val, unique=True)
-    relB = ops.make_relation(B.group, B.key, B.val, unique=True)
-    L = _lib.load()
-    sp = C.c_void_p(stream.cuda_stream)
-    Cm = torch.empty((N, N), dtype=torch.float64, device=dev)
-    dA = torch.empty(N * N, dtype=torch.float64, device=dev)
-    dB = torch.empty(N * N, dtype=torch.float64, device=dev)
-    out = {"workload": f"MM query, dense {N}x{N} tables ({N * N} records each), FP32 values "
-                       f"N(0,1) with 5% x1e3 outliers, seed 4; adjoint with checkpointing "
-                       f"(re-encoding)", "records_per_table": N * N, "N": N, "n_max": n_max,
-           "footprint_bytes": LARGE_BYTES_PER_N2 * N * N}
-    rng = np.random.default_rng(4)
-    rows = np.sort(rng.choice(N, 64, replace=False))
-    cols = np.sort(rng.choice(N, 64, replace=False))
-    ag, ak = A.group.cpu().numpy(), A.key.cpu().numpy()
-    av = A.val.cpu().numpy().astype(np.float64)
-    bk, bh = B.key.cpu().numpy(), B.group.cpu().numpy()
-    bw = B.val.cpu().numpy().astype(np.float64)
-    lut_a = np.full(N, -1); lut_a[rows] = np.arange(64)
-    lut_b = np.full(N, -1); lut_b[cols] = np.arange(64)
-    ga, hb = lut_a[ag], lut_b[bh]
-    ma, mb = ga >= 0, hb >= 0
-    Af = orc.Rel(ga[ma].astype(np.int32), ak[ma], av[ma])
-    Bf = orc.Rel(hb[mb].astype(np.int32), bk[mb], bw[mb])
-    Co, _, _ = orc.join_agg(Af, Bf, 64, N, 64)
-    So, _, _ = orc.join_agg(orc.Rel(Af.group, Af.key, np.abs(Af.val)),
-                            orc.Rel(Bf.group, Bf.key, np.abs(Bf.val)), 64, N, 64)
-    del ag, ak, av, bk, bh, bw, ga, hb
-    tr, tc = torch.as_tensor(rows, device=dev), torch.as_tensor(cols, device=dev)
-    for precision in ("fp64", "split_i8", "crt_i8"):
-        prec = ops.PRECISIONS[precision]
-        ws = ops.alloc_workspace(ops.workspace_bytes(relA, relB, N, N, N, precision,
-                                                     backward=True), dev)
-
-        def fwd():
-            _lib.check(L.tcu_join_agg_fwd(C.byref(relA), C.byref(relB), N, N, N, prec, 1e-12,
-                                          C.c_void_p(Cm.data_ptr()), None,
-                                          C.c_void_p(ws.data_ptr()), ws.numel(), sp), "fwd")
-
-        def step():
-            fwd()
-            _lib.check(L.tcu_join_agg_bwd(C.byref(relA), C.byref(relB), N, N, N, prec, 1e-12,
-                                          C.c_void_p(W.data_ptr()), C.c_void_p(dA.data_ptr()),
-                                          C.c_void_p(dB.data_ptr()), 0,
-                                          C.c_void_p(ws.data_ptr()), ws.numel(), sp), "bwd")
-
-        t_fwd = time_loop(fwd, 1, 1, stream)
-        t_step = time_loop(step, 1, 1, stream)
-        fwd()
-        st, info = ops.sync_status(ws)
-        if st != 0:
-            raise RuntimeError(f"large {precision}: status {st}")
-        blk = Cm[tr][:, tc].cpu().numpy()
-        err = float(np.max(np.abs(blk - Co) / So))
-        log(f"large {precision}: fwd {t_fwd:.1f} ms, fwd+adj {t_step:.1f} ms, err {err:.2e}")
-        out[precision] = {"ms_fwd": t_fwd, "ms_fwd_adjoint_checkpointed": t_step,
-                          "err_cw_block": err,
-                          "fwd_elements_per_s": N * N / (t_fwd * 1e-3),
-                          "fwd_adjoint_elements_per_s": N * N / (t_step * 1e-3)}
-        if precision == "crt_i8":
-            out[precision]["moduli"] = info["slices"]
-        elif precision != "fp64":
-            out[precision]["slices"] = info["slices"]
-        del ws
-        torch.cuda.empty_cache()
-    for precision in ("split_i8", "crt_i8"):
-        out[precision]["speedup_fwd_vs_fp64"] = out["fp64"]["ms_fwd"] / out[precision]["ms_fwd"]
-        out[precision]["speedup_fwd_adjoint_vs_fp64"] = (
-            out["fp64"]["ms_fwd_adjoint_checkpointed"] /
-            out[precision]["ms_fwd_adjoint_checkpointed"])
-    return out
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=4096, help="M = K = N; records per table = n^2")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--no-check", action="store_true", help="skip the oracle error check")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
-    ap.add_argument("--no-queries", action="store_true",
-                    help="skip the Q1/Q3/Q4 microbenchmark leg")
-    ap.add_argument("--large", action="store_true",
-                    help="also time the largest workload: 2^30 records per table, FP32 "
-                         "mixture values, mixed int8 form vs FP64 form, forward + adjoint "
-                         "with checkpointing")
-    ap.add_argument("--large-n", type=int, default=32768,
-                    help="edge of the --large workload (0: the largest that fits in memory)")
-    ap.add_argument("--ooc", action="store_true",
-                    help="also time the 32768^3 FP64 product over pinned host memory through "
-                         "a 24 GB device budget (blocked, pipelined) against the HBM-resident one")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run one plain 512 MiB device copy, the reference that scales "
-                         "profiler byte counters")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--legs", default="all",
+                    help="comma-separated: headline, fp64_2pow24, mixed_2pow24, small, peaks, "
+                         "queries, ooc (not in 'all'), or all")
+    ap.add_argument("--n5", type=int, default=32768,
+                    help="edge of the headline workload (records per table = n5^2)")
+    ap.add_argument("--block", type=int, default=256,
+                    help="edge of the headline's oracle block (its CPU baseline and errors)")
+    ap.add_argument("--fp64-steps", type=int, default=2,
+                    help="timed FP64 comparator steps at the headline workload")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip every oracle check (and the CPU baseline)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "the benchmark measures the single-GPU path only (multi-GPU sharding is not implemented); --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only (the path is built and "
+                                   "measured on a single MI355X); --gpus must be 1"}))
         sys.exit(2)
+    legs = set(args.legs.split(","))
+    if "all" in legs:
+        legs |= {"headline", "fp64_2pow24", "mixed_2pow24", "small", "peaks", "queries"}
 
-    import numpy as np
     import torch
-
-    from paper_2112_07552_amd import _lib, ops
-    from paper_2112_07552_amd import workloads as wl
+    from paper_2112_07552_amd import _lib
 
     _lib.load()  # fails loudly without the HIP library
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    N = args.n
-    n_rec = N * N
-    log(f"generating inputs N={N} ({n_rec} records per table)")
-    A, B = wl.mm_query(N, N, N, seed=2, device=dev)
-    W = wl.draw_values("uniform", N * N, 1002, 0, device=dev).reshape(N, N)
+    hip = Hip()
+    res = {}
+    if "headline" in legs:
+        res["headline"] = leg_headline(args, stream, hip)
+    if "fp64_2pow24" in legs:
+        res["fp64_2pow24"] = leg_2pow24_fp64(args, stream, hip)
+    if "mixed_2pow24" in legs:
+        res["mixed_2pow24"] = leg_2pow24_mixed(args, stream, hip)
+    if "small" in legs:
+        res["forward_2pow14"] = leg_forward_small(args, stream, hip, 128, 0)
+        res["forward_2pow20"] = leg_forward_small(args, stream, hip, 1024, 1)
+    if "peaks" in legs:
+        res["measured_peaks"] = measured_peaks(stream)
+    if "queries" in legs:
+        q = bench_queries(stream, log, args.steps, args.warmup)
+        q["block_sparse"] = bench_bsr(stream, log, args.steps, args.warmup)
+        q["multiway"] = bench_multiway(stream, log, args.steps, args.warmup)
+        res["queries"] = q
+    if "ooc" in legs:
+        res["out_of_core"] = bench_ooc(stream, log)
 
-    relA = ops.make_relation(A.group, A.key, A.val, unique=True)
-    relB = ops.make_relation(B.group, B.key, B.val, unique=True)
-    ws = ops.alloc_workspace(ops.workspace_bytes(relA, relB, N, N, N, backward=True), dev)
-    Cm = torch.empty((N, N), dtype=torch.float64, device=dev)
-    dA = torch.empty(n_rec, dtype=torch.float64, device=dev)
-    dB = torch.empty(n_rec, dtype=torch.float64, device=dev)
-    L = _lib.load()
-    sp = C.c_void_p(stream.cuda_stream)
-    wsp, wsn = C.c_void_p(ws.data_ptr()), ws.numel()
-
-    def fwd():
-        _lib.check(L.tcu_join_agg_fwd(C.byref(relA), C.byref(relB), N, N, N, 0, 0.0,
-                                      C.c_void_p(Cm.data_ptr()), None, wsp, wsn, sp), "fwd")
-
-    def bwd(flags):
-        _lib.check(L.tcu_join_agg_bwd(C.byref(relA), C.byref(relB), N, N, N, 0, 0.0,
-                                      C.c_void_p(W.data_ptr()), C.c_void_p(dA.data_ptr()),
-                                      C.c_void_p(dB.data_ptr()), flags, wsp, wsn, sp), "bwd")
-
-    def step():
-        fwd()
-        bwd(_lib.TCU_BWD_SAVED_ENCODINGS)
-
-    def step_checkpointed():
-        fwd()
-        bwd(0)
-
-    if args.copy_calibration:
-        src = torch.empty(64 << 20, dtype=torch.float64, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)  # reads 512 MiB, writes 512 MiB
-        torch.cuda.synchronize()
-        del src, dst
-
-    log("timing fwd+adjoint")
-    ms_step = time_loop(step, args.steps, args.warmup, stream)
-    log(f"fwd+adjoint {ms_step:.3f} ms")
-    ms_fwd = time_loop(fwd, args.steps, args.warmup, stream)
-    log(f"fwd {ms_fwd:.3f} ms")
-    ms_ckpt = time_loop(step_checkpointed, args.steps, args.warmup, stream)
-    log(f"fwd+adjoint with re-encoding (checkpointed) {ms_ckpt:.3f} ms")
-    st, info = ops.sync_status(ws)
-    if st != 0:
-        raise RuntimeError(f"device status {st}: {info}")
-
-    # dominant kernel: the FP64 matrix-core product, timed alone on the same
-    # stream at the three shapes the step launches (NN forward, NT and TN adjoint)
-    X = torch.empty((N, N), dtype=torch.float64, device=dev)
-    Y = torch.empty((N, N), dtype=torch.float64, device=dev)
-    ops.encode(A.group, A.key, A.val, N, N, False, out=X, unique=True)
-    ops.encode(B.group, B.key, B.val, N, N, True, out=Y, unique=True)
-    G = torch.empty((N, N), dtype=torch.float64, device=dev)
-    gemm_ms = {}
-    for name, (ta, tb, a, b) in {"nn": (0, 0, X, Y), "nt": (0, 1, W, Y),
-                                 "tn": (1, 0, X, W)}.items():
-        def g(ta=ta, tb=tb, a=a, b=b):
-            _lib.check(L.tcu_gemm_f64(ta, tb, N, N, N, C.c_void_p(a.data_ptr()), N,
-                                      C.c_void_p(b.data_ptr()), N, C.c_void_p(G.data_ptr()), N,
-                                      sp), "gemm")
-        gemm_ms[name] = time_loop(g, args.steps, args.warmup, stream)
-        log(f"gemm_f64 {name}: {gemm_ms[name]:.3f} ms")
-    flops = 2.0 * N * N * N
-    achieved = flops / (gemm_ms["nn"] * 1e-3) / 1e12
-
-    peaks = measured_peaks(stream, log)
-
-    result_err = None
-    errors = None
-    if not args.no_check:
-        from oracle import oracle as orc
-        step()
-        torch.cuda.synchronize()
-        RA = orc.Rel(A.group.cpu().numpy(), A.key.cpu().numpy(), A.val.cpu().numpy())
-        RB = orc.Rel(B.group.cpu().numpy(), B.key.cpu().numpy(), B.val.cpu().numpy())
-        errors = sampled_errors(orc, RA, RB, W, N, Cm, dA, dB, seed=0, ncells=1024)
-        result_err = errors["err_cw"]
-        log(f"errors of one step against the oracle: {errors}")
-
-    mixed = None
-    if not args.no_mixed:
-        mixed = bench_mixed(N, args, stream, log)
-    queries = None
-    if not args.no_queries:
-        queries = bench_queries(stream, log, args.steps, args.warmup)
-        queries["block_sparse"] = bench_bsr(stream, log, args.steps, args.warmup)
-        queries["multiway"] = bench_multiway(stream, log, args.steps, args.warmup)
-    large = None
-    if args.large:
-        large = bench_large(stream, log, args.large_n)
-    ooc = None
-    if args.ooc:
-        ooc = bench_ooc(stream, log)
-
-    # context only: the host -> device copy of both tables' columns from
-    # pinned memory (the step starts with the records resident in HBM)
-    h2d = None
-    try:
-        cols = [A.group, A.key, A.val, B.group, B.key, B.val]
-        host = [torch.empty(c.shape, dtype=c.dtype, pin_memory=True) for c in cols]
-        dst = [torch.empty_like(c) for c in cols]
-        for h, c in zip(host, cols):
-            h.copy_(c)
-        torch.cuda.synchronize()
-
-        def copy_in():
-            for d, h in zip(dst, host):
-                d.copy_(h, non_blocking=True)
-        ms_h2d = time_loop(copy_in, 3, 1, stream)
-        nbytes = sum(c.numel() * c.element_size() for c in cols)
-        h2d = {"ms": ms_h2d, "bytes": nbytes, "GB_per_s": nbytes / (ms_h2d * 1e-3) / 1e9,
-               "note": "both tables' columns host -> device from pinned memory; not part of "
-                       "the timed step, whose inputs are resident in HBM"}
-        log(f"h2d context: {nbytes / 1e6:.0f} MB in {ms_h2d:.2f} ms")
-        del host, dst
-    except RuntimeError as e:  # pinned allocation refused: report nothing
-        log(f"h2d context skipped: {e}")
-
-    cpu = None
-    if not args.no_cpu:
-        log("timing the CPU oracle on a sample")
-        cpu = cpu_baseline(A, B, N, W)
-        log(f"cpu oracle {cpu['value']:.3e} elements/s on {cpu['cores']} threads")
-
-    out = {
-        "metric": "elements/sec fwd & fwd+adjoint at 1 GPU; % HBM/MFMA roofline; err vs FP64",
-        "value": n_rec / (ms_step * 1e-3),
-        "unit": "elements/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"MM query, dense {N}x{N} tables ({n_rec} records each, random "
-                               f"order, unique cells), U[-1,1) FP64, seed 2; step = forward + "
-                               f"adjoint (FP64, saved encodings)",
-                   "M": N, "K": N, "N": N, "records_per_table": n_rec, "precision": "fp64"},
-        "fwd_elements_per_s": n_rec / (ms_fwd * 1e-3),
-        "ms_fwd": ms_fwd,
-        # whole-path FP64 rates: 2MNK per forward, 6MNK per forward + adjoint
-        "tflops_fwd": 2.0 * N ** 3 / (ms_fwd * 1e-3) / 1e12,
-        "tflops_fwd_adjoint": 6.0 * N ** 3 / (ms_step * 1e-3) / 1e12,
-        "checkpointed_elements_per_s": n_rec / (ms_ckpt * 1e-3),
-        "ms_checkpointed": ms_ckpt,
-        "err_cw_vs_oracle": result_err,
-        "errors_vs_oracle": errors,
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_F64_MFMA_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_F64_MFMA_TFLOPS,
-                     "traffic": counter_traffic(),
-                     "measured_peak": peaks["fp64_tflops"],
-                     "frac_of_measured": achieved / peaks["fp64_tflops"],
-                     "kernel": "gemm_f64_kernel<true,false,true> (NN, forward)",
-                     "kernel_ms": gemm_ms},
-        "cpu_baseline": cpu,
-        "measured_peaks": peaks,
-        "mixed": mixed,
-        "queries": queries,
-        "large": large,
-        "out_of_core": ooc,
-        "h2d_context": h2d,
-    }
+    out = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "data": "synthetic"}
+    if "headline" in res:
+        h = res["headline"]
+        crt = h["crt_i8"]
+        g = h["gemm_crt"]
+        N = h["N"]
+        out.update({
+            "value": crt["fwd_adjoint_elements_per_s"], "unit": "elements/s",
+            "ms_per_step": crt["ms_fwd_adjoint_checkpointed"],
+            "dtype": "i8",
+            "config": {"workload": h["workload"], "records_per_table": h["records_per_table"],
+                       "M": N, "K": N, "N": N, "precision": "crt_i8 (int8 residues, int32 "
+                       "sums, FP64 reconstruction)", "tol": TOL,
+                       "guarantee": "|C - C*| <= tol (|X||Y|) per cell, certified plan"},
+            "fwd_elements_per_s": crt["fwd_elements_per_s"],
+            "speedup_vs_fp64_form": crt["speedup_fwd_adjoint_vs_fp64"],
+            "err_vs_oracle": {k: v.get("errors_block") for k, v in
+                              (("crt_i8", crt), ("fp64", h["fp64"]))},
+            "roofline": None if g is None else {
+                "bound": "mfma", "achieved": g["achieved_tops"], "peak": PEAK_I8_MFMA_TOPS,
+                "unit": "TOPS", "frac": g["achieved_tops"] / PEAK_I8_MFMA_TOPS,
+                "traffic": counter_traffic("counters_gemm_crt_mm_query_32768.md", "gemm_crt",
+                                           "crt.hip"),
+                "kernel": "gemm_crt_kernel<Cfg<256, 8, 4, 2>, false, 0> (int8 residue "
+                          "products, all of the step's launches)",
+                "launches": g["launches"], "avg_ms": g["avg_ms"],
+                "ops_per_launch": g["avg_ops_per_launch"]},
+            "cpu_baseline": h.get("cpu_baseline"),
+        })
+    out["legs"] = res
     print(json.dumps(out), flush=True)
 
 

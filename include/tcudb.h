@@ -52,7 +52,8 @@ typedef enum {
     TCU_ERR_WORKSPACE = -3,  /* workspace NULL, misaligned or too small        */
     TCU_ERR_INFEASIBLE = -4, /* mixed form: tolerance not reachable            */
     TCU_ERR_NONFINITE = -5,  /* mixed form: NaN or infinity in an encoding     */
-    TCU_ERR_HIP = -6         /* a HIP runtime call failed                      */
+    TCU_ERR_HIP = -6,        /* a HIP runtime call failed                      */
+    TCU_ERR_COUNT_RANGE = -7 /* device: a pair count exceeded INT32_MAX        */
 } tcu_status;
 
 typedef enum { TCU_F64 = 0, TCU_F32 = 1 } tcu_dtype;
@@ -112,11 +113,24 @@ typedef struct {
 
 /* Status block read back by tcu_sync_status (host copy). */
 typedef struct {
-    uint32_t flags;        /* bit 0: out-of-range record, bit 1: non-finite   */
-    uint32_t slices;       /* mixed form: slices used by the last call        */
+    uint32_t flags;        /* TCU_FLAG_* bits                                 */
+    uint32_t slices;       /* mixed forms: digit slices (or moduli) of the
+                              last product; 0 when it ran in FP64            */
     uint64_t skipped_a;    /* records of A skipped by the last call           */
     uint64_t skipped_b;    /* records of B skipped by the last call           */
+    uint32_t bits;         /* residue form: truncation width of the last
+                              product                                        */
+    uint32_t need;         /* mixed forms: the last certificate's largest
+                              per-cell need (bits or digits; 255: a cell it
+                              could not bound)                               */
 } tcu_status_info;
+
+#define TCU_FLAG_KEY_RANGE 1u /* a record had an out-of-range key or group    */
+#define TCU_FLAG_NONFINITE 2u /* a mixed form met NaN or infinity             */
+#define TCU_FLAG_FALLBACK 4u  /* a mixed-form product had no certified plan
+                                 and ran in FP64 instead                      */
+#define TCU_FLAG_COUNT_RANGE 8u /* a pair count exceeded INT32_MAX (stored as
+                                   INT32_MAX)                                 */
 
 /* Bytes of device workspace the calls below need for these shapes (Section
  * 3.3 encodings X and Y, plus the status block; with TCU_WS_BACKWARD one more
@@ -137,28 +151,37 @@ size_t tcu_workspace_bytes(const tcu_relation *A, const tcu_relation *B, int32_t
 tcu_status tcu_encode(const tcu_relation *R, int transpose, int32_t rows, int32_t cols,
                       double *out, void *ws, size_t ws_bytes, hipStream_t stream);
 
-/* Step a0 host part, the mixed form's precision plan (the feasibility test of
- * Section 4.2.1 retargeted): the smallest slice count S in [1, 8] whose
- * a-priori bound meets `tol` for a contraction of length k,
- *   4.04 (S+1) 2^(-7S) + 4.04 * 2^-53 * n_add(S, k) <= tol,
- * the bound on |error| / (k * max|row of A| * max|column of B|) from the
- * dropped digit pairs and the FP64 additions.  Returns S, or
- * TCU_ERR_INFEASIBLE when even S = 8 misses `tol`, or TCU_ERR_ARG.  Host
- * only: touches no device. */
-int tcu_split_slices(tcu_precision p, int32_t k, double tol);
-
-/* The plan of the CRT form (TCU_PREC_CRT_I8) for a contraction of length k:
- * the smallest integer width `bits` with
- *   2^(2 - bits) + 2^(2 - 2 bits) + 2^-51 <= tol
- * (the bound on |error| / (k * max|row of A| * max|column of B|) from the
- * truncation of both operands to `bits`-bit integers per line, plus the
- * rounding of the reconstruction), and the smallest number L of moduli
- * (from 256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 217, 211, 199,
- * 197) whose product exceeds 4 k 2^(2 bits).  Returns L and writes *bits, or
- * returns TCU_ERR_INFEASIBLE (tol below what 53-bit inputs or 15 moduli
- * reach, or k >= 131072, beyond exact int32 sums), or TCU_ERR_ARG.
- * tcu_split_slices(TCU_PREC_CRT_I8, k, tol) returns the same L.  Host only. */
-int tcu_crt_plan(int32_t k, double tol, int32_t *bits);
+/* Step a0 host part, the mixed forms' precision plan (the feasibility test
+ * of Section 4.2.1 retargeted: a cheap look at the operands' magnitudes
+ * decides the narrow type's width, or refuses).  Every mixed-form product
+ * C = X Y (contraction length k) is planned from a certificate computed on
+ * the device from the two operands themselves:
+ *   per line (row g of X, column h of Y): the exponent e with 2^(e-1) <=
+ *     max |z| < 2^e, the normalised sum s = sum |z| 2^-e (rounded up), and
+ *     the magnitude codes q = floor(|z| 2^(7-e)) in [0, 127];
+ *   per cell: T = (Q_X Q_Y)[g,h] by one int8 GEMM, so that
+ *     D_lo = 2^(e_g + f_h - 14) T <= (|X||Y|)[g,h];
+ *   the truncation of both operands to b-bit integers per line (residue
+ *     form) moves C[g,h] by at most 2^(e_g + f_h - b) (s_g + s_h), and S
+ *     digits of 7 bits with the pairs past the first S anti-diagonals
+ *     dropped (digit forms) by at most 2^(e_g + f_h - 7S) (s_g + s_h +
+ *     (S - 1) k);
+ *   the cell's need is the smallest b (or S) whose bound plus the FP64
+ *     rounding of the combination stays within tol * D_lo (0 when row g or
+ *     column h is all zero: every term of the cell is then 0).
+ * need: the largest per-cell need over C (255 for a cell with T = 0 but a
+ * nonzero bound: not certifiable); u: the smaller of the two operands'
+ * largest normalised line sums (then |sum_k x'y'| < 2^(2b) min(u, k)).
+ * Returns the digit count S = max(need, 1) (TCU_PREC_SPLIT_*, at most 8), or
+ * for TCU_PREC_CRT_I8 the modulus count L, the smallest with
+ * prod m_i > 4 * 2^(2b) min(max(u, 1), k), b = max(need, 1) <= 53 written to
+ * *bits (moduli 256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 217,
+ * 211, 199, 197); TCU_ERR_INFEASIBLE when no plan exists (then the product
+ * runs in FP64 and TCU_FLAG_FALLBACK is set), tol < 2^-50, or the residue
+ * form with k > 131071 (int32 sums); TCU_ERR_ARG for a bad precision or
+ * k < 1.  tol <= 0 means 1e-12.  Host only: touches no device. */
+int tcu_mixed_plan(tcu_precision p, int32_t k, double tol, uint32_t need, double u,
+                   int32_t *bits);
 
 /* Step a0 device part alone: the per-line scale exponents and S digit slices
  * of a dense FP64 matrix Z (rows x cols, leading dimension ld).
@@ -188,17 +211,43 @@ tcu_status tcu_gemm_f64(int trans_a, int trans_b, int32_t m, int32_t n, int32_t 
                         const double *A, int64_t lda, const double *B, int64_t ldb,
                         double *C, int64_t ldc, hipStream_t stream);
 
+/* tcu_gemm_f64 for outputs too small to fill the chip, such as the literal
+ * Lemma-Q3 product 1^T C of Section 3.3 (one output row, a long
+ * contraction): the contraction is cut into chunks that run as separate
+ * workgroups, their partial products land in ws, and a second kernel adds
+ * them in chunk order, the same on every run (results are reproducible bit
+ * for bit).  When the output has enough tiles (or k < 1024) this is
+ * tcu_gemm_f64 and ws is not touched.
+ * ws: device, 256-byte aligned, at least tcu_gemm_f64_workspace_bytes(m, n,
+ * k) bytes (0: no workspace needed; ws may then be NULL).
+ * Errors as tcu_gemm_f64, plus TCU_ERR_WORKSPACE. */
+size_t tcu_gemm_f64_workspace_bytes(int32_t m, int32_t n, int32_t k);
+tcu_status tcu_gemm_f64_ws(int trans_a, int trans_b, int32_t m, int32_t n, int32_t k,
+                           const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
+                           int64_t ldc, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Steps a1-a3, the operator (Sections 2.3, 3.3): C (M x N FP64 row-major,
  * rows g ascending, columns h ascending) = the join-aggregate above.
  * count (M x N int32, or NULL): exact number of joined pairs per (g,h); SQL's
  * result holds exactly the cells with count > 0 (a dense C shows 0 elsewhere).
+ * With TCU_REL_UNIQUE_CELLS on both relations (every multiplicity 0 or 1)
+ * the counts come from one int8 product of the 0/1 encodings with exact
+ * int32 sums; otherwise from the FP64 product of the multiplicity encodings
+ * (exact: every partial sum is a non-negative integer no larger than the
+ * count).  A count above INT32_MAX is stored as INT32_MAX and flagged
+ * (TCU_FLAG_COUNT_RANGE; tcu_sync_status returns TCU_ERR_COUNT_RANGE).  The
+ * workspace must be sized with TCU_WS_COUNT.
  * The mixed forms (TCU_PREC_SPLIT_*, TCU_PREC_CRT_I8) guarantee, cell by
  * cell,
- *   |C - exact| <= tol * K * max_k |X[g,k]| * max_k |Y[k,h]|
- * with the slice count from tcu_split_slices or the plan of tcu_crt_plan
- * (tol <= 0 means 1e-12), and return TCU_ERR_INFEASIBLE (launching
- * nothing) when no plan can; the
- * count output is exact in every form.  No call synchronises the host.
+ *   |C - exact| <= tol * (|X||Y|)[g,h]
+ * (tol <= 0 means 1e-12): the plan is certified for every cell of the
+ * product from the operands (tcu_mixed_plan), and a product without a
+ * certified plan runs in FP64 instead (TCU_FLAG_FALLBACK), whose error is
+ * at most about K 2^-53 (|X||Y|)[g,h].  Planning reads the certificate back
+ * to the host, so a mixed-form call SYNCHRONISES the stream once per product;
+ * the FP64 form never does.  TCU_ERR_INFEASIBLE (launching nothing) for
+ * tol < 2^-50 or, in the residue form, K > 131071.  The count output is
+ * exact in every form.
  * Device-side conditions (out-of-range records, NaN/Inf in the mixed forms)
  * are reported by tcu_sync_status. */
 tcu_status tcu_join_agg_fwd(const tcu_relation *A, const tcu_relation *B, int32_t M, int32_t K,
@@ -234,8 +283,11 @@ tcu_status tcu_join_agg_fwd_noalloc(const tcu_relation *A, const tcu_relation *B
  * checkpointing: nothing of the forward is kept); with
  * TCU_BWD_SAVED_ENCODINGS the forward's X and Y in ws are used.  Either
  * output may be NULL.  Skipped records get 0.  Gradients are FP64 whatever
- * the value dtype.  In the mixed forms both products carry the forward's
- * guarantee with their own contraction length (N for dX, M for dY).  Needs a
+ * the value dtype.  In the mixed forms each product (dX = dC Y^T over N,
+ * dY = X^T dC over M) is certified and planned on its own operands as in
+ * the forward, so |dX - exact| <= tol (|dC||Y^T|)[g,k] and |dY - exact| <=
+ * tol (|X^T||dC|)[k,h] cell by cell, and the call synchronises once per
+ * product.  Needs a
  * workspace sized with TCU_WS_BACKWARD.  With both outputs, the gather of
  * dA_val (and, when re-encoding, the encoding of X) runs on the device's
  * internal stream beside the products on the caller's stream; in the FP64
@@ -247,6 +299,52 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
                             int32_t N, tcu_precision p, double tol, const double *dC,
                             double *dA_val, double *dB_val, int flags, void *ws,
                             size_t ws_bytes, hipStream_t stream);
+
+/* ---- Measurement (instrumentation, not a step of the method) -------------
+ *
+ * Launch records of the matrix-core product kernels, for timing the
+ * dominant kernel inside a timed region with HIP events.  While recording
+ * is on for the calling host thread, every launch of one of these kernels
+ * that a call made on this thread issues is bracketed by hipEventRecord of
+ * the next record's `begin` and `end` events, on the stream the kernel runs
+ * on (the caller's or the library's internal one), and the record receives
+ * the kernel, its shape and its algorithmic operation count:
+ *   TCU_KERNEL_GEMM_F64    FP64 product, ops = 2 m n k FLOP
+ *   TCU_KERNEL_GEMM_CRT    residue products, planes = L moduli,
+ *                          ops = L * 2 m n k int8 operations
+ *   TCU_KERNEL_CERTIFY     the certificate's int8 product, ops = 2 m n k
+ *   TCU_KERNEL_GEMM_SPLIT  digit products, planes = S digits,
+ *                          ops = S (S + 1) / 2 * 2 m n k
+ *   TCU_KERNEL_ENCODE      one relation's scatter into an m x n matrix,
+ *                          ops = algorithmic bytes (group, key and value
+ *                          read, one 8-byte cell written per record)
+ *   TCU_KERNEL_GATHER      an adjoint's gather (or a row range of it),
+ *                          ops = 24 bytes per record of the relation
+ *   TCU_KERNEL_COUNT       the pair counts' int8 product, ops = 2 m n k
+ * The caller creates the events (timing enabled) and, once the work has
+ * run, reads each launch's duration with hipEventElapsedTime.
+ * records: the caller's host array of `capacity` records; count: a host
+ * int32 that is set to 0 now and counts every launch seen (launches beyond
+ * `capacity` are counted, not recorded).  count == NULL stops recording.
+ * The arrays must stay valid while recording is on.  TCU_ERR_ARG for a
+ * negative capacity or a NULL array with a positive one. */
+typedef enum {
+    TCU_KERNEL_GEMM_F64 = 1,
+    TCU_KERNEL_GEMM_CRT = 2,
+    TCU_KERNEL_CERTIFY = 3,
+    TCU_KERNEL_GEMM_SPLIT = 4,
+    TCU_KERNEL_ENCODE = 5,
+    TCU_KERNEL_GATHER = 6,
+    TCU_KERNEL_COUNT = 7
+} tcu_kernel_id;
+typedef struct {
+    hipEvent_t begin, end;  /* the caller's events                         */
+    int32_t kernel;         /* tcu_kernel_id                               */
+    int32_t m, n, k;        /* output rows, columns, contraction length    */
+    int32_t planes;         /* moduli or digit slices (1 for FP64)         */
+    double ops;             /* algorithmic operations of the launch        */
+} tcu_launch_record;
+tcu_status tcu_trace_launches(tcu_launch_record *records, int32_t capacity, int32_t *count);
 
 /* Measured matrix-core peaks, the rates the roofline is read against beside
  * the published ones (not a step of the method).  One launch of a
@@ -320,7 +418,7 @@ tcu_status tcu_join_agg_bsr(const tcu_relation *A, const tcu_relation *B, int32_
 /* The choice between the dense FP64 operator (tcu_join_agg_fwd) and the
  * block-sparse one (tcu_join_agg_bsr), after the paper's switch to TCU-SpMM
  * when the encodings are sparse (Section 4.2.4) and its cost model's
- * comparison of estimated times (Section 4.3).  Host only, no device call.
+ * comparison of estimated times (Section 4.2.2).  Host only, no device call.
  * Returns 1 when the block-sparse form is predicted faster, 0 when the dense
  * one is, TCU_ERR_ARG on bad arguments.  The model, with constants measured
  * on MI355X on Q1 pair counts (one record per tuple, n = 4096 and 8192,
@@ -377,8 +475,9 @@ tcu_status tcu_gemm_f64_host(int32_t m, int32_t n, int32_t k, const double *A, i
                              size_t dev_bytes, int64_t block, hipStream_t stream);
 
 /* SYNCHRONISES the stream, then reads the workspace status block written by
- * the last call that used `ws`.  Returns TCU_ERR_KEY_RANGE if records were
- * skipped, TCU_ERR_NONFINITE if the mixed form met NaN/Inf, else TCU_OK.
+ * the last call that used `ws`.  Returns TCU_ERR_NONFINITE if the mixed form
+ * met NaN/Inf, else TCU_ERR_KEY_RANGE if records were skipped, else
+ * TCU_ERR_COUNT_RANGE if a pair count exceeded INT32_MAX, else TCU_OK.
  * info (may be NULL) receives the whole block. */
 tcu_status tcu_sync_status(void *ws, hipStream_t stream, tcu_status_info *info);
 

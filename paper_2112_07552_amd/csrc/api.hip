@@ -37,25 +37,6 @@ bool is_split(tcu_precision p) {
 }
 bool is_crt(tcu_precision p) { return p == TCU_PREC_CRT_I8; }
 
-// The CRT form's plan: truncation width and number of moduli (see tcudb.h).
-int crt_plan(int32_t k, double tol, int32_t *bits_out) {
-    if (k < 1) return TCU_ERR_ARG;
-    if (!(tol > 0.0)) tol = 1e-12;
-    if (k >= 131072) return TCU_ERR_INFEASIBLE;
-    int bits = 0;
-    for (int b = 2; b <= 53; ++b) {
-        const double bound = ldexp(1.0, 2 - b) + ldexp(1.0, 2 - 2 * b) + ldexp(1.0, -51);
-        if (bound <= tol) { bits = b; break; }
-    }
-    if (bits == 0) return TCU_ERR_INFEASIBLE;
-    const double need = 2.0 * bits + log2((double)k) + 2.0;
-    for (int L = 1; L <= crt_max_moduli(); ++L)
-        if (crt_modulus_bits(L) > need) {
-            if (bits_out != nullptr) *bits_out = bits;
-            return L;
-        }
-    return TCU_ERR_INFEASIBLE;
-}
 bool precision_ok(tcu_precision p) { return p == TCU_PREC_FP64 || is_split(p); }
 
 size_t pad128(int64_t x) { return (size_t)((x + 127) / 128 * 128); }
@@ -63,19 +44,80 @@ size_t pad64(int64_t x) { return (size_t)((x + 63) / 64 * 64); }
 size_t pad256(int64_t x) { return (size_t)((x + 255) / 256 * 256); }
 size_t maxz(size_t a, size_t b) { return a > b ? a : b; }
 
+// Mixed forms: tolerances below 2^-50 are refused (the encodings carry 53
+// bits), and the residue form's int32 sums stay exact for k < 2^17.
+constexpr double kMinTol = 0x1p-50;
+constexpr int32_t kCrtMaxK = 131071;
+
+double tol_or_default(double tol) { return tol > 0.0 ? tol : 1e-12; }
+
+// Whether a mixed-form product of contraction length k can meet tol for
+// some data (the shape-only part of the plan).
+bool mixed_shape_ok(tcu_precision p, int32_t k, double tol) {
+    return tol_or_default(tol) >= kMinTol && !(is_crt(p) && k > kCrtMaxK);
+}
+
+// FP64 additions in the digit forms' combination of one output: S
+// diagonals per exact chunk of the contraction.
+int64_t digit_adds(int S, bool bf16, int64_t k) {
+    const int kstep = bf16 ? 16 : 32;
+    const int64_t nblk = (int64_t)pad64(k) / kstep;
+    const int64_t chunk = split_chunk_steps(S, bf16);
+    return (int64_t)S * ((nblk + chunk - 1) / chunk);
+}
+
+// Step a0 host part: the plan of one product from its certificate (see
+// tcudb.h, tcu_mixed_plan).
+int mixed_plan(tcu_precision p, int32_t k, double tol, uint32_t need, double u,
+               int32_t *bits_out) {
+    if (!is_split(p) || k < 1) return TCU_ERR_ARG;
+    tol = tol_or_default(tol);
+    if (!mixed_shape_ok(p, k, tol) || need >= kNeedUncertified) return TCU_ERR_INFEASIBLE;
+    if (!is_crt(p)) {
+        const int S = need < 1 ? 1 : (int)need;
+        return S <= TCU_MAX_SLICES ? S : TCU_ERR_INFEASIBLE;
+    }
+    const int b = need < 1 ? 1 : (int)need;
+    if (b > 53) return TCU_ERR_INFEASIBLE;
+    // |P| < 2^(2b) min(u, k); the reconstruction needs M > 4 |P|
+    const double U = std::min(std::max(u, 1.0), (double)k);
+    const double need_bits = 2.0 * b + log2(U) + 2.0;
+    for (int L = 1; L <= crt_max_moduli(); ++L)
+        if (crt_modulus_bits(L) > need_bits) {
+            if (bits_out != nullptr) *bits_out = b;
+            return L;
+        }
+    return TCU_ERR_INFEASIBLE;
+}
+
 // Workspace layout:
 //   [status block][X: M*K f64][Y: K*N f64]
 //   [G: M*K f64][G2: K*N f64]                           (backward: dX, dY)
-//   [line maxima and exponents of operands A and B]     (mixed forms)
-//   [digit slices of operands A and B, TCU_MAX_SLICES each]
+//   mixed forms, per operand A and B of a product:
+//   [line maxima][exponents][normalised sums of |z|][partial column sums]
+//   [magnitude plane][digit slices or residues, TCU_MAX_SLICES or
+//    TCU_MAX_MODULI planes]  and, for the residue form, the product's residues
 // In the mixed forms "A" is the left operand of a product (X forward, W
 // for dX, X^T for dY) and "B" the right one (Y, Y^T, W).
 struct Layout {
     size_t x = 0, y = 0, g = 0, g2 = 0, mba = 0, mbb = 0, ea = 0, eb = 0, sa = 0, sb = 0, res = 0;
+    size_t sxa = 0, sxb = 0, psa = 0, psb = 0, qa = 0, qb = 0;
     size_t total = 0;
 };
 
-Layout plan_layout(int32_t M, int32_t K, int32_t N, tcu_precision p, int flags) {
+// Padding of the magnitude planes (the int8 GEMM's operand layout).
+size_t qlen(int64_t x) { return (size_t)((x + crt_len_align() - 1) / crt_len_align() * crt_len_align()); }
+
+// Whether a forward with a count output takes the int8 path (both relations
+// with unique cells: multiplicities 0 or 1), which needs 0/1 planes.
+bool count_planes(const tcu_relation *A, const tcu_relation *B, int flags) {
+    if ((flags & TCU_WS_COUNT) == 0) return false;
+    if (A == nullptr || B == nullptr) return true;
+    return (A->flags & TCU_REL_UNIQUE_CELLS) && (B->flags & TCU_REL_UNIQUE_CELLS);
+}
+
+Layout plan_layout(int32_t M, int32_t K, int32_t N, tcu_precision p, int flags,
+                   bool with_count_planes = false) {
     Layout L;
     const bool bwd = (flags & TCU_WS_BACKWARD) != 0;
     size_t off = sizeof(StatusBlock);
@@ -101,6 +143,8 @@ Layout plan_layout(int32_t M, int32_t K, int32_t N, tcu_precision p, int flags) 
         // backward W (M, N) and Y^T (K, N) for dX, X^T (K, M) and W (N, M) for dY
         size_t la = padl(M), lb = padl(N);
         size_t za = padl(M) * padk(K), zb = padl(N) * padk(K);
+        size_t qa = pad256(M) * qlen(K), qb = pad256(N) * qlen(K);
+        size_t na = pad256(M), nb = pad256(N);
         // CRT: per-modulus residues of each product (m x n, rows padded to 32)
         size_t out = (size_t)crt_residue_plane(M, N);
         if (bwd) {
@@ -108,18 +152,35 @@ Layout plan_layout(int32_t M, int32_t K, int32_t N, tcu_precision p, int flags) 
             lb = maxz(lb, padl(K));
             za = maxz(za, maxz(padl(M) * padk(N), padl(K) * padk(M)));
             zb = maxz(zb, maxz(padl(K) * padk(N), padl(N) * padk(M)));
+            qa = maxz(qa, maxz(pad256(M) * qlen(N), pad256(K) * qlen(M)));
+            qb = maxz(qb, maxz(pad256(K) * qlen(N), pad256(N) * qlen(M)));
+            na = maxz(na, pad256(K));
+            nb = maxz(nb, pad256(K));
             out = maxz(out, maxz((size_t)crt_residue_plane(M, K), (size_t)crt_residue_plane(K, N)));
         }
+        la = maxz(la, na);
+        lb = maxz(lb, nb);
         L.mba = off; off += align_up(la * 8);
         L.mbb = off; off += align_up(lb * 8);
         L.ea = off; off += align_up(la * 4);
         L.eb = off; off += align_up(lb * 4);
+        L.sxa = off; off += align_up(la * 8);
+        L.sxb = off; off += align_up(lb * 8);
+        L.psa = off; off += align_up((size_t)kColParts * la * 8);
+        L.psb = off; off += align_up((size_t)kColParts * lb * 8);
+        L.qa = off; off += align_up(qa);
+        L.qb = off; off += align_up(qb);
         L.sa = off; off += align_up(planes * za * digit);
         L.sb = off; off += align_up(planes * zb * digit);
         if (is_crt(p)) {
             L.res = off;
             off += align_up(TCU_MAX_MODULI * out);
         }
+    } else if (with_count_planes) {
+        // the count's 0/1 planes (the mixed forms' magnitude planes hold them
+        // there)
+        L.qa = off; off += align_up(pad256(M) * qlen(K));
+        L.qb = off; off += align_up(pad256(N) * qlen(K));
     }
     L.total = off;
     return L;
@@ -161,41 +222,87 @@ struct SplitOperand {
 };
 
 // Plan of one mixed-form product: the slice count S (or modulus count, with
-// the truncation width `bits`), the padded contraction length and the padded
-// line counts of the two operands.
+// the truncation width `bits`; S = 0: no certified plan, the product runs in
+// FP64), the padded contraction length and the padded line counts.
 struct MixedPlan {
     int S = 0, bits = 0, len_pad = 0, la = 0, lb = 0;
 };
 
-hipError_t mixed_plan(int m, int n, int k, int S, tcu_precision p, double tol, MixedPlan *mp) {
-    mp->S = S;
-    if (is_crt(p)) {
-        int32_t bits = 0;
-        const int nmod = crt_plan(k, tol, &bits);
-        if (nmod != S) return hipErrorInvalidValue;  // the caller planned with the same k, tol
+// Step a0 for one operand: line maxima and sums of |z|, then the magnitude
+// plane and normalised sums of the certificate.
+hipError_t certify_prepare(const SplitOperand &o, bool second, void *ws, const Layout &L,
+                           StatusBlock *st, hipStream_t s) {
+    auto *mb = at<unsigned long long>(ws, second ? L.mbb : L.mba);
+    double *ps = at<double>(ws, second ? L.psb : L.psa);
+    const int lines = o.axis == 0 ? o.rows : o.cols, len = o.axis == 0 ? o.cols : o.rows;
+    hipError_t e = launch_line_max(o.Z, o.rows, o.cols, o.ld, o.axis, mb, ps, st, s);
+    if (e != hipSuccess) return e;
+    return launch_mag_plane(o.Z, o.rows, o.cols, o.ld, o.axis, mb, ps,
+                            at<double>(ws, second ? L.sxb : L.sxa),
+                            second ? &st->umax_b : &st->umax_a,
+                            at<int8_t>(ws, second ? L.qb : L.qa), (int)pad256(lines),
+                            (int)qlen(len), s);
+}
+
+// The certificate of a product whose operands went through certify_prepare,
+// then the plan.  Reads the certificate back: SYNCHRONISES the stream.
+hipError_t certify_and_plan(int m, int n, int k, tcu_precision p, double tol, void *ws,
+                            const Layout &L, StatusBlock *st, MixedPlan *mp, hipStream_t s) {
+    tol = tol_or_default(tol);
+    CertArgs ca{};
+    ca.sx = at<double>(ws, L.sxa);
+    ca.sy = at<double>(ws, L.sxb);
+    // the residue form's reconstruction rounds once, the digit forms'
+    // combination once per FP64 addition; the factor keeps the comparisons
+    // on the safe side of their own roundings
+    ca.tcrt = (tol - 0x1p-52) * (1.0 - 0x1p-40);
+    ca.kterm = 16384.0 * (double)k;
+    for (int S = 1; S <= TCU_MAX_SLICES; ++S)
+        ca.tdig[S] = is_crt(p) ? 0.0
+                               : (tol - (double)digit_adds(S, p == TCU_PREC_SPLIT_BF16, k) *
+                                            0x1p-52) * (1.0 - 0x1p-40);
+    ca.need_bits = &st->need_bits;
+    ca.need_slices = &st->need_slices;
+    hipError_t e = launch_certify(m, n, k, at<int8_t>(ws, L.qa), (int)pad256(m),
+                                  at<int8_t>(ws, L.qb), (int)pad256(n), (int)qlen(k), ca, s);
+    if (e != hipSuccess) return e;
+    StatusBlock host;
+    e = hipMemcpyAsync(&host, st, sizeof(host), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    double ua, ub;
+    memcpy(&ua, &host.umax_a, sizeof(ua));
+    memcpy(&ub, &host.umax_b, sizeof(ub));
+    int32_t bits = 0;
+    int r = TCU_ERR_NONFINITE;
+    if (!(host.flags & kFlagNonFinite))
+        r = mixed_plan(p, k, tol, is_crt(p) ? host.need_bits : host.need_slices,
+                       std::min(ua, ub), &bits);
+    *mp = MixedPlan{};
+    if (r > 0) {
+        mp->S = r;
         mp->bits = bits;
-        mp->len_pad = (k + crt_len_align() - 1) / crt_len_align() * crt_len_align();
-        mp->la = (int)pad256(m);
-        mp->lb = (int)pad256(n);
-    } else {
-        mp->len_pad = (int)pad64(k);
-        mp->la = (int)pad128(m);
-        mp->lb = (int)pad128(n);
+        if (is_crt(p)) {
+            mp->len_pad = (int)qlen(k);
+            mp->la = (int)pad256(m);
+            mp->lb = (int)pad256(n);
+        } else {
+            mp->len_pad = (int)pad64(k);
+            mp->la = (int)pad128(m);
+            mp->lb = (int)pad128(n);
+        }
     }
     return hipSuccess;
 }
 
-// Line maxima, exponents and digit slices (or residues) of one operand of a
-// mixed-form product, into the workspace buffers of side A (second = false)
-// or side B; the two sides touch disjoint buffers (and the status block only
-// through atomics), so they may run on different streams.
-hipError_t mixed_prepare(const SplitOperand &o, bool second, const MixedPlan &mp, tcu_precision p,
-                         void *ws, const Layout &L, StatusBlock *st, hipStream_t s) {
-    auto *mb = at<unsigned long long>(ws, second ? L.mbb : L.mba);
+// Digit slices or residues of one operand under the plan (its line maxima
+// are in place from certify_prepare), into the workspace buffers of side A
+// (second = false) or side B.
+hipError_t mixed_split(const SplitOperand &o, bool second, const MixedPlan &mp, tcu_precision p,
+                       void *ws, const Layout &L, hipStream_t s) {
+    const auto *mb = at<unsigned long long>(ws, second ? L.mbb : L.mba);
     int *ex = at<int>(ws, second ? L.eb : L.ea);
     const int lines = second ? mp.lb : mp.la;
-    hipError_t e = launch_line_max(o.Z, o.rows, o.cols, o.ld, o.axis, mb, st, s);
-    if (e != hipSuccess) return e;
     if (is_crt(p))
         return launch_crt_split(o.Z, o.rows, o.cols, o.ld, o.axis, mb, mp.S, mp.bits,
                                 at<int8_t>(ws, second ? L.sb : L.sa), lines, mp.len_pad, ex, s);
@@ -215,14 +322,36 @@ hipError_t mixed_multiply(int m, int n, int k, const MixedPlan &mp, tcu_precisio
                              at<char>(ws, L.sb), mp.lb, mp.len_pad, ea, eb, C, ldc, s);
 }
 
-hipError_t split_product(const SplitOperand &a, const SplitOperand &b, int m, int n, int k,
-                         int S, tcu_precision p, double tol, void *ws, const Layout &L,
-                         StatusBlock *st, double *C, int64_t ldc, hipStream_t s) {
+// The rest of a product once both operands went through certify_prepare:
+// certificate and plan, then the narrow products, or the FP64 product of
+// the same operands when no plan is certified (recorded in the status
+// block with the plan).
+hipError_t finish_product(const SplitOperand &a, const SplitOperand &b, int m, int n, int k,
+                          tcu_precision p, double tol, void *ws, const Layout &L, StatusBlock *st,
+                          double *C, int64_t ldc, hipStream_t s) {
     MixedPlan mp;
-    hipError_t e = mixed_plan(m, n, k, S, p, tol, &mp);
-    if (e == hipSuccess) e = mixed_prepare(a, false, mp, p, ws, L, st, s);
-    if (e == hipSuccess) e = mixed_prepare(b, true, mp, p, ws, L, st, s);
+    hipError_t e = certify_and_plan(m, n, k, p, tol, ws, L, st, &mp, s);
+    if (e != hipSuccess) return e;
+    if (mp.S == 0) {
+        e = launch_gemm_f64(a.axis, b.axis == 0 ? 1 : 0, m, n, k, a.Z, a.ld, b.Z, b.ld, C, ldc, s);
+        if (e == hipSuccess) e = launch_set_plan(st, 0, 0, true, s);
+        return e;
+    }
+    e = mixed_split(a, false, mp, p, ws, L, s);
+    if (e == hipSuccess) e = mixed_split(b, true, mp, p, ws, L, s);
     if (e == hipSuccess) e = mixed_multiply(m, n, k, mp, p, ws, L, C, ldc, s);
+    if (e == hipSuccess) e = launch_set_plan(st, (uint32_t)mp.S, (uint32_t)mp.bits, false, s);
+    return e;
+}
+
+// One whole mixed-form product of two dense operands.
+hipError_t mixed_product(const SplitOperand &a, const SplitOperand &b, int m, int n, int k,
+                         tcu_precision p, double tol, void *ws, const Layout &L, StatusBlock *st,
+                         double *C, int64_t ldc, hipStream_t s) {
+    hipError_t e = launch_reset_plan(st, s);
+    if (e == hipSuccess) e = certify_prepare(a, false, ws, L, st, s);
+    if (e == hipSuccess) e = certify_prepare(b, true, ws, L, st, s);
+    if (e == hipSuccess) e = finish_product(a, b, m, n, k, p, tol, ws, L, st, C, ldc, s);
     return e;
 }
 
@@ -293,33 +422,37 @@ struct CallEvents {
 
 }  // namespace
 
+LaunchTrace &tcu::launch_trace() {
+    static thread_local LaunchTrace t;
+    return t;
+}
+
 extern "C" {
+
+tcu_status tcu_trace_launches(tcu_launch_record *records, int32_t capacity, int32_t *count) {
+    LaunchTrace &t = launch_trace();
+    if (count == nullptr) {
+        t = LaunchTrace{};
+        return TCU_OK;
+    }
+    if (capacity < 0 || (capacity > 0 && records == nullptr)) return TCU_ERR_ARG;
+    *count = 0;
+    t.rec = records;
+    t.cap = capacity;
+    t.count = count;
+    return TCU_OK;
+}
 
 size_t tcu_workspace_bytes(const tcu_relation *A, const tcu_relation *B, int32_t M, int32_t K,
                            int32_t N, tcu_precision p, int flags) {
-    (void)A; (void)B;
     if (!shapes_ok(M, K, N)) return 0;
     if (!precision_ok(p)) return 0;
-    return plan_layout(M, K, N, p, flags).total;
+    return plan_layout(M, K, N, p, flags, count_planes(A, B, flags)).total;
 }
 
-int tcu_crt_plan(int32_t k, double tol, int32_t *bits) { return crt_plan(k, tol, bits); }
-
-int tcu_split_slices(tcu_precision p, int32_t k, double tol) {
-    if (!is_split(p) || k < 1) return TCU_ERR_ARG;
-    if (is_crt(p)) return crt_plan(k, tol, nullptr);
-    if (!(tol > 0.0)) tol = 1e-12;
-    const int bf16 = p == TCU_PREC_SPLIT_BF16;
-    const int kstep = bf16 ? 16 : 32;
-    const int64_t nblk = (int64_t)pad64(k) / kstep;
-    for (int S = 1; S <= TCU_MAX_SLICES; ++S) {
-        const int64_t chunk = split_chunk_steps(S, bf16);
-        const int64_t n_add = (int64_t)S * ((nblk + chunk - 1) / chunk);
-        const double trunc_bound = 4.04 * (S + 1) * ldexp(1.0, -7 * S);
-        const double round_bound = 4.04 * (double)n_add * ldexp(1.0, -53);
-        if (trunc_bound + round_bound <= tol) return S;
-    }
-    return TCU_ERR_INFEASIBLE;
+int tcu_mixed_plan(tcu_precision p, int32_t k, double tol, uint32_t need, double u,
+                   int32_t *bits) {
+    return mixed_plan(p, k, tol, need, u, bits);
 }
 
 tcu_status tcu_split(const double *Z, int32_t rows, int32_t cols, int64_t ld, int axis,
@@ -335,7 +468,7 @@ tcu_status tcu_split(const double *Z, int32_t rows, int32_t cols, int64_t ld, in
     StatusBlock *st = at<StatusBlock>(ws, 0);
     auto *mb = at<unsigned long long>(ws, sizeof(StatusBlock));
     TCU_TRY(launch_clear_status(st, stream, (uint32_t)S));
-    TCU_TRY(launch_line_max(Z, rows, cols, ld, axis, mb, st, stream));
+    TCU_TRY(launch_line_max(Z, rows, cols, ld, axis, mb, nullptr, st, stream));
     TCU_TRY(launch_split(Z, rows, cols, ld, axis, mb, S, p == TCU_PREC_SPLIT_BF16, slices,
                          lines_pad, len_pad, exps, stream));
     return TCU_OK;
@@ -367,6 +500,29 @@ tcu_status tcu_gemm_f64(int trans_a, int trans_b, int32_t m, int32_t n, int32_t 
     return hip_status(launch_gemm_f64(trans_a, trans_b, m, n, k, A, lda, B, ldb, C, ldc, stream));
 }
 
+size_t tcu_gemm_f64_workspace_bytes(int32_t m, int32_t n, int32_t k) {
+    if (m < 1 || n < 1 || k < 1) return 0;
+    return gemm_f64_split_bytes(m, n, k);
+}
+
+tcu_status tcu_gemm_f64_ws(int trans_a, int trans_b, int32_t m, int32_t n, int32_t k,
+                           const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
+                           int64_t ldc, void *ws, size_t ws_bytes, hipStream_t stream) {
+    if ((trans_a != 0 && trans_a != 1) || (trans_b != 0 && trans_b != 1)) return TCU_ERR_ARG;
+    if (m < 0 || n < 0 || k < 0) return TCU_ERR_ARG;
+    if (m == 0 || n == 0) return TCU_OK;
+    if (C == nullptr || ldc < n) return TCU_ERR_ARG;
+    if (k > 0) {
+        if (A == nullptr || B == nullptr) return TCU_ERR_ARG;
+        if (lda < (trans_a ? m : k) || ldb < (trans_b ? k : n)) return TCU_ERR_ARG;
+    }
+    const size_t need = k > 0 ? gemm_f64_split_bytes(m, n, k) : 0;
+    if (need > 0 && !ws_ok(ws, ws_bytes, need)) return TCU_ERR_WORKSPACE;
+    return hip_status(launch_gemm_f64_split(trans_a, trans_b, m, n, k, A, lda, B, ldb, C, ldc,
+                                            need > 0 ? static_cast<double *>(ws) : nullptr,
+                                            stream));
+}
+
 tcu_status tcu_join_agg_fwd(const tcu_relation *A, const tcu_relation *B, int32_t M, int32_t K,
                             int32_t N, tcu_precision p, double tol, double *C, int32_t *count,
                             void *ws, size_t ws_bytes, hipStream_t stream) {
@@ -383,47 +539,54 @@ tcu_status tcu::join_agg_fwd_ws(const tcu_relation *A, const tcu_relation *B, in
     if (!relation_ok(A) || !relation_ok(B) || !shapes_ok(M, K, N) || C == nullptr)
         return TCU_ERR_ARG;
     if (!precision_ok(p)) return TCU_ERR_ARG;
-    int S = 0;
-    if (is_split(p)) {
-        S = tcu_split_slices(p, K, tol);
-        if (S < 0) return (tcu_status)S;
-    }
-    const Layout L = plan_layout(M, K, N, p, 0);
+    if (is_split(p) && !mixed_shape_ok(p, K, tol)) return TCU_ERR_INFEASIBLE;
+    const bool planes = count != nullptr && count_planes(A, B, TCU_WS_COUNT);
+    const Layout L = plan_layout(M, K, N, p, 0, planes);
     if (!ws_ok(ws, ws_bytes, L.total)) return TCU_ERR_WORKSPACE;
     StatusBlock *st = at<StatusBlock>(ws, 0);
     double *X = at<double>(ws, L.x), *Y = at<double>(ws, L.y);
 
-    TCU_TRY(launch_clear_status(st, stream, (uint32_t)S));
-    if (count != nullptr) {
-        // exact pair counts: the 0/1 (multiplicity) encodings of Section 3.1,
-        // multiplied in FP64 (integers below 2^53 are exact), C as scratch
+    TCU_TRY(launch_clear_status(st, stream));
+    if (planes) {
+        // exact pair counts, Section 3.1's 0/1 encodings (unique cells): one
+        // int8 product with exact int32 sums (K < 2^31)
+        int8_t *qa = at<int8_t>(ws, L.qa), *qb = at<int8_t>(ws, L.qb);
+        TCU_TRY(launch_count_planes(*A, M, K, qa, (int)pad256(M), (int)qlen(K), stream));
+        TCU_TRY(launch_count_planes(*B, N, K, qb, (int)pad256(N), (int)qlen(K), stream));
+        TCU_TRY(launch_count_product(M, N, K, qa, (int)pad256(M), qb, (int)pad256(N),
+                                     (int)qlen(K), count, N, stream));
+    } else if (count != nullptr) {
+        // the multiplicity encodings of Section 3.1, multiplied in FP64 (every
+        // partial sum is a non-negative integer no larger than the count, so a
+        // count below 2^53 is exact), C as scratch; counts beyond int32 are
+        // saturated and flagged
         TCU_TRY(encode_both(*A, *B, M, K, N, X, Y, nullptr, true, stream));
         TCU_TRY(launch_gemm_f64(0, 0, M, N, K, X, K, Y, N, C, N, stream));
-        TCU_TRY(launch_f64_to_i32(C, count, (size_t)M * N, stream));
+        TCU_TRY(launch_f64_to_i32(C, count, (size_t)M * N, st, stream));
     }
-    if (S == 0) {
+    if (!is_split(p)) {
         TCU_TRY(encode_both(*A, *B, M, K, N, X, Y, st, false, stream));
         TCU_TRY(launch_gemm_f64(0, 0, M, N, K, X, K, Y, N, C, N, stream));
         return TCU_OK;
     }
     // Mixed forms: each operand is encoded and at once reduced to its line
-    // maxima and slices or residues, which read it while it is still in the
-    // caches; then the other operand.
+    // statistics and magnitude plane, which read it while it is still in the
+    // caches; then the other operand, the certificate and the plan.
     // X: M lines (rows) of length K; Y: N lines (columns) of length K
     const SplitOperand a{X, M, K, K, 0}, b{Y, K, N, N, 1};
-    MixedPlan mp;
-    TCU_TRY(mixed_plan(M, N, K, S, p, tol, &mp));
+    TCU_TRY(launch_reset_plan(st, stream));
     TCU_TRY(encode_one(*A, 0, M, K, X, st, stream));
-    TCU_TRY(mixed_prepare(a, false, mp, p, ws, L, st, stream));
+    TCU_TRY(certify_prepare(a, false, ws, L, st, stream));
     TCU_TRY(encode_one(*B, 1, K, N, Y, st, stream));
-    TCU_TRY(mixed_prepare(b, true, mp, p, ws, L, st, stream));
-    TCU_TRY(mixed_multiply(M, N, K, mp, p, ws, L, C, N, stream));
+    TCU_TRY(certify_prepare(b, true, ws, L, st, stream));
+    TCU_TRY(finish_product(a, b, M, N, K, p, tol, ws, L, st, C, N, stream));
     return TCU_OK;
 }
 
-size_t tcu::join_agg_fwd_ws_bytes(int32_t M, int32_t K, int32_t N, tcu_precision p) {
+size_t tcu::join_agg_fwd_ws_bytes(const tcu_relation *A, const tcu_relation *B, int32_t M,
+                                  int32_t K, int32_t N, tcu_precision p, bool with_count) {
     if (!shapes_ok(M, K, N) || !precision_ok(p)) return 0;
-    return plan_layout(M, K, N, p, 0).total;
+    return plan_layout(M, K, N, p, 0, with_count && count_planes(A, B, TCU_WS_COUNT)).total;
 }
 
 extern "C" {
@@ -436,13 +599,10 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
         return TCU_ERR_ARG;
     if ((flags & ~TCU_BWD_SAVED_ENCODINGS) != 0) return TCU_ERR_ARG;
     if (!precision_ok(p)) return TCU_ERR_ARG;
-    int S1 = 0, S2 = 0;
-    if (is_split(p)) {
-        S1 = tcu_split_slices(p, N, tol);  // dX contracts over h
-        S2 = tcu_split_slices(p, M, tol);  // dY contracts over g
-        if (S1 < 0) return (tcu_status)S1;
-        if (S2 < 0) return (tcu_status)S2;
-    }
+    // dX contracts over h (length N), dY over g (length M)
+    if (is_split(p) && (!mixed_shape_ok(p, N, tol) || !mixed_shape_ok(p, M, tol)))
+        return TCU_ERR_INFEASIBLE;
+    const bool mixed = is_split(p);
     const Layout L = plan_layout(M, K, N, p, TCU_WS_BACKWARD);
     if (!ws_ok(ws, ws_bytes, L.total)) return TCU_ERR_WORKSPACE;
     StatusBlock *st = at<StatusBlock>(ws, 0);
@@ -485,12 +645,12 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
     }
     if (dA_val != nullptr) {
         // dX = dC * Y^T (M x K), then dA.val[i] = dX[g_i, k_i]
-        if (S1 == 0) {
+        if (!mixed) {
             TCU_TRY(launch_gemm_f64(0, 1, M, K, N, dC, N, Y, N, G, K, stream));
         } else {
             // dC: M lines (rows) of length N; Y^T: K lines = rows of Y, length N
             const SplitOperand a{dC, M, N, N, 0}, b{Y, K, N, N, 0};
-            TCU_TRY(split_product(a, b, M, K, N, S1, p, tol, ws, L, st, G, K, stream));
+            TCU_TRY(mixed_product(a, b, M, K, N, p, tol, ws, L, st, G, K, stream));
         }
         if (both) {
             // ev_fork is free again once the side stream has waited for it
@@ -510,7 +670,7 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
         // when that costs no extra round of workgroups: the dB gather of the
         // first block's records runs on the side stream beside the second
         // block's product, and only the second block's gather stays behind.
-        const int k1 = (both && S2 == 0) ? gemm_f64_row_cut(K, N) : 0;
+        const int k1 = (both && !mixed) ? gemm_f64_row_cut(K, N) : 0;
         if (k1 > 0) {
             TCU_TRY(launch_gemm_f64(1, 0, k1, N, M, X, K, dC, N, G2, N, stream));
             TCU_TRY(hipEventRecord(ev_fork, stream));
@@ -519,12 +679,12 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
             TCU_TRY(hipEventRecord(ev_a, side));
             TCU_TRY(launch_gemm_f64(1, 0, K - k1, N, M, X + k1, K, dC, N, G2 + (size_t)k1 * N, N,
                                     stream));
-        } else if (S2 == 0) {
+        } else if (!mixed) {
             TCU_TRY(launch_gemm_f64(1, 0, K, N, M, X, K, dC, N, G2, N, stream));
         } else {
             // X^T: K lines = columns of X, length M; dC: N lines = columns, length M
             const SplitOperand a{X, M, K, K, 1}, b{dC, M, N, N, 1};
-            TCU_TRY(split_product(a, b, K, N, M, S2, p, tol, ws, L, st, G2, N, stream));
+            TCU_TRY(mixed_product(a, b, K, N, M, p, tol, ws, L, st, G2, N, stream));
         }
         TCU_TRY(launch_gather(*B, 1, K, N, G2, dB_val, stream, k1, K));
         if (both) TCU_TRY(evs.join(ev_a));  // the side's gathers are done
@@ -652,9 +812,12 @@ tcu_status tcu_sync_status(void *ws, hipStream_t stream, tcu_status_info *info) 
         info->slices = host.slices;
         info->skipped_a = host.skipped_a;
         info->skipped_b = host.skipped_b;
+        info->bits = host.bits;
+        info->need = host.need_bits > host.need_slices ? host.need_bits : host.need_slices;
     }
     if (host.flags & kFlagNonFinite) return TCU_ERR_NONFINITE;
     if (host.flags & kFlagKeyRange) return TCU_ERR_KEY_RANGE;
+    if (host.flags & kFlagCountRange) return TCU_ERR_COUNT_RANGE;
     return TCU_OK;
 }
 
@@ -667,6 +830,7 @@ const char *tcu_status_str(tcu_status s) {
         case TCU_ERR_INFEASIBLE: return "requested tolerance not reachable by the mixed form";
         case TCU_ERR_NONFINITE: return "non-finite value in the mixed form";
         case TCU_ERR_HIP: return "HIP runtime error";
+        case TCU_ERR_COUNT_RANGE: return "a pair count exceeded int32 (stored as INT32_MAX)";
     }
     return "unknown status";
 }

@@ -215,6 +215,142 @@ crt_cols_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
         *reinterpret_cast<uint4 *>(o + (int64_t)i * plane) = residues16(pc, cc, i);
 }
 
+// ------------------------------------------------------- the certificate
+// The plan of a mixed-form product is certified cell by cell from a lower
+// bound of (|X||Y|)[g,h] computed by one int8 GEMM of "magnitude planes":
+//   q = floor(|z| 2^(7 - e)) in [0, 127],  e the line's exponent as above,
+// so q 2^(e - 7) <= |z| and D_lo = 2^(e_g + f_h - 14) (Q_X Q_Y)[g,h] <=
+// (|X||Y|)[g,h], exactly (power-of-two scalings, exact integer sums).  The
+// lines also carry their sums of |z| relative to 2^e, s = sum |z| 2^-e
+// (rounded up), which bound the truncation errors (see CertArgs).
+
+// The normalised sum of a line, rounded up: the FP64 sum of at most 2^31
+// non-negative terms is within a relative 2^-22 of the exact one, and the
+// power-of-two scaling is exact (for sums above the subnormal range).
+__device__ inline double shat_of(double sum, int e) { return ldexp(sum, -e) * (1.0 + 0x1p-20); }
+
+// wave-wide maximum of non-negative doubles, then one atomic max per wave
+__device__ inline void wave_max_to(double v, unsigned long long *dst) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(dst, (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ inline int8_t mag_q(double z, int e) {
+    if (!isfinite(z)) z = 0.0;  // non-finite inputs are flagged by the line maxima
+    return (int8_t)(int)floor(ldexp(fabs(z), 7 - e));
+}
+
+__device__ inline uint4 pack16(const int8_t (&q)[16]) {
+    uint32_t w[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        w[j] = (uint32_t)(uint8_t)q[4 * j] | ((uint32_t)(uint8_t)q[4 * j + 1] << 8) |
+               ((uint32_t)(uint8_t)q[4 * j + 2] << 16) | ((uint32_t)(uint8_t)q[4 * j + 3] << 24);
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// Lines are rows (the tile walk of crt_rows_kernel).  sums[line] is the
+// line's sum of |z|; the blocks of the first position tile write shat and
+// fold its maximum into *umax.
+__global__ void __launch_bounds__(kThreads)
+mag_rows_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
+                const unsigned long long *__restrict__ maxbits, const double *__restrict__ sums,
+                double *__restrict__ shat, unsigned long long *umax, int8_t *__restrict__ out,
+                int lines_pad) {
+    __shared__ double tile[64][64 + 2];
+    const int p0 = blockIdx.x * 64, l0 = blockIdx.y * 64;
+    const int t = threadIdx.x;
+    int64_t off = (int64_t)(l0 + (t >> 6)) * ld + p0 + (t & 63);
+    const int64_t step = 4 * ld;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int lr = (t >> 6) + 4 * j, pc = t & 63;
+        const bool in = l0 + lr < rows && p0 + pc < cols;
+        const double v = Z[in ? off : 0];
+        tile[lr][pc] = in ? v : 0.0;
+        off += step;
+    }
+    __syncthreads();
+    const int r = t & 63, g = t >> 6;
+    const int line = l0 + r;
+    const int e = line < rows ? line_exp(maxbits[line]) : 0;
+    int8_t q[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) q[k] = mag_q(tile[r][16 * g + k], e);
+    *reinterpret_cast<uint4 *>(out + res_offset(line, p0 + 16 * g, lines_pad)) = pack16(q);
+    if (blockIdx.x == 0 && g == 0) {
+        double sh = 0.0;
+        if (line < rows) {
+            sh = shat_of(sums[line], e);
+            shat[line] = sh;
+        }
+        wave_max_to(sh, umax);
+    }
+}
+
+// Lines are columns (the walk of crt_cols_kernel); a column's sum is the sum
+// of its `parts` partial sums sums[part * cols + col], added in order.
+__global__ void __launch_bounds__(kThreads)
+mag_cols_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
+                const unsigned long long *__restrict__ maxbits, const double *__restrict__ sums,
+                int parts, double *__restrict__ shat, unsigned long long *umax,
+                int8_t *__restrict__ out, int lines_pad) {
+    const int p0 = blockIdx.x * 64, l0 = blockIdx.y * 64;
+    const int r = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int col = l0 + r;
+    const int e = col < cols ? line_exp(maxbits[col]) : 0;
+    int8_t q[16];
+    int64_t off = (int64_t)(p0 + 16 * g) * ld + col;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int row = p0 + 16 * g + k;
+        q[k] = mag_q((row < rows && col < cols) ? Z[off] : 0.0, e);
+        off += ld;
+    }
+    *reinterpret_cast<uint4 *>(out + res_offset(col, p0 + 16 * g, lines_pad)) = pack16(q);
+    if (blockIdx.x == 0 && g == 0) {
+        double sh = 0.0;
+        if (col < cols) {
+            double sm = 0.0;
+            for (int p = 0; p < parts; ++p) sm += sums[(int64_t)p * cols + col];
+            sh = shat_of(sm, e);
+            shat[col] = sh;
+        }
+        wave_max_to(sh, umax);
+    }
+}
+
+// Per cell (g, h), with T = (Q_X Q_Y)[g,h] and r = 2^14 (s_g + s_h) (r = 0
+// when s_g or s_h is 0: an all-zero line leaves nothing to truncate): the
+// truncation of both operands to `b`-bit integers per line (the residue
+// form) changes the product by at most 2^(e_g + f_h) 2^-b (s_g + s_h), and
+// S digits per line with the digit pairs past the first S anti-diagonals
+// dropped (the slice forms) by at most 2^(e_g + f_h) 2^-7S (s_g + s_h +
+// (S - 1) K).  Against D_lo = 2^(e_g + f_h - 14) T the cell meets the
+// tolerance with
+//   residue form:  2^-b r <= tcrt T,
+//   digit forms:   2^-7S (r + (S - 1) kterm) <= tdig[S] T,  kterm = 2^14 K,
+// where tcrt and tdig[S] are the tolerance less the rounding of the FP64
+// combination.  The cell's need is the smallest such b and S; a cell with T
+// = 0 but r > 0 cannot be bounded (kNeedUncertified).
+__device__ inline void cert_cell(double r, int T, const CertArgs &ca, uint32_t &nb,
+                                 uint32_t &ns) {
+    if (T <= 0) {
+        nb = ns = r > 0.0 ? kNeedUncertified : 0u;
+        return;
+    }
+    const double dT = (double)T;
+    int e = 0;
+    // 2^(e-1) <= q < 2^e, with q enlarged past the rounding of the division
+    frexp(r / (ca.tcrt * dT) * (1.0 + 0x1p-40), &e);
+    nb = (uint32_t)min(max(e, 1), (int)kNeedUncertified - 1);
+    ns = kNeedUncertified;
+#pragma unroll
+    for (int S = 1; S <= TCU_MAX_SLICES; ++S)
+        if (ns == kNeedUncertified && ldexp(r + (S - 1) * ca.kterm, -7 * S) <= ca.tdig[S] * dT)
+            ns = (uint32_t)S;
+}
+
 // ---------------------------------------------------------------- the GEMM
 // Tile configuration: a workgroup computes BM x BN outputs with NW waves in a
 // 2 x (NW / 2) grid (each wave 128 rows by BN / (NW / 2) columns, i.e. WA = 4
@@ -382,13 +518,19 @@ __device__ inline void crt_stages(int st, int nst, const StageLoads<G> &L, unsig
         crt_stages<G, B + 1>(st, nst, L, lds_addr, voff, lds_a, lds_b, fc, fm, acc);
 }
 
+// What the int8 GEMM does with its exact int32 sums.
+constexpr int kEpiResidue = 0;  // residues modulo the workgroup's modulus, int8 planes
+constexpr int kEpiCertify = 1;  // the plan's per-cell needs (cert_cell), maxima into ca
+constexpr int kEpiCount = 2;    // the int32 sums themselves (pair counts), into cnt
+
 // nblk (k-steps) must be a multiple of 2 NS.  SMALL: nblk * 32 <= 4096, so
 // every int32 sum is at most 2^26 in magnitude.
-template <typename G, bool SMALL>
+template <typename G, bool SMALL, int EPI>
 __global__ void __launch_bounds__(G::threads) __attribute__((amdgpu_waves_per_eu(G::WPE, G::WPE)))
 gemm_crt_kernel(int m, int n, int nblk, int tiles_m, int tiles_n, const int8_t *__restrict__ xs,
                 int xlp, const int8_t *__restrict__ ys, int ylp, int64_t plane_x,
-                int64_t plane_y, CrtConsts cc, int8_t *__restrict__ res, int64_t plane_res) {
+                int64_t plane_y, CrtConsts cc, int8_t *__restrict__ res, int64_t plane_res,
+                CertArgs ca, int32_t *__restrict__ cnt, int64_t ldcnt) {
     constexpr int WA = G::WA, WB = G::WB, PW = G::PER_WAVE, NS = G::NS;
     __shared__ __attribute__((aligned(16))) i4 lds[NS * G::STAGE];
     // workgroup -> (modulus, tile).  Tiles of one modulus are numbered in
@@ -448,6 +590,61 @@ gemm_crt_kernel(int m, int n, int nblk, int tiles_m, int tiles_n, const int8_t *
         crt_stages<G, 0>(st, nst, L, lds_addr, voff, lds_a, lds_b, fc, fm, acc);
     wait_vm<0>();  // no load into LDS outlives the loop
 
+    if constexpr (EPI == kEpiCount) {
+#pragma unroll
+        for (int a = 0; a < WA; ++a) {
+            const int rbase = m0 + wm * 32 * WA + a * 32;
+            if (rbase >= m) continue;
+#pragma unroll
+            for (int b = 0; b < WB; ++b) {
+                const int col = n0 + wn * 32 * WB + b * 32 + l32;
+                if (col >= n) continue;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int row = rbase + 8 * (i >> 2) + 4 * half + (i & 3);
+                    if (row < m) cnt[(int64_t)row * ldcnt + col] = acc[a][b][i];
+                }
+            }
+        }
+        return;
+    }
+    if constexpr (EPI == kEpiCertify) {
+        // each cell's needs (cert_cell); the wave's maxima go out in one atomic each
+        uint32_t nb = 0, ns = 0;
+#pragma unroll
+        for (int a = 0; a < WA; ++a) {
+            const int rbase = m0 + wm * 32 * WA + a * 32;
+            if (rbase >= m) continue;
+#pragma unroll
+            for (int b = 0; b < WB; ++b) {
+                const int col = n0 + wn * 32 * WB + b * 32 + l32;
+                if (col >= n) continue;
+                const double sy = ca.sy[col];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int row = rbase + 8 * (i >> 2) + 4 * half + (i & 3);
+                    if (row >= m) continue;
+                    // an all-zero line makes every term of the cell zero
+                    // in the exact and in the truncated product alike
+                    const double sx = ca.sx[row];
+                    const double r = (sx > 0.0 && sy > 0.0) ? 16384.0 * (sx + sy) : 0.0;
+                    uint32_t cb, cs;
+                    cert_cell(r, acc[a][b][i], ca, cb, cs);
+                    nb = max(nb, cb);
+                    ns = max(ns, cs);
+                }
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            nb = max(nb, (uint32_t)__shfl_xor((int)nb, off));
+            ns = max(ns, (uint32_t)__shfl_xor((int)ns, off));
+        }
+        if (lane == 0) {
+            atomicMax(ca.need_bits, nb);
+            atomicMax(ca.need_slices, ns);
+        }
+        return;
+    }
     // epilogue: residues of the int32 sums as int8 in the accumulator's own
     // order (see crt_reconstruct_kernel): one 16-byte store per 32 x 32 block
     const int mi = cc.mi[mod], c16 = cc.c16[mod];
@@ -658,19 +855,104 @@ hipError_t launch_gemm_crt(int m, int n, int k, int L, int bits, const int8_t *x
     const int64_t wgs = (int64_t)tiles_m * tiles_n * L;
     const int64_t plane_res = crt_residue_plane(m, n);
     using G = CrtCfg;
-    // |sum| <= len_pad 2^14 (residues at most 128 in magnitude)
-    if (len_pad <= 4096)
-        gemm_crt_kernel<G, true><<<(unsigned)wgs, G::threads, 0, s>>>(
-            m, n, nblk, tiles_m, tiles_n, xs, x_lines_pad, ys, y_lines_pad,
-            (int64_t)x_lines_pad * len_pad, (int64_t)y_lines_pad * len_pad, cc, res, plane_res);
-    else
-        gemm_crt_kernel<G, false><<<(unsigned)wgs, G::threads, 0, s>>>(
-            m, n, nblk, tiles_m, tiles_n, xs, x_lines_pad, ys, y_lines_pad,
-            (int64_t)x_lines_pad * len_pad, (int64_t)y_lines_pad * len_pad, cc, res, plane_res);
-    hipError_t e = hipGetLastError();
+    const CertArgs none{};
+    const int64_t px = (int64_t)x_lines_pad * len_pad, py = (int64_t)y_lines_pad * len_pad;
+    hipError_t e;
+    {
+        TraceScope ts(TCU_KERNEL_GEMM_CRT, m, n, k, L, L * 2.0 * m * n * (double)k, s);
+        // |sum| <= len_pad 2^14 (residues at most 128 in magnitude)
+        if (len_pad <= 4096)
+            gemm_crt_kernel<G, true, kEpiResidue><<<(unsigned)wgs, G::threads, 0, s>>>(
+                m, n, nblk, tiles_m, tiles_n, xs, x_lines_pad, ys, y_lines_pad, px, py, cc, res,
+                plane_res, none, nullptr, 0);
+        else
+            gemm_crt_kernel<G, false, kEpiResidue><<<(unsigned)wgs, G::threads, 0, s>>>(
+                m, n, nblk, tiles_m, tiles_n, xs, x_lines_pad, ys, y_lines_pad, px, py, cc, res,
+                plane_res, none, nullptr, 0);
+        e = hipGetLastError();
+    }
     if (e != hipSuccess) return e;
     const dim3 grid((unsigned)((n + kThreads / 4 - 1) / (kThreads / 4)), (unsigned)((m + 31) / 32));
     kReconstruct[L](grid, s, m, n, res, plane_res, cc, ex, ey, C, ldc, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_mag_plane(const double *Z, int rows, int cols, int64_t ld, int axis,
+                            const unsigned long long *maxbits, const double *sums, double *shat,
+                            unsigned long long *umax, int8_t *out, int lines_pad, int len_pad,
+                            hipStream_t s) {
+    if (rows < 1 || cols < 1 || lines_pad % 64 || len_pad % 64) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(len_pad / 64), (unsigned)(lines_pad / 64));
+    if (axis == 0)
+        mag_rows_kernel<<<grid, kThreads, 0, s>>>(Z, rows, cols, ld, maxbits, sums, shat, umax,
+                                                  out, lines_pad);
+    else
+        mag_cols_kernel<<<grid, kThreads, 0, s>>>(Z, rows, cols, ld, maxbits, sums,
+                                                  col_sum_parts(rows), shat, umax, out,
+                                                  lines_pad);
+    return hipGetLastError();
+}
+
+hipError_t launch_certify(int m, int n, int k, const int8_t *qa, int a_lines_pad,
+                          const int8_t *qb, int b_lines_pad, int len_pad, const CertArgs &ca,
+                          hipStream_t s) {
+    if (m == 0 || n == 0) return hipSuccess;
+    if (a_lines_pad % CrtCfg::BM || b_lines_pad % CrtCfg::BN || len_pad % kCrtLenAlign ||
+        len_pad < k || a_lines_pad < m || b_lines_pad < n)
+        return hipErrorInvalidValue;
+    const CrtConsts cc = make_consts(1, 0);
+    const int tiles_m = (m + CrtCfg::BM - 1) / CrtCfg::BM, tiles_n = (n + CrtCfg::BN - 1) / CrtCfg::BN;
+    using G = CrtCfg;
+    TraceScope ts(TCU_KERNEL_CERTIFY, m, n, k, 1, 2.0 * m * n * (double)k, s);
+    gemm_crt_kernel<G, false, kEpiCertify><<<(unsigned)(tiles_m * tiles_n), G::threads, 0, s>>>(
+        m, n, len_pad / 32, tiles_m, tiles_n, qa, a_lines_pad, qb, b_lines_pad,
+        (int64_t)a_lines_pad * len_pad, (int64_t)b_lines_pad * len_pad, cc, nullptr, 0, ca,
+        nullptr, 0);
+    return hipGetLastError();
+}
+
+// A 1 at (line = group, position = key) of every in-range record of R in its
+// 0/1 plane (zeroed first); plain byte stores (unique cells).  Skipped
+// records were counted by the value encoding already.
+__global__ void __launch_bounds__(kThreads)
+count_plane_kernel(int64_t n, const int32_t *__restrict__ grp, const int32_t *__restrict__ key,
+                   int lines, int len, int8_t *__restrict__ plane, int lines_pad) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const int g = grp[i], k = key[i];
+    if ((unsigned)g < (unsigned)lines && (unsigned)k < (unsigned)len)
+        plane[res_offset(g, k, lines_pad)] = 1;
+}
+
+hipError_t launch_count_planes(const tcu_relation &R, int lines, int len, int8_t *plane,
+                               int lines_pad, int len_pad, hipStream_t s) {
+    if (lines_pad < lines || len_pad < len || lines_pad % 64 || len_pad % 64)
+        return hipErrorInvalidValue;
+    // zeroed by a kernel, not a memset node (the call may be captured)
+    hipError_t e = launch_zero_f64(reinterpret_cast<double *>(plane),
+                                   (size_t)lines_pad * len_pad / 8, s);
+    if (e != hipSuccess || R.n == 0) return e;
+    count_plane_kernel<<<(unsigned)((R.n + kThreads - 1) / kThreads), kThreads, 0, s>>>(
+        R.n, R.group, R.key, lines, len, plane, lines_pad);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_product(int m, int n, int k, const int8_t *qa, int a_lines_pad,
+                                const int8_t *qb, int b_lines_pad, int len_pad, int32_t *count,
+                                int64_t ldc, hipStream_t s) {
+    if (m == 0 || n == 0) return hipSuccess;
+    if (a_lines_pad % CrtCfg::BM || b_lines_pad % CrtCfg::BN || len_pad % kCrtLenAlign ||
+        len_pad < k || a_lines_pad < m || b_lines_pad < n)
+        return hipErrorInvalidValue;
+    const CrtConsts cc = make_consts(1, 0);
+    const int tiles_m = (m + CrtCfg::BM - 1) / CrtCfg::BM, tiles_n = (n + CrtCfg::BN - 1) / CrtCfg::BN;
+    using G = CrtCfg;
+    const CertArgs none{};
+    TraceScope ts(TCU_KERNEL_COUNT, m, n, k, 1, 2.0 * m * n * (double)k, s);
+    gemm_crt_kernel<G, false, kEpiCount><<<(unsigned)(tiles_m * tiles_n), G::threads, 0, s>>>(
+        m, n, len_pad / 32, tiles_m, tiles_n, qa, a_lines_pad, qb, b_lines_pad,
+        (int64_t)a_lines_pad * len_pad, (int64_t)b_lines_pad * len_pad, cc, nullptr, 0, none,
+        count, ldc);
     return hipGetLastError();
 }
 

@@ -35,6 +35,22 @@ __global__ void zero_status_kernel(StatusBlock *st, uint32_t slices) {
     w[threadIdx.x] = threadIdx.x == 1 ? slices : 0u;  // 64 threads x 4 bytes; word 1 = slices
 }
 
+// The plan words of the status block before a mixed-form product's
+// certificate: needs and normalised-sum maxima to zero.
+__global__ void reset_plan_kernel(StatusBlock *st) {
+    st->need_bits = 0;
+    st->need_slices = 0;
+    st->umax_a = 0;
+    st->umax_b = 0;
+}
+
+// The plan a mixed-form product ran with (slices = 0: FP64 fallback).
+__global__ void set_plan_kernel(StatusBlock *st, uint32_t slices, uint32_t bits, int fallback) {
+    st->slices = slices;
+    st->bits = bits;
+    if (fallback) st->flags |= kFlagFallback;
+}
+
 // Counts this wave's invalid records and adds them to the status block once
 // (st == nullptr: a repeated pass whose skips were already counted).
 __device__ inline void report_skips(bool bad, StatusBlock *st, int which) {
@@ -89,10 +105,17 @@ gather_kernel(int64_t n, const int32_t *__restrict__ grp, const int32_t *__restr
 }
 
 __global__ void __launch_bounds__(kThreads)
-f64_to_i32_kernel(const double *__restrict__ src, int32_t *__restrict__ dst, size_t n) {
+f64_to_i32_kernel(const double *__restrict__ src, int32_t *__restrict__ dst, size_t n,
+                  StatusBlock *st) {
     const size_t stride = (size_t)gridDim.x * kThreads;
-    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride)
-        dst[i] = (int32_t)src[i];
+    bool over = false;
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) {
+        const double v = src[i];
+        const bool big = !(v <= 2147483647.0);
+        over |= big;
+        dst[i] = big ? 2147483647 : (int32_t)v;
+    }
+    if (__ballot(over) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&st->flags, kFlagCountRange);
 }
 
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
@@ -117,10 +140,24 @@ hipError_t launch_clear_status(StatusBlock *st, hipStream_t s, uint32_t slices) 
     return hipGetLastError();
 }
 
+hipError_t launch_reset_plan(StatusBlock *st, hipStream_t s) {
+    reset_plan_kernel<<<1, 1, 0, s>>>(st);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_plan(StatusBlock *st, uint32_t slices, uint32_t bits, bool fallback,
+                           hipStream_t s) {
+    set_plan_kernel<<<1, 1, 0, s>>>(st, slices, bits, fallback ? 1 : 0);
+    return hipGetLastError();
+}
+
 hipError_t launch_encode(const tcu_relation &R, int transpose, int rows, int cols, double *out,
                          StatusBlock *st, int which, hipStream_t s) {
     if (R.n == 0) return hipSuccess;
     const unsigned grid = grid_for(R.n);
+    // algorithmic bytes: the record (group, key, value) in, one 8-byte cell out
+    const double vbytes = R.val == nullptr ? 0.0 : (R.dtype == TCU_F32 ? 4.0 : 8.0);
+    TraceScope ts(TCU_KERNEL_ENCODE, rows, cols, 0, 1, (double)R.n * (16.0 + vbytes), s);
     const bool unique = (R.flags & TCU_REL_UNIQUE_CELLS) != 0;
     const float *vf = static_cast<const float *>(R.val);
     const double *vd = static_cast<const double *>(R.val);
@@ -150,14 +187,17 @@ hipError_t launch_gather(const tcu_relation &R, int transpose, int rows, int col
                          const double *src, double *dst, hipStream_t s, int r0, int r1) {
     if (R.n == 0) return hipSuccess;
     if (r1 < 0) r1 = rows;
+    // algorithmic bytes: group and key in, one 8-byte cell in, 8 bytes out
+    TraceScope ts(TCU_KERNEL_GATHER, rows, cols, 0, 1, (double)R.n * 24.0, s);
     gather_kernel<<<grid_for(R.n), kThreads, 0, s>>>(R.n, R.group, R.key, transpose, rows, cols,
                                                      r0, r1, src, dst);
     return hipGetLastError();
 }
 
-hipError_t launch_f64_to_i32(const double *src, int32_t *dst, size_t n, hipStream_t s) {
+hipError_t launch_f64_to_i32(const double *src, int32_t *dst, size_t n, StatusBlock *st,
+                             hipStream_t s) {
     if (n == 0) return hipSuccess;
-    f64_to_i32_kernel<<<capped_grid(n), kThreads, 0, s>>>(src, dst, n);
+    f64_to_i32_kernel<<<capped_grid(n), kThreads, 0, s>>>(src, dst, n, st);
     return hipGetLastError();
 }
 

@@ -33,6 +33,8 @@
 //    main loop whose address arithmetic is all scalar (see the whole-tile
 //    path below): busy matrix cores leave vector-ALU instructions few issue
 //    slots.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace tcu {
@@ -239,9 +241,19 @@ template <bool A_KC, bool B_KC, bool FULL>
 __global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
 gemm_f64_kernel(int m, int n, int k, const double *__restrict__ A, int64_t lda,
                 const double *__restrict__ B, int64_t ldb, double *__restrict__ C, int64_t ldc,
-                int vec_a, int vec_b, int accumulate) {
+                int vec_a, int vec_b, int accumulate, int kc = 0, int64_t cstride = 0) {
     __shared__ __attribute__((aligned(16))) double lds_a[2][Tile<A_KC>::elems];
     __shared__ __attribute__((aligned(16))) double lds_b[2][Tile<B_KC>::elems];
+
+    // split contraction (kc > 0): workgroup row y of the grid multiplies the
+    // chunk [y kc, (y + 1) kc) of k into its own partial product at C + y cstride
+    if (kc > 0) {
+        const int k0 = (int)blockIdx.y * kc;
+        A += A_KC ? (int64_t)k0 : (int64_t)k0 * lda;
+        B += B_KC ? (int64_t)k0 : (int64_t)k0 * ldb;
+        C += (int64_t)blockIdx.y * cstride;
+        k = min(kc, k - k0);
+    }
 
     const int tiles_m = (m + BM - 1) / BM, tiles_n = (n + BN - 1) / BN;
     int tm, tn;
@@ -354,21 +366,95 @@ hipError_t launch(int m, int n, int k, const double *A, int64_t lda, const doubl
         // the whole 16-deep stages of k on the whole-tile path; a last
         // partial stage (k % 16 terms) is added to C by a guarded launch
         const int kf = k / BK * BK;
-        gemm_f64_kernel<A_KC, B_KC, true><<<tiles, THREADS, 0, s>>>(m, n, kf, A, lda, B, ldb, C,
-                                                                    ldc, vec_a, vec_b, accumulate);
+        {
+            TraceScope ts(TCU_KERNEL_GEMM_F64, m, n, kf, 1, 2.0 * m * n * (double)kf, s);
+            gemm_f64_kernel<A_KC, B_KC, true><<<tiles, THREADS, 0, s>>>(
+                m, n, kf, A, lda, B, ldb, C, ldc, vec_a, vec_b, accumulate);
+        }
         if (kf < k) {
             const double *At = A_KC ? A + kf : A + (int64_t)kf * lda;
             const double *Bt = B_KC ? B + kf : B + (int64_t)kf * ldb;
+            TraceScope ts(TCU_KERNEL_GEMM_F64, m, n, k - kf, 1, 2.0 * m * n * (double)(k - kf), s);
             gemm_f64_kernel<A_KC, B_KC, false><<<tiles, THREADS, 0, s>>>(
                 m, n, k - kf, At, lda, Bt, ldb, C, ldc, vec_a, vec_b, 1);
         }
-    } else
+    } else {
+        TraceScope ts(TCU_KERNEL_GEMM_F64, m, n, k, 1, 2.0 * m * n * (double)k, s);
         gemm_f64_kernel<A_KC, B_KC, false><<<tiles, THREADS, 0, s>>>(m, n, k, A, lda, B, ldb, C,
                                                                      ldc, vec_a, vec_b, accumulate);
+    }
+    return hipGetLastError();
+}
+
+// The split contraction's partial products summed in chunk order:
+// C[i, j] = sum_p part[p][i * n + j], the same order on every run.
+__global__ void __launch_bounds__(THREADS)
+sum_partials_kernel(int m, int n, int parts, const double *__restrict__ part,
+                    double *__restrict__ C, int64_t ldc) {
+    const int64_t i = (int64_t)blockIdx.x * THREADS + threadIdx.x;
+    const int64_t mn = (int64_t)m * n;
+    if (i >= mn) return;
+    double s = 0.0;
+    for (int p = 0; p < parts; ++p) s += part[p * mn + i];
+    C[(i / n) * ldc + i % n] = s;
+}
+
+// Chunks of the split contraction: enough workgroups for two rounds of the
+// chip when the output alone has few tiles, each chunk at least 256 deep.
+// 0: no split.
+int split_parts(int m, int n, int k) {
+    const int64_t tiles = (int64_t)((m + BM - 1) / BM) * ((n + BN - 1) / BN);
+    if (tiles >= 128 || k < 1024) return 0;
+    int64_t parts = (512 + tiles - 1) / tiles;
+    parts = std::min<int64_t>(parts, k / 256);
+    return parts >= 2 ? (int)parts : 0;
+}
+
+int split_chunk(int k, int parts) { return ((k + parts - 1) / parts + BK - 1) / BK * BK; }
+
+template <bool A_KC, bool B_KC>
+hipError_t launch_split(int m, int n, int k, const double *A, int64_t lda, const double *B,
+                        int64_t ldb, double *C, int64_t ldc, double *part, int parts,
+                        hipStream_t s) {
+    const int kc = split_chunk(k, parts);
+    const int used = (k + kc - 1) / kc;  // chunks that hold part of k
+    const int tiles = ((m + BM - 1) / BM) * ((n + BN - 1) / BN);
+    const int vec_a = (lda % 2 == 0) && (((uintptr_t)A & 15) == 0);
+    const int vec_b = (ldb % 2 == 0) && (((uintptr_t)B & 15) == 0);
+    {
+        TraceScope ts(TCU_KERNEL_GEMM_F64, m, n, k, used, 2.0 * m * n * (double)k, s);
+        gemm_f64_kernel<A_KC, B_KC, false><<<dim3(tiles, used), THREADS, 0, s>>>(
+            m, n, k, A, lda, B, ldb, part, n, vec_a, vec_b, 0, kc, (int64_t)m * n);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t mn = (int64_t)m * n;
+    sum_partials_kernel<<<(unsigned)((mn + THREADS - 1) / THREADS), THREADS, 0, s>>>(
+        m, n, used, part, C, ldc);
     return hipGetLastError();
 }
 
 }  // namespace
+
+size_t gemm_f64_split_bytes(int m, int n, int k) {
+    const int parts = split_parts(m, n, k);
+    return parts == 0 ? 0 : (size_t)parts * (size_t)m * (size_t)n * sizeof(double);
+}
+
+hipError_t launch_gemm_f64_split(int trans_a, int trans_b, int m, int n, int k, const double *A,
+                                 int64_t lda, const double *B, int64_t ldb, double *C,
+                                 int64_t ldc, double *part, hipStream_t s) {
+    const int parts = split_parts(m, n, k);
+    if (parts == 0 || part == nullptr)
+        return launch_gemm_f64(trans_a, trans_b, m, n, k, A, lda, B, ldb, C, ldc, s);
+    if (!trans_a && !trans_b)
+        return launch_split<true, false>(m, n, k, A, lda, B, ldb, C, ldc, part, parts, s);
+    if (!trans_a && trans_b)
+        return launch_split<true, true>(m, n, k, A, lda, B, ldb, C, ldc, part, parts, s);
+    if (trans_a && !trans_b)
+        return launch_split<false, false>(m, n, k, A, lda, B, ldb, C, ldc, part, parts, s);
+    return launch_split<false, true>(m, n, k, A, lda, B, ldb, C, ldc, part, parts, s);
+}
 
 int gemm_f64_row_cut(int m, int n) {
     int dev = 0, cus = 0;

@@ -391,6 +391,10 @@ hipError_t launch_s(int m, int n, int nblk, const void *xs, int x_lines_pad, con
     const int chunk = Mfma<T>::kSum ? nblk : flush;
     for (int kb0 = 0; kb0 < nblk; kb0 += chunk) {
         const int kb1 = kb0 + chunk < nblk ? kb0 + chunk : nblk;
+        const int kstep = 32 / (int)sizeof(T);
+        const double kk = (double)(kb1 - kb0) * kstep;
+        TraceScope ts(TCU_KERNEL_GEMM_SPLIT, m, n, (int)kk, S, S * (S + 1) / 2 * 2.0 * m * n * kk,
+                      s);
         gemm_split_kernel<T, S><<<tiles, split_threads<T>(), 0, s>>>(
             m, n, nblk, kb0, kb1, flush, kb0 > 0, static_cast<const char *>(xs), x_lines_pad,
             static_cast<const char *>(ys), y_lines_pad, ex, ey, C, ldc);

@@ -12,31 +12,83 @@ namespace tcu {
 
 // Workspace status block (first 256 bytes of every workspace).
 struct StatusBlock {
-    uint32_t flags;                 // bit 0: out-of-range record, bit 1: non-finite
-    uint32_t slices;                // mixed form: slice count used
+    uint32_t flags;                 // kFlag* bits
+    uint32_t slices;                // mixed form: slices or moduli of the last product (0: FP64)
     unsigned long long skipped_a;   // records of A skipped
     unsigned long long skipped_b;   // records of B skipped
-    int32_t exp_lo, exp_hi;         // mixed form: exponent range seen by the stats pass
-    uint32_t pad[56];
+    uint32_t bits;                  // residue form: truncation width of the last product
+    uint32_t need_bits;             // certificate: largest per-cell truncation width needed
+    uint32_t need_slices;           // certificate: largest per-cell digit count needed
+    uint32_t pad0;
+    unsigned long long umax_a;      // bit pattern of max over lines of sum|z| 2^-e, operand A
+    unsigned long long umax_b;      // the same for operand B
+    uint32_t pad[50];
 };
 static_assert(sizeof(StatusBlock) == 256, "status block must be 256 bytes");
 
 constexpr uint32_t kFlagKeyRange = 1u;
 constexpr uint32_t kFlagNonFinite = 2u;
+constexpr uint32_t kFlagFallback = 4u;   // a mixed-form product ran in FP64 (no certified plan)
+constexpr uint32_t kFlagCountRange = 8u; // a pair count exceeded INT32_MAX
+constexpr uint32_t kNeedUncertified = 255u;  // a cell the certificate cannot bound
 constexpr size_t kAlign = 256;
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Launch records of the matrix-core product kernels (tcu_trace_launches):
+// the calling thread's buffer, or none.  A TraceScope around one launch
+// records the begin event before it and the end event after it, on the
+// launch's stream.
+struct LaunchTrace {
+    tcu_launch_record *rec = nullptr;
+    int32_t cap = 0;
+    int32_t *count = nullptr;
+};
+LaunchTrace &launch_trace();
+
+class TraceScope {
+  public:
+    TraceScope(int kernel, int m, int n, int k, int planes, double ops, hipStream_t s) : s_(s) {
+        LaunchTrace &t = launch_trace();
+        if (t.count == nullptr) return;
+        const int32_t i = (*t.count)++;
+        if (t.rec == nullptr || i >= t.cap) return;
+        r_ = &t.rec[i];
+        r_->kernel = kernel;
+        r_->m = m;
+        r_->n = n;
+        r_->k = k;
+        r_->planes = planes;
+        r_->ops = ops;
+        (void)hipEventRecord(r_->begin, s_);
+    }
+    ~TraceScope() {
+        if (r_ != nullptr) (void)hipEventRecord(r_->end, s_);
+    }
+    TraceScope(const TraceScope &) = delete;
+    TraceScope &operator=(const TraceScope &) = delete;
+
+  private:
+    tcu_launch_record *r_ = nullptr;
+    hipStream_t s_;
+};
 
 // api.hip: the body of tcu_join_agg_fwd on a given workspace, and the
 // workspace bytes it needs (0 for invalid shapes or precision).
 tcu_status join_agg_fwd_ws(const tcu_relation *A, const tcu_relation *B, int32_t M, int32_t K,
                            int32_t N, tcu_precision p, double tol, double *C, int32_t *count,
                            void *ws, size_t ws_bytes, hipStream_t stream);
-size_t join_agg_fwd_ws_bytes(int32_t M, int32_t K, int32_t N, tcu_precision p);
+size_t join_agg_fwd_ws_bytes(const tcu_relation *A, const tcu_relation *B, int32_t M,
+                             int32_t K, int32_t N, tcu_precision p, bool with_count);
 
 // encode.hip
 hipError_t launch_zero_f64(double *p, size_t n, hipStream_t s);
 hipError_t launch_clear_status(StatusBlock *st, hipStream_t s, uint32_t slices = 0);
+// status words of a mixed-form product: cleared before its certificate, and
+// the plan it ran with (slices = 0 and the fallback flag: FP64)
+hipError_t launch_reset_plan(StatusBlock *st, hipStream_t s);
+hipError_t launch_set_plan(StatusBlock *st, uint32_t slices, uint32_t bits, bool fallback,
+                           hipStream_t s);
 hipError_t launch_encode(const tcu_relation &R, int transpose, int rows, int cols, double *out,
                          StatusBlock *st, int which, hipStream_t s);
 // dst[i] = src[row_i, col_i] for the records whose row lies in [r0, r1)
@@ -45,12 +97,22 @@ hipError_t launch_encode(const tcu_relation &R, int transpose, int rows, int col
 hipError_t launch_gather(const tcu_relation &R, int transpose, int rows, int cols,
                          const double *src, double *dst, hipStream_t s, int r0 = 0,
                          int r1 = -1);
-hipError_t launch_f64_to_i32(const double *src, int32_t *dst, size_t n, hipStream_t s);
+// counts held in FP64 to int32; values above INT32_MAX are stored as
+// INT32_MAX and set kFlagCountRange
+hipError_t launch_f64_to_i32(const double *src, int32_t *dst, size_t n, StatusBlock *st,
+                             hipStream_t s);
 
 // split.hip: per-line max |z| (axis 0: rows, 1: columns) into maxbits (bit
-// patterns of non-negative doubles), and the digit slices of Z.
+// patterns of non-negative doubles), the sums of |z| (sums may be NULL), and
+// the digit slices of Z.  Row sums land in sums[row]; column sums in
+// col_sum_parts(rows) partial sums sums[part * cols + col], which
+// line_abs_sum adds in order (sums then holds kColParts * cols doubles).
+constexpr int kColParts = 32;
+int col_sum_chunk(int rows);
+int col_sum_parts(int rows);
 hipError_t launch_line_max(const double *Z, int rows, int cols, int64_t ld, int axis,
-                           unsigned long long *maxbits, StatusBlock *st, hipStream_t s);
+                           unsigned long long *maxbits, double *sums, StatusBlock *st,
+                           hipStream_t s);
 // Lines are rows (axis 0, lines_pad >= rows, len_pad >= cols) or columns
 // (axis 1, lines_pad >= cols, len_pad >= rows); lines_pad % 128 == 0,
 // len_pad % 64 == 0.  Layout: slices[p][t / KSTEP][(t % KSTEP) / HALF][line][t % HALF]
@@ -74,6 +136,14 @@ int split_chunk_steps(int S, int digit_bf16);
 hipError_t launch_gemm_f64(int trans_a, int trans_b, int m, int n, int k, const double *A,
                            int64_t lda, const double *B, int64_t ldb, double *C, int64_t ldc,
                            hipStream_t s, int accumulate = 0);
+// The same product with the contraction split into chunks whose partial
+// products go to `part` and are summed in chunk order, when the output has
+// too few tiles to fill the chip (gemm_f64_split_bytes > 0); otherwise (or
+// part == NULL) launch_gemm_f64.  part: gemm_f64_split_bytes(m, n, k) bytes.
+size_t gemm_f64_split_bytes(int m, int n, int k);
+hipError_t launch_gemm_f64_split(int trans_a, int trans_b, int m, int n, int k, const double *A,
+                                 int64_t lda, const double *B, int64_t ldb, double *C,
+                                 int64_t ldc, double *part, hipStream_t s);
 // Rows m1 (a multiple of the tile height, 0 < m1 < m) at which an m x n FP64
 // product can be cut into two launches that together take no more rounds of
 // concurrently resident workgroups than one launch; 0 when no such cut exists
@@ -123,6 +193,33 @@ hipError_t launch_mfma_peak(int kind, int iters, void *out, hipStream_t s);
 // multiple of 256; the GEMM writes per-modulus residues of the product into
 // res (L planes of crt_residue_plane(m, n) int8) and reconstructs C (m x n,
 // ldc) from them.
+// The certificate of a mixed-form product (crt.hip): magnitude planes of
+// both operands (int8, the residue layout; lines_pad a multiple of 256,
+// len_pad of crt_len_align()) with their lines' normalised sums of |z|, then
+// one int8 GEMM whose epilogue folds every cell's needs into need_bits
+// (residue form: truncation width) and need_slices (digit forms: digits).
+struct CertArgs {
+    const double *sx, *sy;  // normalised sums of the lines of A and B (rounded up)
+    double tcrt;            // residue form: tolerance left for the truncation
+    double kterm;           // 2^14 K
+    double tdig[TCU_MAX_SLICES + 1];  // digit forms: tolerance left, per digit count
+    uint32_t *need_bits, *need_slices;
+};
+hipError_t launch_mag_plane(const double *Z, int rows, int cols, int64_t ld, int axis,
+                            const unsigned long long *maxbits, const double *sums, double *shat,
+                            unsigned long long *umax, int8_t *out, int lines_pad, int len_pad,
+                            hipStream_t s);
+hipError_t launch_certify(int m, int n, int k, const int8_t *qa, int a_lines_pad,
+                          const int8_t *qb, int b_lines_pad, int len_pad, const CertArgs &ca,
+                          hipStream_t s);
+// The count path (crt.hip): the 0/1 plane of a relation with unique cells
+// (line = group, position = key; the rest zero), then one int8 product with
+// exact int32 sums written to count (m x n, leading dimension ldc).
+hipError_t launch_count_planes(const tcu_relation &R, int lines, int len, int8_t *plane,
+                               int lines_pad, int len_pad, hipStream_t s);
+hipError_t launch_count_product(int m, int n, int k, const int8_t *qa, int a_lines_pad,
+                                const int8_t *qb, int b_lines_pad, int len_pad, int32_t *count,
+                                int64_t ldc, hipStream_t s);
 double crt_modulus_bits(int L);
 int crt_max_moduli();
 int64_t crt_residue_plane(int64_t m, int64_t n);

@@ -65,7 +65,7 @@ tcu_status tcu_join_agg_fwd_noalloc(const tcu_relation *A, const tcu_relation *B
                                     int32_t K, int32_t N, tcu_precision p, double tol, double *C,
                                     int32_t *count, void *status, hipStream_t stream) {
     if (status != nullptr && ((uintptr_t)status % tcu::kAlign) != 0) return TCU_ERR_ARG;
-    const size_t need = tcu::join_agg_fwd_ws_bytes(M, K, N, p);
+    const size_t need = tcu::join_agg_fwd_ws_bytes(A, B, M, K, N, p, count != nullptr);
     if (need == 0) return TCU_ERR_ARG;
     if (need > tcu::kScratchBytes) return TCU_ERR_WORKSPACE;
     void *ws = nullptr;

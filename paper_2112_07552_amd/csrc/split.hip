@@ -42,10 +42,13 @@ __device__ inline unsigned long long abs_bits(double z) {
     return (unsigned long long)__double_as_longlong(fabs(z));
 }
 
-// Max |z| per row: one wave per row.
+// Max |z| and sum of |z| per row: one wave per row.  Each lane adds its
+// columns in a fixed order and lane 0 combines the lanes in a fixed order,
+// so the sum is the same on every run.
 __global__ void __launch_bounds__(kThreads)
 row_max_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
-               unsigned long long *__restrict__ maxbits, StatusBlock *st) {
+               unsigned long long *__restrict__ maxbits, double *__restrict__ sums,
+               StatusBlock *st) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int row = blockIdx.x * (kThreads / 64) + wave;
     if (row >= rows) return;
@@ -53,6 +56,7 @@ row_max_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
     // eight independent loads in flight per lane (the loop is latency-bound
     // with one)
     double m[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     bool bad = false;
     int c = lane;
     for (; c + 7 * 64 < cols; c += 8 * 64) {
@@ -63,38 +67,47 @@ row_max_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
         for (int u = 0; u < 8; ++u) {
             bad |= !isfinite(v[u]);
             m[u] = fmax(m[u], fabs(v[u]));
+            a[u] += fabs(v[u]);
         }
     }
     for (; c < cols; c += 64) {
         const double v = z[c];
         bad |= !isfinite(v);
         m[0] = fmax(m[0], fabs(v));
+        a[0] += fabs(v);
     }
     double mx = fmax(fmax(fmax(m[0], m[1]), fmax(m[2], m[3])), fmax(fmax(m[4], m[5]), fmax(m[6], m[7])));
+    double sm = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    // lane 0 ends with the same association of the 64 lane sums on every run
+    for (int off = 32; off > 0; off >>= 1) sm += __shfl_down(sm, off);
     const unsigned long long anybad = __ballot(bad);
     if (lane == 0) {
         maxbits[row] = abs_bits(mx);
+        if (sums != nullptr) sums[row] = sm;
         if (anybad) atomicOr(&st->flags, kFlagNonFinite);
     }
 }
 
-// Max |z| per column: threads own columns, blocks own chunks of rows, and the
-// partial maxima meet in an atomic max on the (monotone) bit patterns of the
-// non-negative doubles.  maxbits must be zero beforehand.
-constexpr int kColChunk = 64;
-
+// Max |z| and sum of |z| per column: threads own columns, blocks own chunks
+// of rows.  The partial maxima meet in an atomic max on the (monotone) bit
+// patterns of the non-negative doubles (maxbits must be zero beforehand);
+// the partial sums of chunk y go to sums[y * cols + col], and
+// col_sum_parts(rows) chunks are later added in order (line_abs_sum), so the
+// column sums do not depend on the order in which blocks run.
 __global__ void __launch_bounds__(kThreads)
-col_max_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
-               unsigned long long *__restrict__ maxbits, StatusBlock *st) {
+col_max_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld, int chunk,
+               unsigned long long *__restrict__ maxbits, double *__restrict__ sums,
+               StatusBlock *st) {
     const int col = blockIdx.x * kThreads + threadIdx.x;
-    const int r0 = blockIdx.y * kColChunk;
-    const int r1 = min(rows, r0 + kColChunk);
+    const int r0 = blockIdx.y * chunk;
+    const int r1 = min(rows, r0 + chunk);
     double mx = 0.0;
     bool bad = false;
     if (col < cols) {
         // eight independent loads in flight per thread
         double m[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         const double *z = Z + col;
         int r = r0;
         int64_t off = (int64_t)r0 * ld;  // element offset of row r (a running sum)
@@ -107,15 +120,20 @@ col_max_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
             for (int u = 0; u < 8; ++u) {
                 bad |= !isfinite(v[u]);
                 m[u] = fmax(m[u], fabs(v[u]));
+                a[u] += fabs(v[u]);
             }
         }
         for (; r < r1; ++r, off += ld) {
             const double v = z[off];
             bad |= !isfinite(v);
             m[0] = fmax(m[0], fabs(v));
+            a[0] += fabs(v);
         }
         mx = fmax(fmax(fmax(m[0], m[1]), fmax(m[2], m[3])), fmax(fmax(m[4], m[5]), fmax(m[6], m[7])));
         atomicMax(maxbits + col, abs_bits(mx));
+        if (sums != nullptr)
+            sums[(int64_t)blockIdx.y * cols + col] =
+                ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     }
     const unsigned long long anybad = __ballot(bad);
     if (anybad && (threadIdx.x & 63) == 0) atomicOr(&st->flags, kFlagNonFinite);
@@ -330,18 +348,28 @@ hipError_t launch_split_t(const double *Z, int rows, int cols, int64_t ld, int a
 
 }  // namespace
 
+int col_sum_parts(int rows) { return (rows + col_sum_chunk(rows) - 1) / col_sum_chunk(rows); }
+
+int col_sum_chunk(int rows) {
+    // at most kColParts chunks, at least 64 rows each, a multiple of 8 rows
+    const int c = (rows + kColParts - 1) / kColParts;
+    return c < 64 ? 64 : (c + 7) / 8 * 8;
+}
+
 hipError_t launch_line_max(const double *Z, int rows, int cols, int64_t ld, int axis,
-                           unsigned long long *maxbits, StatusBlock *st, hipStream_t s) {
+                           unsigned long long *maxbits, double *sums, StatusBlock *st,
+                           hipStream_t s) {
     if (rows == 0 || cols == 0) return hipSuccess;
     if (axis == 0) {
         const unsigned grid = (unsigned)((rows + 3) / 4);
-        row_max_kernel<<<grid, kThreads, 0, s>>>(Z, rows, cols, ld, maxbits, st);
+        row_max_kernel<<<grid, kThreads, 0, s>>>(Z, rows, cols, ld, maxbits, sums, st);
     } else {
         // zero the maxima with a kernel (the bit pattern of +0.0 is all zeros)
         hipError_t e = launch_zero_f64(reinterpret_cast<double *>(maxbits), (size_t)cols, s);
         if (e != hipSuccess) return e;
-        dim3 grid((cols + kThreads - 1) / kThreads, (rows + kColChunk - 1) / kColChunk);
-        col_max_kernel<<<grid, kThreads, 0, s>>>(Z, rows, cols, ld, maxbits, st);
+        const int chunk = col_sum_chunk(rows);
+        dim3 grid((cols + kThreads - 1) / kThreads, (rows + chunk - 1) / chunk);
+        col_max_kernel<<<grid, kThreads, 0, s>>>(Z, rows, cols, ld, chunk, maxbits, sums, st);
     }
     return hipGetLastError();
 }

@@ -40,6 +40,16 @@ def _need_cuda(t: torch.Tensor, name: str, dtypes) -> None:
         raise ValueError(f"{name} must be contiguous")
 
 
+def _need_out(out: torch.Tensor, shape, device) -> None:
+    """A caller-supplied output must have exactly the shape the library
+    writes (it writes every element of that shape), on the inputs' device."""
+    _need_cuda(out, "out", (torch.float64,))
+    if tuple(out.shape) != tuple(shape):
+        raise ValueError(f"out must have shape {tuple(shape)}, got {tuple(out.shape)}")
+    if out.device != torch.device(device):
+        raise ValueError(f"out must be on {device}, got {out.device}")
+
+
 def make_relation(group: torch.Tensor, key: torch.Tensor, val: Optional[torch.Tensor],
                   unique: bool = False):
     """tcu_relation for one relation.  unique=True declares that no two
@@ -80,23 +90,17 @@ def alloc_workspace(nbytes: int, device) -> torch.Tensor:
     return ws
 
 
-def split_slices(precision: str, k: int, tol: float) -> int:
-    """Step a0 host plan: slice count for a contraction of length k (raises
-    TcuError with TCU_ERR_INFEASIBLE when no slice count meets tol)."""
-    S = _lib.load().tcu_split_slices(PRECISIONS[precision], int(k), float(tol))
-    if S < 0:
-        raise TcuError(S, "tcu_split_slices")
-    return S
-
-
-def crt_plan(k: int, tol: float):
-    """The CRT form's plan for a contraction of length k: (number of moduli,
-    truncation bits); raises TcuError (TCU_ERR_INFEASIBLE) when none meets tol."""
+def mixed_plan(precision: str, k: int, tol: float, need: int, u: float):
+    """Step a0 host plan of one mixed-form product from its certificate (the
+    largest per-cell need and the bound u on the normalised line sums):
+    (slice or modulus count, truncation bits or 0); raises TcuError
+    (TCU_ERR_INFEASIBLE) when no plan exists."""
     bits = C.c_int32(0)
-    L = _lib.load().tcu_crt_plan(int(k), float(tol), C.byref(bits))
-    if L < 0:
-        raise TcuError(L, "tcu_crt_plan")
-    return L, bits.value
+    r = _lib.load().tcu_mixed_plan(PRECISIONS[precision], int(k), float(tol), int(need),
+                                   float(u), C.byref(bits))
+    if r < 0:
+        raise TcuError(r, "tcu_mixed_plan")
+    return r, bits.value
 
 
 def _pad(x: int, m: int) -> int:
@@ -143,7 +147,7 @@ def encode(group, key, val, rows: int, cols: int, transpose: bool = False,
     dev = group.device
     if out is None:
         out = torch.empty((rows, cols), dtype=torch.float64, device=dev)
-    _need_cuda(out, "out", (torch.float64,))
+    _need_out(out, (rows, cols), dev)
     if ws is None:
         ws = alloc_workspace(256, dev)
     check(_lib.load().tcu_encode(C.byref(rel), int(transpose), rows, cols, _ptr(out), _ptr(ws),
@@ -160,12 +164,22 @@ def gemm_f64(A: torch.Tensor, B: torch.Tensor, trans_a: bool = False, trans_b: b
     kb, n = (B.shape[1], B.shape[0]) if trans_b else (B.shape[0], B.shape[1])
     if k != kb:
         raise ValueError(f"inner dimensions differ: {k} vs {kb}")
+    if B.device != A.device:
+        raise ValueError("A and B must be on one device")
     if out is None:
         out = torch.empty((m, n), dtype=torch.float64, device=A.device)
-    _need_cuda(out, "out", (torch.float64,))
-    check(_lib.load().tcu_gemm_f64(int(trans_a), int(trans_b), m, n, k, _ptr(A), A.shape[1],
-                                   _ptr(B), B.shape[1], _ptr(out), n, _stream(A.device)),
-          "tcu_gemm_f64")
+    _need_out(out, (m, n), A.device)
+    L = _lib.load()
+    nb = int(L.tcu_gemm_f64_workspace_bytes(m, n, k)) if m and n and k else 0
+    if nb > 0:
+        # few output tiles: the contraction is split over workgroups
+        ws = alloc_workspace(nb, A.device)
+        check(L.tcu_gemm_f64_ws(int(trans_a), int(trans_b), m, n, k, _ptr(A), A.shape[1],
+                                _ptr(B), B.shape[1], _ptr(out), n, _ptr(ws), ws.numel(),
+                                _stream(A.device)), "tcu_gemm_f64_ws")
+        return out
+    check(L.tcu_gemm_f64(int(trans_a), int(trans_b), m, n, k, _ptr(A), A.shape[1],
+                         _ptr(B), B.shape[1], _ptr(out), n, _stream(A.device)), "tcu_gemm_f64")
     return out
 
 
@@ -247,7 +261,8 @@ def sync_status(ws: torch.Tensor) -> Tuple[int, dict]:
     info = _lib.tcu_status_info()
     st = _lib.load().tcu_sync_status(_ptr(ws), _stream(ws.device), C.byref(info))
     return st, {"flags": info.flags, "slices": info.slices,
-                "skipped_a": info.skipped_a, "skipped_b": info.skipped_b}
+                "skipped_a": info.skipped_a, "skipped_b": info.skipped_b,
+                "bits": info.bits, "need": info.need}
 
 
 def _checkpoint_needed(M: int, K: int, N: int, device) -> bool:
@@ -309,7 +324,7 @@ def join_agg_bsr(a_group, a_key, a_val, b_key, b_group, b_val, M: int, K: int, N
 
 def block_sparse_preferred(a_group, a_key, a_val, b_key, b_group, b_val, M: int, K: int,
                            N: int) -> bool:
-    """The library's cost-model choice (Sections 4.2.4, 4.3): True when the
+    """The library's cost-model choice (Sections 4.2.4, 4.2.2): True when the
     block-sparse operator is predicted faster than the dense FP64 one."""
     A = make_relation(a_group, a_key, a_val)
     B = make_relation(b_group, b_key, b_val)

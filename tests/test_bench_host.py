@@ -17,7 +17,7 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     msg = json.loads(r.stdout.strip().splitlines()[-1])
-    assert "single-GPU" in msg["error"]
+    assert "one GPU only" in msg["error"]
 
 
 def test_code_digest_ignores_comments_not_code(tmp_path):
@@ -31,19 +31,27 @@ def test_code_digest_ignores_comments_not_code(tmp_path):
 
 
 def test_counter_traffic_only_for_the_counted_code(tmp_path, monkeypatch):
-    src = tmp_path / "k.hip"
+    csrc = tmp_path / "paper_2112_07552_amd" / "csrc"
+    profiles = tmp_path / "profiles"
+    csrc.mkdir(parents=True)
+    profiles.mkdir()
+    src = csrc / "k.hip"
     src.write_text("__global__ void k() {}\n")
-    prof = tmp_path / "counters.md"
-    prof.write_text(f"figures\n\ntraffic: nn_bytes=123456 code_sha256={bench.code_digest(str(src))}\n")
-    monkeypatch.setattr(bench, "GEMM_SOURCE", str(src))
-    monkeypatch.setattr(bench, "COUNTERS_FILE", str(prof))
-    assert bench.counter_traffic() == 123456
+    (profiles / "counters.md").write_text(
+        f"figures\n\ntraffic: gemm=123456 code_sha256={bench.code_digest(str(src))}\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.counter_traffic("counters.md", "gemm", "k.hip") == 123456
+    assert bench.counter_traffic("counters.md", "other", "k.hip") is None
     src.write_text("__global__ void k() { int x = 0; }\n")   # the kernel changed
-    assert bench.counter_traffic() is None
-    monkeypatch.setattr(bench, "COUNTERS_FILE", str(tmp_path / "missing.md"))
-    assert bench.counter_traffic() is None
+    assert bench.counter_traffic("counters.md", "gemm", "k.hip") is None
+    assert bench.counter_traffic("missing.md", "gemm", "k.hip") is None
 
 
-def test_committed_counters_name_a_digest():
-    text = open(bench.COUNTERS_FILE).read()
-    assert "traffic: nn_bytes=" in text and "code_sha256=" in text
+def test_launch_stats_average_and_rate():
+    launches = [(2.0, 4e12, 8, 8, 8, 2), (4.0, 8e12, 8, 8, 8, 4)]
+    st = bench.launch_stats(launches, 1e12, "tops")
+    assert st["launches"] == 2 and st["avg_ms"] == 3.0
+    assert st["avg_ops_per_launch"] == 6e12
+    assert abs(st["achieved_tops"] - 12e12 / 6e-3 / 1e12) < 1e-9
+    assert st["shapes_m_n_k_planes"] == [[8, 8, 8, 2], [8, 8, 8, 4]]
+    assert bench.launch_stats([], 1e12, "tops") is None

@@ -168,6 +168,47 @@ def test_gemm_f64_odd_leading_dimensions(orc):
     assert err_cw(out[:, :n].cpu().numpy(), Co, S) <= TOL
 
 
+@pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("m,n,k", [(1, 32, 32768), (3, 200, 5000), (130, 129, 2000),
+                                   (1, 1, 1024)])
+def test_gemm_f64_split_contraction(orc, m, n, k, ta, tb):
+    """Outputs of few tiles split the contraction over workgroups (partial
+    products in a workspace, summed in chunk order): against the oracle, and
+    bit for bit the same on a second run."""
+    dev = cuda_or_skip()
+    L = ops._lib.load()
+    assert L.tcu_gemm_f64_workspace_bytes(m, n, k) > 0
+    g = torch.Generator(device="cpu").manual_seed(m * 31 + n + k + 10 * ta + tb)
+    X = (torch.rand((m, k), generator=g, dtype=torch.float64) * 2 - 1)
+    Y = (torch.rand((k, n), generator=g, dtype=torch.float64) * 2 - 1)
+    Ad = (X.t().contiguous() if ta else X).to(dev)
+    Bd = (Y.t().contiguous() if tb else Y).to(dev)
+    C1 = ops.gemm_f64(Ad, Bd, trans_a=bool(ta), trans_b=bool(tb))
+    C2 = ops.gemm_f64(Ad, Bd, trans_a=bool(ta), trans_b=bool(tb))
+    assert torch.equal(C1, C2)
+    RA = to_orc(orc, dense_relation_from_matrix(X, False))
+    RB = to_orc(orc, dense_relation_from_matrix(Y, True))
+    Co, _, _ = orc.join_agg(RA, RB, m, k, n)
+    S, _, _ = orc.join_agg(abs_rel(orc, RA), abs_rel(orc, RB), m, k, n)
+    assert err_cw(C1.cpu().numpy(), Co, S) <= TOL
+
+
+def test_gemm_f64_ws_refuses_a_short_workspace():
+    dev = cuda_or_skip()
+    L = ops._lib.load()
+    A = torch.ones((1, 4096), dtype=torch.float64, device=dev)
+    B = torch.ones((4096, 8), dtype=torch.float64, device=dev)
+    C = torch.zeros((1, 8), dtype=torch.float64, device=dev)
+    need = L.tcu_gemm_f64_workspace_bytes(1, 8, 4096)
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    st = L.tcu_gemm_f64_ws(0, 0, 1, 8, 4096, ops._ptr(A), 4096, ops._ptr(B), 8, ops._ptr(C), 8,
+                           ops._ptr(ws), need - 8, ops._stream(dev))
+    assert st == ops._lib.TCU_ERR_WORKSPACE and torch.all(C == 0)
+    st = L.tcu_gemm_f64_ws(0, 0, 1, 8, 4096, ops._ptr(A), 4096, ops._ptr(B), 8, ops._ptr(C), 8,
+                           ops._ptr(ws), need, ops._stream(dev))
+    assert st == 0 and torch.all(C == 4096.0)
+
+
 def test_gemm_f64_k_zero():
     dev = cuda_or_skip()
     out = torch.full((5, 7), 3.0, dtype=torch.float64, device=dev)
@@ -325,3 +366,75 @@ def test_fwd_integer_values_bit_exact(orc, lo, hi):
     r = np.where(rng.random(N) < 0.5, -1.0, 1.0)
     lhs = np.array([math.fsum(row * r) for row in Ch])
     assert np.array_equal(lhs, orc.freivalds(RA, RB, N, N, N, r))
+
+
+def test_out_buffers_of_the_wrong_shape_are_refused():
+    """A caller's `out` must have exactly the written shape: a smaller one
+    would take out-of-bounds writes, so the binding refuses it first."""
+    dev = cuda_or_skip()
+    A, B = wl.mm_query(16, 12, 10, seed=5, device=dev)
+    small = torch.empty((16, 11), dtype=torch.float64, device=dev)
+    with pytest.raises(ValueError):
+        ops.encode(A.group, A.key, A.val, 16, 12, out=small, unique=True)
+    X = torch.rand((16, 12), dtype=torch.float64, device=dev)
+    Y = torch.rand((12, 10), dtype=torch.float64, device=dev)
+    with pytest.raises(ValueError):
+        ops.gemm_f64(X, Y, out=torch.empty((10, 16), dtype=torch.float64, device=dev))
+    good = ops.gemm_f64(X, Y, out=torch.empty((16, 10), dtype=torch.float64, device=dev))
+    assert good.shape == (16, 10)
+
+
+def _unique_cells(n, rows, cols, seed, tag, dev, bad=0):
+    """n records on distinct (group, key) cells of a rows x cols grid, in a
+    seeded order, plus `bad` records with an out-of-range key."""
+    u = wl.uniform01(wl.stream_key(seed, tag), torch.arange(rows * cols, device=dev))
+    cells = torch.argsort(u)[:n]
+    g = (cells // cols).to(torch.int32)
+    k = (cells % cols).to(torch.int32)
+    v = wl.draw_values("uniform", n, seed, tag, device=dev)
+    if bad:
+        k[:bad] = cols + 2
+    return wl.Relation(g, k, v)
+
+
+@pytest.mark.parametrize("M,K,N,fill,bad", [
+    (300, 257, 290, 0.3, 0),      # ragged tiles of the int8 product
+    (1, 5000, 70, 0.05, 0),       # one group
+    (513, 1, 600, 1.0, 0),        # K = 1: every pair joins
+    (260, 700, 250, 0.1, 17),     # out-of-range records
+])
+def test_fwd_counts_int8_path_unique_cells(orc, M, K, N, fill, bad):
+    """Unique cells on both sides: the counts come from the int8 product of
+    the 0/1 encodings, bit for bit the oracle's."""
+    dev = cuda_or_skip()
+    A = _unique_cells(int(fill * M * K) + bad, M, K, 31, 1, dev, bad)
+    Bt = _unique_cells(int(fill * N * K), N, K, 31, 2, dev)
+    Cg, cnt, ws = ops.join_agg_fwd(A.group, A.key, A.val, Bt.key, Bt.group, Bt.val, M, K, N,
+                                   with_count=True, unique=True)
+    st, info = ops.sync_status(ws)
+    assert st == (ops._lib.TCU_ERR_KEY_RANGE if bad else 0)
+    RA, RB = to_orc(orc, A), to_orc(orc, Bt)
+    Co, co, _ = orc.join_agg(RA, RB, M, K, N, with_count=True)
+    assert np.array_equal(cnt.cpu().numpy(), co)
+    S, _, _ = orc.join_agg(abs_rel(orc, RA), abs_rel(orc, RB), M, K, N)
+    assert err_cw(Cg.cpu().numpy(), Co, S) <= TOL
+
+
+@pytest.mark.parametrize("n,over", [(46340, False), (46341, True)])
+def test_fwd_count_at_the_int32_limit(n, over):
+    """n records of A and n of B on one key and one group each: one cell with
+    n^2 pairs.  46340^2 fits int32 and is exact; 46341^2 does not: the cell
+    holds INT32_MAX and the call reports TCU_ERR_COUNT_RANGE."""
+    dev = cuda_or_skip()
+    z = torch.zeros(n, dtype=torch.int32, device=dev)
+    one = torch.ones(n, dtype=torch.float64, device=dev)
+    Cg, cnt, ws = ops.join_agg_fwd(z, z, one, z, z, one, 2, 3, 2, with_count=True)
+    st, info = ops.sync_status(ws)
+    c = cnt.cpu().numpy()
+    assert c[0, 0] == (2 ** 31 - 1 if over else n * n)
+    assert np.all(c.reshape(-1)[1:] == 0)
+    assert float(Cg[0, 0]) == float(n * n)
+    if over:
+        assert st == ops._lib.TCU_ERR_COUNT_RANGE and info["flags"] & ops._lib.TCU_FLAG_COUNT_RANGE
+    else:
+        assert st == 0 and info["flags"] == 0

@@ -35,7 +35,7 @@ def test_exports_every_declared_symbol(lib):
 
 def test_version_and_status_strings(lib):
     assert b"gfx950" in lib.tcu_version()
-    for code in range(-6, 1):
+    for code in range(-7, 1):
         s = lib.tcu_status_str(code).decode()
         assert s and s != "unknown status"
     assert lib.tcu_status_str(-99).decode() == "unknown status"
@@ -111,22 +111,48 @@ def test_argument_errors_return_before_launch(lib):
     assert lib.tcu_sync_status(None, None, None) == _lib.TCU_ERR_WORKSPACE
 
 
-def test_split_plan_host_only(lib):
-    """The precision plan (feasibility test retargeted) needs no device."""
+MODULI = [256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 217, 211, 199, 197]
+
+
+def _plan(lib, p, k, tol, need, u):
+    bits = C.c_int32(-1)
+    r = lib.tcu_mixed_plan(p, k, tol, need, u, C.byref(bits))
+    return r, bits.value
+
+
+def test_mixed_plan_host_only(lib):
+    """Step a0's host part: the plan from a product's certificate."""
+    import math
     for p in (_lib.TCU_PREC_SPLIT_BF16, _lib.TCU_PREC_SPLIT_I8):
-        prev = 0
-        for tol in (1e-3, 1e-6, 1e-9, 1e-12):
-            S = lib.tcu_split_slices(p, 4096, tol)
-            assert 1 <= S <= _lib.TCU_MAX_SLICES and S >= prev
-            prev = S
-        # the bound's truncation part alone: 4.04 (S+1) 2^-7S must not exceed tol
-        S = lib.tcu_split_slices(p, 4096, 1e-12)
-        assert 4.04 * (S + 1) * 2.0 ** (-7 * S) <= 1e-12
-        assert 4.04 * S * 2.0 ** (-7 * (S - 1)) > 1e-12  # S - 1 slices would not do
-        assert lib.tcu_split_slices(p, 4096, 1e-18) == _lib.TCU_ERR_INFEASIBLE
-        assert lib.tcu_split_slices(p, 0, 1e-9) == _lib.TCU_ERR_ARG
-        assert lib.tcu_split_slices(p, 64, 0.0) == lib.tcu_split_slices(p, 64, 1e-12)
-    assert lib.tcu_split_slices(_lib.TCU_PREC_FP64, 64, 1e-9) == _lib.TCU_ERR_ARG
+        assert _plan(lib, p, 4096, 1e-12, 0, 1.0)[0] == 1        # all-zero product
+        for need in range(1, 9):
+            assert _plan(lib, p, 4096, 1e-12, need, 100.0)[0] == need
+        assert _plan(lib, p, 4096, 1e-12, 9, 1.0)[0] == _lib.TCU_ERR_INFEASIBLE
+        assert _plan(lib, p, 4096, 1e-12, 255, 1.0)[0] == _lib.TCU_ERR_INFEASIBLE
+    crt = _lib.TCU_PREC_CRT_I8
+    # the modulus count: the smallest L with prod m_i > 4 * 2^(2b) * min(max(u, 1), k)
+    for k, need, u in ((4096, 42, 4096.0), (4096, 46, 136.0), (32768, 48, 325.0),
+                       (1, 2, 0.9), (257, 53, 257.0), (100, 20, 1e9), (5000, 0, 0.0)):
+        b = max(need, 1)
+        U = min(max(u, 1.0), float(k))
+        want = next((L for L in range(1, 16)
+                     if math.log2(math.prod(MODULI[:L])) > 2 * b + math.log2(U) + 2), None)
+        got, bits = _plan(lib, crt, k, 1e-12, need, u)
+        if want is None:
+            assert got == _lib.TCU_ERR_INFEASIBLE
+        else:
+            assert (got, bits) == (want, b), (k, need, u)
+    # every modulus count is reachable
+    seen = ({_plan(lib, crt, 131071, 1e-12, b, 131071.0)[0] for b in range(1, 54)} |
+            {_plan(lib, crt, 1, 1e-12, b, 1.0)[0] for b in range(1, 54)})
+    assert sorted(seen - {_lib.TCU_ERR_INFEASIBLE}) == list(range(1, 16))
+    assert _plan(lib, crt, 4096, 1e-12, 54, 1.0)[0] == _lib.TCU_ERR_INFEASIBLE
+    assert _plan(lib, crt, 131072, 1e-12, 10, 1.0)[0] == _lib.TCU_ERR_INFEASIBLE  # int32 sums
+    for p in (crt, _lib.TCU_PREC_SPLIT_I8):
+        assert _plan(lib, p, 64, 2.0 ** -51, 3, 1.0)[0] == _lib.TCU_ERR_INFEASIBLE  # tol floor
+        assert _plan(lib, p, 64, 0.0, 3, 1.0) == _plan(lib, p, 64, 1e-12, 3, 1.0)
+        assert _plan(lib, p, 0, 1e-9, 3, 1.0)[0] == _lib.TCU_ERR_ARG
+    assert _plan(lib, _lib.TCU_PREC_FP64, 64, 1e-9, 3, 1.0)[0] == _lib.TCU_ERR_ARG
 
 
 def test_split_argument_errors(lib):
@@ -265,3 +291,39 @@ def test_noalloc_rejects_before_touching_the_device(lib):
     assert need <= _lib.TCU_NOALLOC_MAX_BYTES
     assert lib.tcu_workspace_bytes(C.byref(A), C.byref(B), 2200, 2048, 2200, 0, 0) > \
         _lib.TCU_NOALLOC_MAX_BYTES
+
+
+def test_ops_out_shape_and_device_checked(monkeypatch):
+    """ops.encode / ops.gemm_f64 refuse an `out` whose shape or device differs
+    from what the library writes (host-side, before any library call)."""
+    import torch
+    from paper_2112_07552_amd import ops
+
+    monkeypatch.setattr(ops, "_need_cuda", lambda *a, **k: None)  # CPU tensors stand in
+    out = torch.empty((3, 4), dtype=torch.float64)
+    ops._need_out(out, (3, 4), "cpu")
+    for shape in ((4, 3), (3, 5), (12,)):
+        with pytest.raises(ValueError):
+            ops._need_out(out, shape, "cpu")
+    with pytest.raises(ValueError):
+        ops._need_out(out, (3, 4), "meta")
+
+
+def test_gemm_split_workspace_sizes(lib):
+    """The split contraction applies to outputs of few tiles with a long
+    contraction; its workspace holds one partial product per chunk."""
+    assert lib.tcu_gemm_f64_workspace_bytes(4096, 4096, 4096) == 0   # enough tiles
+    assert lib.tcu_gemm_f64_workspace_bytes(1, 32, 512) == 0         # short contraction
+    nb = lib.tcu_gemm_f64_workspace_bytes(1, 32, 32768)
+    assert nb > 0 and nb % (1 * 32 * 8) == 0 and nb // (32 * 8) >= 2
+    assert lib.tcu_gemm_f64_workspace_bytes(0, 32, 32768) == 0
+    cbuf = C.c_void_p(0x2000)
+    # argument errors return before any launch
+    assert lib.tcu_gemm_f64_ws(2, 0, 1, 32, 32768, cbuf, 32768, cbuf, 32, cbuf, 32, cbuf, nb,
+                               None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_gemm_f64_ws(0, 0, 1, 32, 32768, cbuf, 32768, cbuf, 32, cbuf, 31, cbuf, nb,
+                               None) == _lib.TCU_ERR_ARG
+    assert lib.tcu_gemm_f64_ws(0, 0, 1, 32, 32768, cbuf, 32768, cbuf, 32, cbuf, 32, None, nb,
+                               None) == _lib.TCU_ERR_WORKSPACE
+    assert lib.tcu_gemm_f64_ws(0, 0, 1, 32, 32768, cbuf, 32768, cbuf, 32, cbuf, 32, cbuf, nb - 1,
+                               None) == _lib.TCU_ERR_WORKSPACE
