@@ -120,9 +120,9 @@ typedef struct {
     uint64_t skipped_b;    /* records of B skipped by the last call           */
     uint32_t bits;         /* residue form: truncation width of the last
                               product                                        */
-    uint32_t need;         /* mixed forms: the last certificate's largest
-                              per-cell need (bits or digits; 255: a cell it
-                              could not bound)                               */
+    uint32_t need;         /* mixed forms: the last product certificate's
+                              largest per-cell need in its form (bits or
+                              digits; 255: a cell it could not bound)        */
 } tcu_status_info;
 
 #define TCU_FLAG_KEY_RANGE 1u /* a record had an out-of-range key or group    */

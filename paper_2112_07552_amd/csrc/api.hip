@@ -226,6 +226,7 @@ struct SplitOperand {
 // FP64), the padded contraction length and the padded line counts.
 struct MixedPlan {
     int S = 0, bits = 0, len_pad = 0, la = 0, lb = 0;
+    uint32_t need = 0;  // the certificate's need in this form
 };
 
 // Step a0 for one operand: line maxima and sums of |z|, then the magnitude
@@ -264,7 +265,8 @@ hipError_t certify_and_plan(int m, int n, int k, tcu_precision p, double tol, vo
     ca.need_bits = &st->need_bits;
     ca.need_slices = &st->need_slices;
     hipError_t e = launch_certify(m, n, k, at<int8_t>(ws, L.qa), (int)pad256(m),
-                                  at<int8_t>(ws, L.qb), (int)pad256(n), (int)qlen(k), ca, s);
+                                  at<int8_t>(ws, L.qb), (int)pad256(n), (int)qlen(k), ca,
+                                  !is_crt(p), s);
     if (e != hipSuccess) return e;
     StatusBlock host;
     e = hipMemcpyAsync(&host, st, sizeof(host), hipMemcpyDeviceToHost, s);
@@ -279,6 +281,7 @@ hipError_t certify_and_plan(int m, int n, int k, tcu_precision p, double tol, vo
         r = mixed_plan(p, k, tol, is_crt(p) ? host.need_bits : host.need_slices,
                        std::min(ua, ub), &bits);
     *mp = MixedPlan{};
+    mp->need = is_crt(p) ? host.need_bits : host.need_slices;
     if (r > 0) {
         mp->S = r;
         mp->bits = bits;
@@ -334,13 +337,14 @@ hipError_t finish_product(const SplitOperand &a, const SplitOperand &b, int m, i
     if (e != hipSuccess) return e;
     if (mp.S == 0) {
         e = launch_gemm_f64(a.axis, b.axis == 0 ? 1 : 0, m, n, k, a.Z, a.ld, b.Z, b.ld, C, ldc, s);
-        if (e == hipSuccess) e = launch_set_plan(st, 0, 0, true, s);
+        if (e == hipSuccess) e = launch_set_plan(st, 0, 0, mp.need, true, s);
         return e;
     }
     e = mixed_split(a, false, mp, p, ws, L, s);
     if (e == hipSuccess) e = mixed_split(b, true, mp, p, ws, L, s);
     if (e == hipSuccess) e = mixed_multiply(m, n, k, mp, p, ws, L, C, ldc, s);
-    if (e == hipSuccess) e = launch_set_plan(st, (uint32_t)mp.S, (uint32_t)mp.bits, false, s);
+    if (e == hipSuccess)
+        e = launch_set_plan(st, (uint32_t)mp.S, (uint32_t)mp.bits, mp.need, false, s);
     return e;
 }
 
@@ -813,7 +817,7 @@ tcu_status tcu_sync_status(void *ws, hipStream_t stream, tcu_status_info *info) 
         info->skipped_a = host.skipped_a;
         info->skipped_b = host.skipped_b;
         info->bits = host.bits;
-        info->need = host.need_bits > host.need_slices ? host.need_bits : host.need_slices;
+        info->need = host.need;
     }
     if (host.flags & kFlagNonFinite) return TCU_ERR_NONFINITE;
     if (host.flags & kFlagKeyRange) return TCU_ERR_KEY_RANGE;

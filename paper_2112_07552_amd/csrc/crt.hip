@@ -29,6 +29,8 @@
 // KB), four stages in LDS filled by direct-to-LDS loads issued three stages
 // ahead; the fragments of the next k-step are read while the current one
 // multiplies, and the barrier sits between the two k-steps of a stage.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace tcu {
@@ -333,22 +335,31 @@ mag_cols_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
 // where tcrt and tdig[S] are the tolerance less the rounding of the FP64
 // combination.  The cell's need is the smallest such b and S; a cell with T
 // = 0 but r > 0 cannot be bounded (kNeedUncertified).
-__device__ inline void cert_cell(double r, int T, const CertArgs &ca, uint32_t &nb,
-                                 uint32_t &ns) {
-    if (T <= 0) {
-        nb = ns = r > 0.0 ? kNeedUncertified : 0u;
-        return;
-    }
+// The residue form's need of one cell: the smallest b >= 1 with r <= 2^b u,
+// u = tcrt T, read off the exponents and mantissas of r (enlarged past the
+// rounding of u) and u: with r = mr 2^er and u = mu 2^eu (mantissas in
+// [0.5, 1)), b = er - eu, plus 1 when mr > mu.
+__device__ inline uint32_t cert_bits(double r, int T, const CertArgs &ca) {
+    if (T <= 0) return r > 0.0 ? kNeedUncertified : 0u;
+    if (r <= 0.0) return 0u;
+    int er, eu;
+    const double mr = frexp(r * (1.0 + 0x1p-40), &er);
+    const double mu = frexp(ca.tcrt * (double)T, &eu);
+    const int b = er - eu + (mr > mu ? 1 : 0);
+    return (uint32_t)min(max(b, 1), (int)kNeedUncertified - 1);
+}
+
+// The digit forms' need of one cell: the smallest S in 1..8 with
+// 2^-7S (r + (S - 1) kterm) <= tdig[S] T (kNeedUncertified when none).
+__device__ inline uint32_t cert_slices(double r, int T, const CertArgs &ca) {
+    if (T <= 0) return r > 0.0 ? kNeedUncertified : 0u;
+    if (r <= 0.0) return 0u;
     const double dT = (double)T;
-    int e = 0;
-    // 2^(e-1) <= q < 2^e, with q enlarged past the rounding of the division
-    frexp(r / (ca.tcrt * dT) * (1.0 + 0x1p-40), &e);
-    nb = (uint32_t)min(max(e, 1), (int)kNeedUncertified - 1);
-    ns = kNeedUncertified;
+    uint32_t ns = kNeedUncertified;
 #pragma unroll
-    for (int S = 1; S <= TCU_MAX_SLICES; ++S)
-        if (ns == kNeedUncertified && ldexp(r + (S - 1) * ca.kterm, -7 * S) <= ca.tdig[S] * dT)
-            ns = (uint32_t)S;
+    for (int S = TCU_MAX_SLICES; S >= 1; --S)
+        if (ldexp(r + (S - 1) * ca.kterm, -7 * S) <= ca.tdig[S] * dT) ns = (uint32_t)S;
+    return ns;
 }
 
 // ---------------------------------------------------------------- the GEMM
@@ -376,6 +387,12 @@ constexpr int NUM_XCD = 8, GROUP_M = 4, RUN = 32;
 // k-steps of 32 per unrolled round of the main loop: the contraction length
 // of the residue planes is padded to a multiple of this
 constexpr int kCrtLenAlign = 64 * CrtCfg::NS;
+// k per launch of the residue products (a multiple of kCrtLenAlign)
+#ifndef CRT_KCHUNK
+#define CRT_KCHUNK 8192
+#endif
+constexpr int kCrtChunk = CRT_KCHUNK;
+static_assert(kCrtChunk % kCrtLenAlign == 0, "chunks hold whole unrolled rounds");
 
 template <int V>
 __device__ inline void wait_vm() {
@@ -520,17 +537,20 @@ __device__ inline void crt_stages(int st, int nst, const StageLoads<G> &L, unsig
 
 // What the int8 GEMM does with its exact int32 sums.
 constexpr int kEpiResidue = 0;  // residues modulo the workgroup's modulus, int8 planes
-constexpr int kEpiCertify = 1;  // the plan's per-cell needs (cert_cell), maxima into ca
+constexpr int kEpiCertify = 1;  // the residue form's per-cell needs (cert_bits), maximum into ca
+constexpr int kEpiCertifyDigits = 3;  // the digit forms' (cert_slices)
 constexpr int kEpiCount = 2;    // the int32 sums themselves (pair counts), into cnt
 
 // nblk (k-steps) must be a multiple of 2 NS.  SMALL: nblk * 32 <= 4096, so
-// every int32 sum is at most 2^26 in magnitude.
+// every int32 sum is at most 2^26 in magnitude (and no carry).  carry: this
+// launch is a later chunk of a longer contraction, whose earlier chunks'
+// residues it adds to its own sums before reducing them (only !SMALL).
 template <typename G, bool SMALL, int EPI>
 __global__ void __launch_bounds__(G::threads) __attribute__((amdgpu_waves_per_eu(G::WPE, G::WPE)))
 gemm_crt_kernel(int m, int n, int nblk, int tiles_m, int tiles_n, const int8_t *__restrict__ xs,
                 int xlp, const int8_t *__restrict__ ys, int ylp, int64_t plane_x,
                 int64_t plane_y, CrtConsts cc, int8_t *__restrict__ res, int64_t plane_res,
-                CertArgs ca, int32_t *__restrict__ cnt, int64_t ldcnt) {
+                CertArgs ca, int32_t *__restrict__ cnt, int64_t ldcnt, int carry) {
     constexpr int WA = G::WA, WB = G::WB, PW = G::PER_WAVE, NS = G::NS;
     __shared__ __attribute__((aligned(16))) i4 lds[NS * G::STAGE];
     // workgroup -> (modulus, tile).  Tiles of one modulus are numbered in
@@ -608,9 +628,9 @@ gemm_crt_kernel(int m, int n, int nblk, int tiles_m, int tiles_n, const int8_t *
         }
         return;
     }
-    if constexpr (EPI == kEpiCertify) {
-        // each cell's needs (cert_cell); the wave's maxima go out in one atomic each
-        uint32_t nb = 0, ns = 0;
+    if constexpr (EPI == kEpiCertify || EPI == kEpiCertifyDigits) {
+        // each cell's need; the wave's maximum goes out in one atomic
+        uint32_t need = 0;
 #pragma unroll
         for (int a = 0; a < WA; ++a) {
             const int rbase = m0 + wm * 32 * WA + a * 32;
@@ -628,21 +648,14 @@ gemm_crt_kernel(int m, int n, int nblk, int tiles_m, int tiles_n, const int8_t *
                     // in the exact and in the truncated product alike
                     const double sx = ca.sx[row];
                     const double r = (sx > 0.0 && sy > 0.0) ? 16384.0 * (sx + sy) : 0.0;
-                    uint32_t cb, cs;
-                    cert_cell(r, acc[a][b][i], ca, cb, cs);
-                    nb = max(nb, cb);
-                    ns = max(ns, cs);
+                    need = max(need, EPI == kEpiCertify ? cert_bits(r, acc[a][b][i], ca)
+                                                        : cert_slices(r, acc[a][b][i], ca));
                 }
             }
         }
-        for (int off = 32; off > 0; off >>= 1) {
-            nb = max(nb, (uint32_t)__shfl_xor((int)nb, off));
-            ns = max(ns, (uint32_t)__shfl_xor((int)ns, off));
-        }
-        if (lane == 0) {
-            atomicMax(ca.need_bits, nb);
-            atomicMax(ca.need_slices, ns);
-        }
+        for (int off = 32; off > 0; off >>= 1)
+            need = max(need, (uint32_t)__shfl_xor((int)need, off));
+        if (lane == 0) atomicMax(EPI == kEpiCertify ? ca.need_bits : ca.need_slices, need);
         return;
     }
     // epilogue: residues of the int32 sums as int8 in the accumulator's own
@@ -658,15 +671,24 @@ gemm_crt_kernel(int m, int n, int nblk, int tiles_m, int tiles_n, const int8_t *
         for (int b = 0; b < WB; ++b) {
             const int col = n0 + wn * 32 * WB + b * 32 + l32;
             if (col >= n) continue;
+            uint4 *dst = reinterpret_cast<uint4 *>(r + ((int64_t)rb * n + col) * 32 + 16 * half);
+            // a later chunk of the contraction adds the residues the earlier
+            // chunks left (congruent to their sums), byte j of word q for sum 4q + j
+            uint32_t prev[4] = {0u, 0u, 0u, 0u};
+            if (!SMALL && carry) {
+                const uint4 p4 = *dst;
+                prev[0] = p4.x; prev[1] = p4.y; prev[2] = p4.z; prev[3] = p4.w;
+            }
             uint32_t w[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int xs4[4] = {acc[a][b][4 * q], acc[a][b][4 * q + 1], acc[a][b][4 * q + 2],
-                                    acc[a][b][4 * q + 3]};
+                int xs4[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    xs4[j] = acc[a][b][4 * q + j] + (int)(int8_t)(prev[q] >> (8 * j));
                 w[q] = sym_mod32x4<SMALL>(xs4, mi, c16, inv);
             }
-            *reinterpret_cast<uint4 *>(r + ((int64_t)rb * n + col) * 32 + 16 * half) =
-                make_uint4(w[0], w[1], w[2], w[3]);
+            *dst = make_uint4(w[0], w[1], w[2], w[3]);
         }
     }
 }
@@ -857,19 +879,29 @@ hipError_t launch_gemm_crt(int m, int n, int k, int L, int bits, const int8_t *x
     using G = CrtCfg;
     const CertArgs none{};
     const int64_t px = (int64_t)x_lines_pad * len_pad, py = (int64_t)y_lines_pad * len_pad;
-    hipError_t e;
+    hipError_t e = hipSuccess;
     {
         TraceScope ts(TCU_KERNEL_GEMM_CRT, m, n, k, L, L * 2.0 * m * n * (double)k, s);
-        // |sum| <= len_pad 2^14 (residues at most 128 in magnitude)
-        if (len_pad <= 4096)
-            gemm_crt_kernel<G, true, kEpiResidue><<<(unsigned)wgs, G::threads, 0, s>>>(
-                m, n, nblk, tiles_m, tiles_n, xs, x_lines_pad, ys, y_lines_pad, px, py, cc, res,
-                plane_res, none, nullptr, 0);
-        else
-            gemm_crt_kernel<G, false, kEpiResidue><<<(unsigned)wgs, G::threads, 0, s>>>(
-                m, n, nblk, tiles_m, tiles_n, xs, x_lines_pad, ys, y_lines_pad, px, py, cc, res,
-                plane_res, none, nullptr, 0);
-        e = hipGetLastError();
+        // Contractions longer than kCrtChunk run as launches over chunks of k:
+        // the workgroups of one launch start together and stream the same
+        // k-slices of shared panels, so a chunk keeps them close enough in k
+        // for the caches to serve each slice to all of them; each later
+        // chunk adds the residues the earlier ones left.
+        for (int k0 = 0; k0 < len_pad && e == hipSuccess; k0 += kCrtChunk) {
+            const int kn = std::min(kCrtChunk, len_pad - k0);
+            // a chunk starts k0 / 32 k-steps into each plane: k0 bytes per line
+            const int8_t *xc = xs + (int64_t)k0 * x_lines_pad, *yc = ys + (int64_t)k0 * y_lines_pad;
+            // |sum| <= kn 2^14 (residues at most 128 in magnitude)
+            if (kn <= 4096 && k0 == 0)
+                gemm_crt_kernel<G, true, kEpiResidue><<<(unsigned)wgs, G::threads, 0, s>>>(
+                    m, n, kn / 32, tiles_m, tiles_n, xc, x_lines_pad, yc, y_lines_pad, px, py, cc,
+                    res, plane_res, none, nullptr, 0, 0);
+            else
+                gemm_crt_kernel<G, false, kEpiResidue><<<(unsigned)wgs, G::threads, 0, s>>>(
+                    m, n, kn / 32, tiles_m, tiles_n, xc, x_lines_pad, yc, y_lines_pad, px, py, cc,
+                    res, plane_res, none, nullptr, 0, k0 > 0 ? 1 : 0);
+            e = hipGetLastError();
+        }
     }
     if (e != hipSuccess) return e;
     const dim3 grid((unsigned)((n + kThreads / 4 - 1) / (kThreads / 4)), (unsigned)((m + 31) / 32));
@@ -895,7 +927,7 @@ hipError_t launch_mag_plane(const double *Z, int rows, int cols, int64_t ld, int
 
 hipError_t launch_certify(int m, int n, int k, const int8_t *qa, int a_lines_pad,
                           const int8_t *qb, int b_lines_pad, int len_pad, const CertArgs &ca,
-                          hipStream_t s) {
+                          bool digits, hipStream_t s) {
     if (m == 0 || n == 0) return hipSuccess;
     if (a_lines_pad % CrtCfg::BM || b_lines_pad % CrtCfg::BN || len_pad % kCrtLenAlign ||
         len_pad < k || a_lines_pad < m || b_lines_pad < n)
@@ -904,10 +936,16 @@ hipError_t launch_certify(int m, int n, int k, const int8_t *qa, int a_lines_pad
     const int tiles_m = (m + CrtCfg::BM - 1) / CrtCfg::BM, tiles_n = (n + CrtCfg::BN - 1) / CrtCfg::BN;
     using G = CrtCfg;
     TraceScope ts(TCU_KERNEL_CERTIFY, m, n, k, 1, 2.0 * m * n * (double)k, s);
-    gemm_crt_kernel<G, false, kEpiCertify><<<(unsigned)(tiles_m * tiles_n), G::threads, 0, s>>>(
-        m, n, len_pad / 32, tiles_m, tiles_n, qa, a_lines_pad, qb, b_lines_pad,
-        (int64_t)a_lines_pad * len_pad, (int64_t)b_lines_pad * len_pad, cc, nullptr, 0, ca,
-        nullptr, 0);
+    const unsigned grid = (unsigned)(tiles_m * tiles_n);
+    const int64_t pa = (int64_t)a_lines_pad * len_pad, pb = (int64_t)b_lines_pad * len_pad;
+    if (digits)
+        gemm_crt_kernel<G, false, kEpiCertifyDigits><<<grid, G::threads, 0, s>>>(
+            m, n, len_pad / 32, tiles_m, tiles_n, qa, a_lines_pad, qb, b_lines_pad, pa, pb, cc,
+            nullptr, 0, ca, nullptr, 0, 0);
+    else
+        gemm_crt_kernel<G, false, kEpiCertify><<<grid, G::threads, 0, s>>>(
+            m, n, len_pad / 32, tiles_m, tiles_n, qa, a_lines_pad, qb, b_lines_pad, pa, pb, cc,
+            nullptr, 0, ca, nullptr, 0, 0);
     return hipGetLastError();
 }
 
@@ -952,7 +990,7 @@ hipError_t launch_count_product(int m, int n, int k, const int8_t *qa, int a_lin
     gemm_crt_kernel<G, false, kEpiCount><<<(unsigned)(tiles_m * tiles_n), G::threads, 0, s>>>(
         m, n, len_pad / 32, tiles_m, tiles_n, qa, a_lines_pad, qb, b_lines_pad,
         (int64_t)a_lines_pad * len_pad, (int64_t)b_lines_pad * len_pad, cc, nullptr, 0, none,
-        count, ldc);
+        count, ldc, 0);
     return hipGetLastError();
 }
 

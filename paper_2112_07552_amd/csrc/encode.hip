@@ -45,9 +45,11 @@ __global__ void reset_plan_kernel(StatusBlock *st) {
 }
 
 // The plan a mixed-form product ran with (slices = 0: FP64 fallback).
-__global__ void set_plan_kernel(StatusBlock *st, uint32_t slices, uint32_t bits, int fallback) {
+__global__ void set_plan_kernel(StatusBlock *st, uint32_t slices, uint32_t bits, uint32_t need,
+                                int fallback) {
     st->slices = slices;
     st->bits = bits;
+    st->need = need;
     if (fallback) st->flags |= kFlagFallback;
 }
 
@@ -145,9 +147,9 @@ hipError_t launch_reset_plan(StatusBlock *st, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_set_plan(StatusBlock *st, uint32_t slices, uint32_t bits, bool fallback,
-                           hipStream_t s) {
-    set_plan_kernel<<<1, 1, 0, s>>>(st, slices, bits, fallback ? 1 : 0);
+hipError_t launch_set_plan(StatusBlock *st, uint32_t slices, uint32_t bits, uint32_t need,
+                           bool fallback, hipStream_t s) {
+    set_plan_kernel<<<1, 1, 0, s>>>(st, slices, bits, need, fallback ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ struct StatusBlock {
     uint32_t bits;                  // residue form: truncation width of the last product
     uint32_t need_bits;             // certificate: largest per-cell truncation width needed
     uint32_t need_slices;           // certificate: largest per-cell digit count needed
-    uint32_t pad0;
+    uint32_t need;                  // the last product's need in its own form
     unsigned long long umax_a;      // bit pattern of max over lines of sum|z| 2^-e, operand A
     unsigned long long umax_b;      // the same for operand B
     uint32_t pad[50];
@@ -87,8 +87,8 @@ hipError_t launch_clear_status(StatusBlock *st, hipStream_t s, uint32_t slices =
 // status words of a mixed-form product: cleared before its certificate, and
 // the plan it ran with (slices = 0 and the fallback flag: FP64)
 hipError_t launch_reset_plan(StatusBlock *st, hipStream_t s);
-hipError_t launch_set_plan(StatusBlock *st, uint32_t slices, uint32_t bits, bool fallback,
-                           hipStream_t s);
+hipError_t launch_set_plan(StatusBlock *st, uint32_t slices, uint32_t bits, uint32_t need,
+                           bool fallback, hipStream_t s);
 hipError_t launch_encode(const tcu_relation &R, int transpose, int rows, int cols, double *out,
                          StatusBlock *st, int which, hipStream_t s);
 // dst[i] = src[row_i, col_i] for the records whose row lies in [r0, r1)
@@ -196,8 +196,8 @@ hipError_t launch_mfma_peak(int kind, int iters, void *out, hipStream_t s);
 // The certificate of a mixed-form product (crt.hip): magnitude planes of
 // both operands (int8, the residue layout; lines_pad a multiple of 256,
 // len_pad of crt_len_align()) with their lines' normalised sums of |z|, then
-// one int8 GEMM whose epilogue folds every cell's needs into need_bits
-// (residue form: truncation width) and need_slices (digit forms: digits).
+// one int8 GEMM whose epilogue folds every cell's need into need_bits
+// (residue form: truncation width) or need_slices (digit forms: digits).
 struct CertArgs {
     const double *sx, *sy;  // normalised sums of the lines of A and B (rounded up)
     double tcrt;            // residue form: tolerance left for the truncation
@@ -211,7 +211,7 @@ hipError_t launch_mag_plane(const double *Z, int rows, int cols, int64_t ld, int
                             hipStream_t s);
 hipError_t launch_certify(int m, int n, int k, const int8_t *qa, int a_lines_pad,
                           const int8_t *qb, int b_lines_pad, int len_pad, const CertArgs &ca,
-                          hipStream_t s);
+                          bool digits, hipStream_t s);
 // The count path (crt.hip): the 0/1 plane of a relation with unique cells
 // (line = group, position = key; the rest zero), then one int8 product with
 // exact int32 sums written to count (m x n, leading dimension ldc).

@@ -133,13 +133,18 @@ def test_mixed_forms_2pow30_records_forward_adjoint_checkpointed(orc):
     tia, tib = torch.as_tensor(ia, device=dev), torch.as_tensor(ib, device=dev)
 
     # -- each mixed form -------------------------------------------------------
-    for precision in ("split_i8", "crt_i8"):
+    for precision in ("crt_i8", "split_i8"):
         log(f"{precision} forward")
         Cs, _, ws = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, N, N, N,
                                      precision=precision, tol=TOL, unique=True)
         st, info = ops.sync_status(ws)
-        assert st == 0 and info["flags"] & ops._lib.TCU_FLAG_FALLBACK == 0
         log(f"{precision} plan: {info}")
+        assert st == 0
+        if precision == "crt_i8":
+            # the residue form certifies this workload; the digit forms' bound
+            # carries a term (S - 1) K 2^-7S per cell that 8 digits cannot
+            # bring under 1e-12 (|X||Y|) at K = 32768, so they may run in FP64
+            assert info["flags"] & ops._lib.TCU_FLAG_FALLBACK == 0
         del ws
         log(f"{precision} adjoint, checkpointed")
         dAs, dBs, ws = ops.join_agg_bwd(A.group, A.key, A.val, B.key, B.group, B.val, N, N, N,
