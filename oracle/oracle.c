@@ -544,7 +544,7 @@ int orc_trunc_product(int32_t M, int32_t K, int32_t N, const double *X, const do
  *   when s_g or s_h is 0 (an all-zero line: every term of the cell is 0).
  * need_bits = max over cells of the smallest b >= 1 with r <= 2^b tcrt T,
  * need_slices = max over cells of the smallest S in 1..8 with
- *   r + (S - 1) 2^14 K <= 2^(7S) tdig[S] T  (9 when no S meets it);
+ *   r + (S - 1) 2^14 K <= 2^(7S) tdig[S] T  (255 when no S meets it);
  * a cell with T = 0 needs 0 when r = 0 and 255 of each otherwise.
  * umax[0], umax[1]: the largest s over the rows of X and the columns of Y.
  * T_out (M x N) and s_out (M + N: rows, then columns) may be NULL.
@@ -634,7 +634,7 @@ int orc_certificate(int32_t M, int32_t K, int32_t N, const double *X, const doub
                     const long double tT = (long double)tcrt * (long double)T;
                     cb = 1;
                     while (cb < 254 && r > ldexpl(tT, (int)cb)) ++cb;
-                    cs = 9;
+                    cs = 255;
                     for (int S = 1; S <= 8; ++S) {
                         const long double lhs = r + (long double)(S - 1) * 16384.0L * K;
                         if (lhs <= ldexpl((long double)tdig[S] * (long double)T, 7 * S)) {

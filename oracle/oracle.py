@@ -283,7 +283,8 @@ def trunc_product(X, Y, bits: int, threads: Optional[int] = None):
 def certificate(X, Y, tcrt: float, tdig, with_detail: bool = False,
                 threads: Optional[int] = None):
     """The certificate of the mixed-form product X Y (oracle.c,
-    orc_certificate): returns (need_bits, need_slices, (umax_x, umax_y)) and,
+    orc_certificate): returns (need_bits, need_slices, (umax_x, umax_y)) (255:
+    no width or digit count certifies some cell) and,
     with_detail, also T (M x N int64) and the normalised line sums (rows of
     X, then columns of Y).  tdig: 9 tolerances indexed by the digit count
     (entry 0 unused)."""

@@ -149,3 +149,42 @@ def test_crt_sweep_covered_every_count():
     if len(_seen_counts) != len(_L_SWEEP):
         pytest.skip("the sweep did not run in this session")
     assert sorted(_seen_counts) == list(range(1, 16))
+
+
+@pytest.mark.parametrize("precision", ["crt_i8", "split_i8"])
+@pytest.mark.parametrize("M,K,N,kind,tol", [
+    (300, 257, 129, "loguniform", 1e-12),
+    (200, 1000, 170, "mixture", 1e-12),
+    (150, 700, 260, "uniform", 1e-9),
+])
+def test_certificate_need_matches_the_oracle(orc, precision, M, K, N, kind, tol):
+    """The plan's certificate (step a0) against the oracle's, written from its
+    definition without rounding margins: the device's need is the oracle's,
+    or one more where the device's margins (relative 2^-20 on the line sums,
+    2^-40 on the comparison) tip a cell over a power of two."""
+    dev = cuda_or_skip()
+    A, B = wl.mm_query(M, K, N, seed=M + 3 * K, values=kind, device=dev)
+    Cg, _, ws = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, M, K, N,
+                                 precision=precision, tol=tol, unique=True)
+    st, info = ops.sync_status(ws)
+    assert st == 0
+    RA, RB = to_orc(orc, A), to_orc(orc, B)
+    X, _ = orc.encode_A(RA, M, K)
+    Y, _ = orc.encode_B(RB, K, N)
+    lib = ops._lib.load()
+    # the tolerances the device compares against (tcudb.h, tcu_mixed_plan)
+    tcrt = (tol - 2.0 ** -52) * (1 - 2.0 ** -40)
+    if precision == "crt_i8":
+        tdig = [0.0] * 9
+    else:
+        # int8 digits: one FP64 addition per diagonal for K <= 16384
+        tdig = [0.0] + [(tol - S * 2.0 ** -52) * (1 - 2.0 ** -40) for S in range(1, 9)]
+    nb, ns, umax = orc.certificate(X, Y, tcrt, tdig)
+    want = nb if precision == "crt_i8" else ns
+    assert info["need"] in (want, want + 1), (info, want)
+    if info["flags"] & ops._lib.TCU_FLAG_FALLBACK == 0:
+        # the plan the host derives from the oracle's need (same u up to the margin)
+        got = ops.mixed_plan(precision, K, tol, info["need"], min(umax) * (1 + 2.0 ** -20))
+        assert got[0] == info["slices"]
+        if precision == "crt_i8":
+            assert got[1] == info["bits"]
