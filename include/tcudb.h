@@ -133,9 +133,13 @@ typedef struct {
                                    INT32_MAX)                                 */
 
 /* Bytes of device workspace the calls below need for these shapes (Section
- * 3.3 encodings X and Y, plus the status block; with TCU_WS_BACKWARD one more
- * K-sized gradient matrix; in the mixed form the BF16 slices).  The
- * workspace must be 256-byte aligned.  Returns 0 for invalid shapes. */
+ * 3.3 encodings X and Y, plus the status block; with TCU_WS_BACKWARD the two
+ * gradient matrices; in the mixed forms the certificate's planes, digit
+ * slices or residues).  Given the relations (A and B not NULL), the size also
+ * holds the scratch with which an encoding of 1 GiB or more runs window by
+ * window (tcu_encode); a workspace sized without it (A or B NULL) is still
+ * accepted and encodes in one pass.  The workspace must be 256-byte aligned.
+ * Returns 0 for invalid shapes. */
 size_t tcu_workspace_bytes(const tcu_relation *A, const tcu_relation *B, int32_t M, int32_t K,
                            int32_t N, tcu_precision p, int flags);
 
@@ -147,9 +151,20 @@ size_t tcu_workspace_bytes(const tcu_relation *A, const tcu_relation *B, int32_t
  * unique coordinates give the values bit for bit (with TCU_REL_UNIQUE_CELLS
  * through plain stores).  Out-of-range records are
  * skipped and counted as A's skips in the workspace status block.
- * ws: at least tcu_workspace_bytes(...) for any shapes (256 bytes suffice). */
+ * ws: 256-byte aligned, at least 256 bytes (the status block).  With
+ * tcu_encode_workspace_bytes(R, rows, cols) bytes, a matrix of 1 GiB or more
+ * is filled one window of rows at a time (about 128 MiB each: the records are
+ * first partitioned by window, then each window is zeroed and filled while it
+ * stays in the last-level cache); with less, in one pass.  Same result. */
 tcu_status tcu_encode(const tcu_relation *R, int transpose, int32_t rows, int32_t cols,
                       double *out, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Workspace bytes with which tcu_encode fills this matrix window by window:
+ * 256 plus, for matrices of at least 1 GiB, a scratch of about (4 + value
+ * size) bytes per record (the records' cell offsets and values, ordered by
+ * window).  Returns 256 where the one-pass fill is used anyway, 0 for
+ * invalid arguments. */
+size_t tcu_encode_workspace_bytes(const tcu_relation *R, int32_t rows, int32_t cols);
 
 /* Step a0 host part, the mixed forms' precision plan (the feasibility test
  * of Section 4.2.1 retargeted: a cheap look at the operands' magnitudes
@@ -341,7 +356,8 @@ typedef struct {
     hipEvent_t begin, end;  /* the caller's events                         */
     int32_t kernel;         /* tcu_kernel_id                               */
     int32_t m, n, k;        /* output rows, columns, contraction length    */
-    int32_t planes;         /* moduli or digit slices (1 for FP64)         */
+    int32_t planes;         /* moduli or digit slices (1 for FP64); for an
+                               encoding, its row windows (1: one pass)     */
     double ops;             /* algorithmic operations of the launch        */
 } tcu_launch_record;
 tcu_status tcu_trace_launches(tcu_launch_record *records, int32_t capacity, int32_t *count);

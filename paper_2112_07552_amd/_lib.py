@@ -45,7 +45,8 @@ TCU_NOALLOC_MAX_BYTES = (64 << 20) + (64 << 10)
 TCU_BWD_SAVED_ENCODINGS = 1
 
 EXPORTS = (
-    "tcu_workspace_bytes", "tcu_mixed_plan", "tcu_split", "tcu_encode", "tcu_gemm_f64",
+    "tcu_workspace_bytes", "tcu_mixed_plan", "tcu_split", "tcu_encode",
+    "tcu_encode_workspace_bytes", "tcu_gemm_f64",
     "tcu_gemm_f64_workspace_bytes", "tcu_gemm_f64_ws",
     "tcu_join_agg_fwd", "tcu_join_agg_fwd_noalloc", "tcu_join_agg_bwd", "tcu_dict_workspace_bytes", "tcu_dict_encode",
     "tcu_join_agg_row_workspace_bytes", "tcu_join_agg_row",
@@ -112,6 +113,8 @@ def load():
     L.tcu_split.restype = C.c_int
     L.tcu_encode.argtypes = [rel_p, C.c_int, i32, i32, vp, vp, C.c_size_t, vp]
     L.tcu_encode.restype = C.c_int
+    L.tcu_encode_workspace_bytes.argtypes = [rel_p, i32, i32]
+    L.tcu_encode_workspace_bytes.restype = C.c_size_t
     L.tcu_gemm_f64.argtypes = [C.c_int, C.c_int, i32, i32, i32, vp, i64, vp, i64, vp, i64, vp]
     L.tcu_gemm_f64.restype = C.c_int
     L.tcu_gemm_f64_workspace_bytes.argtypes = [i32, i32, i32]

@@ -195,18 +195,48 @@ T *at(void *ws, size_t off) {
     return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
 }
 
+// Scratch for window-by-window encodings: the workspace past the layout's
+// end, when the caller sized it with the relations (tcu_workspace_bytes);
+// a workspace without it encodes in one pass.
+struct EncScratch {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+size_t enc_scratch_bytes(const tcu_relation *A, const tcu_relation *B, int32_t M, int32_t K,
+                         int32_t N) {
+    if (A == nullptr || B == nullptr) return 0;
+    return std::max(encode_scratch_bytes(*A, M, K), encode_scratch_bytes(*B, K, N));
+}
+
+EncScratch enc_scratch(void *ws, size_t ws_bytes, const Layout &L, const tcu_relation *A,
+                       const tcu_relation *B, int32_t M, int32_t K, int32_t N) {
+    EncScratch e;
+    const size_t need = enc_scratch_bytes(A, B, M, K, N);
+    if (need > 0 && ws_bytes >= L.total + need) {
+        e.p = static_cast<char *>(ws) + L.total;
+        e.bytes = ws_bytes - L.total;
+    }
+    return e;
+}
+
+// One relation's encoding on stream s (the matrix zeroed, then the records
+// placed; window by window for large matrices when there is scratch).
+hipError_t encode_one(const tcu_relation &R, int which, int rows, int cols, double *Z,
+                      StatusBlock *st, const EncScratch &sc, hipStream_t s) {
+    return launch_encode_zeroed(R, which, rows, cols, Z, st, which, sc.p, sc.bytes, s);
+}
+
 // X (M x K) and Y (K x N) from the records; `count_only` encodes ones.
 hipError_t encode_both(const tcu_relation &A, const tcu_relation &B, int32_t M, int32_t K,
                        int32_t N, double *X, double *Y, StatusBlock *st, bool count_only,
-                       hipStream_t s) {
+                       const EncScratch &sc, hipStream_t s) {
     tcu_relation a = A, b = B;
     if (count_only) { a.val = nullptr; b.val = nullptr; }
     // each matrix is zeroed right before its scatter, so its freshly written
     // lines are still in the caches when the random 8-byte stores land
-    hipError_t e = launch_zero_f64(X, (size_t)M * K, s);
-    if (e == hipSuccess) e = launch_encode(a, 0, M, K, X, st, 0, s);
-    if (e == hipSuccess) e = launch_zero_f64(Y, (size_t)K * N, s);
-    if (e == hipSuccess) e = launch_encode(b, 1, K, N, Y, st, 1, s);
+    hipError_t e = encode_one(a, 0, M, K, X, st, sc, s);
+    if (e == hipSuccess) e = encode_one(b, 1, K, N, Y, st, sc, s);
     return e;
 }
 
@@ -359,14 +389,6 @@ hipError_t mixed_product(const SplitOperand &a, const SplitOperand &b, int m, in
     return e;
 }
 
-// One relation's encoding on stream s: zero the matrix, scatter the records.
-hipError_t encode_one(const tcu_relation &R, int which, int rows, int cols, double *Z,
-                      StatusBlock *st, hipStream_t s) {
-    hipError_t e = launch_zero_f64(Z, (size_t)rows * cols, s);
-    if (e == hipSuccess) e = launch_encode(R, which, rows, cols, Z, st, which, s);
-    return e;
-}
-
 // The adjoint's second stream: one non-blocking stream (default priority) per
 // device, created on first use and kept for the life of the process.  Work
 // on it is ordered against the caller's stream by events only, so a call
@@ -451,7 +473,8 @@ size_t tcu_workspace_bytes(const tcu_relation *A, const tcu_relation *B, int32_t
                            int32_t N, tcu_precision p, int flags) {
     if (!shapes_ok(M, K, N)) return 0;
     if (!precision_ok(p)) return 0;
-    return plan_layout(M, K, N, p, flags, count_planes(A, B, flags)).total;
+    return plan_layout(M, K, N, p, flags, count_planes(A, B, flags)).total +
+           enc_scratch_bytes(A, B, M, K, N);
 }
 
 int tcu_mixed_plan(tcu_precision p, int32_t k, double tol, uint32_t need, double u,
@@ -485,9 +508,17 @@ tcu_status tcu_encode(const tcu_relation *R, int transpose, int32_t rows, int32_
     if (!ws_ok(ws, ws_bytes, sizeof(StatusBlock))) return TCU_ERR_WORKSPACE;
     StatusBlock *st = at<StatusBlock>(ws, 0);
     TCU_TRY(launch_clear_status(st, stream));
-    TCU_TRY(launch_zero_f64(out, (size_t)rows * (size_t)cols, stream));
-    TCU_TRY(launch_encode(*R, transpose, rows, cols, out, st, 0, stream));
+    // the workspace past the status block, if large enough, lets a large
+    // matrix be filled window by window
+    TCU_TRY(launch_encode_zeroed(*R, transpose, rows, cols, out, st, 0,
+                                 static_cast<char *>(ws) + sizeof(StatusBlock),
+                                 ws_bytes - sizeof(StatusBlock), stream));
     return TCU_OK;
+}
+
+size_t tcu_encode_workspace_bytes(const tcu_relation *R, int32_t rows, int32_t cols) {
+    if (!relation_ok(R) || rows < 1 || cols < 1) return 0;
+    return sizeof(StatusBlock) + encode_scratch_bytes(*R, rows, cols);
 }
 
 tcu_status tcu_gemm_f64(int trans_a, int trans_b, int32_t m, int32_t n, int32_t k,
@@ -549,6 +580,7 @@ tcu_status tcu::join_agg_fwd_ws(const tcu_relation *A, const tcu_relation *B, in
     if (!ws_ok(ws, ws_bytes, L.total)) return TCU_ERR_WORKSPACE;
     StatusBlock *st = at<StatusBlock>(ws, 0);
     double *X = at<double>(ws, L.x), *Y = at<double>(ws, L.y);
+    const EncScratch sc = enc_scratch(ws, ws_bytes, L, A, B, M, K, N);
 
     TCU_TRY(launch_clear_status(st, stream));
     if (planes) {
@@ -564,12 +596,12 @@ tcu_status tcu::join_agg_fwd_ws(const tcu_relation *A, const tcu_relation *B, in
         // partial sum is a non-negative integer no larger than the count, so a
         // count below 2^53 is exact), C as scratch; counts beyond int32 are
         // saturated and flagged
-        TCU_TRY(encode_both(*A, *B, M, K, N, X, Y, nullptr, true, stream));
+        TCU_TRY(encode_both(*A, *B, M, K, N, X, Y, nullptr, true, sc, stream));
         TCU_TRY(launch_gemm_f64(0, 0, M, N, K, X, K, Y, N, C, N, stream));
         TCU_TRY(launch_f64_to_i32(C, count, (size_t)M * N, st, stream));
     }
     if (!is_split(p)) {
-        TCU_TRY(encode_both(*A, *B, M, K, N, X, Y, st, false, stream));
+        TCU_TRY(encode_both(*A, *B, M, K, N, X, Y, st, false, sc, stream));
         TCU_TRY(launch_gemm_f64(0, 0, M, N, K, X, K, Y, N, C, N, stream));
         return TCU_OK;
     }
@@ -579,9 +611,9 @@ tcu_status tcu::join_agg_fwd_ws(const tcu_relation *A, const tcu_relation *B, in
     // X: M lines (rows) of length K; Y: N lines (columns) of length K
     const SplitOperand a{X, M, K, K, 0}, b{Y, K, N, N, 1};
     TCU_TRY(launch_reset_plan(st, stream));
-    TCU_TRY(encode_one(*A, 0, M, K, X, st, stream));
+    TCU_TRY(encode_one(*A, 0, M, K, X, st, sc, stream));
     TCU_TRY(certify_prepare(a, false, ws, L, st, stream));
-    TCU_TRY(encode_one(*B, 1, K, N, Y, st, stream));
+    TCU_TRY(encode_one(*B, 1, K, N, Y, st, sc, stream));
     TCU_TRY(certify_prepare(b, true, ws, L, st, stream));
     TCU_TRY(finish_product(a, b, M, N, K, p, tol, ws, L, st, C, N, stream));
     return TCU_OK;
@@ -612,6 +644,9 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
     StatusBlock *st = at<StatusBlock>(ws, 0);
     double *X = at<double>(ws, L.x), *Y = at<double>(ws, L.y);
     double *G = at<double>(ws, L.g), *G2 = at<double>(ws, L.g2);
+    // Y's re-encoding ends (stream order) before X's starts on the side
+    // stream, so the two share the scratch
+    const EncScratch sc = enc_scratch(ws, ws_bytes, L, A, B, M, K, N);
 
     if (dA_val == nullptr && dB_val == nullptr) return TCU_OK;
     const bool saved = (flags & TCU_BWD_SAVED_ENCODINGS) != 0;
@@ -636,15 +671,15 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
     if (!saved) {
         // activation checkpointing: the encodings are rebuilt from the records
         TCU_TRY(launch_clear_status(st, stream));
-        TCU_TRY(encode_one(*B, 1, K, N, Y, st, stream));
+        TCU_TRY(encode_one(*B, 1, K, N, Y, st, sc, stream));
         if (both) {
             TCU_TRY(hipEventRecord(ev_fork, stream));
             TCU_TRY(hipStreamWaitEvent(side, ev_fork, 0));
             evs.forked(side, stream);
-            TCU_TRY(encode_one(*A, 0, M, K, X, st, side));
+            TCU_TRY(encode_one(*A, 0, M, K, X, st, sc, side));
             TCU_TRY(hipEventRecord(ev_x, side));
         } else {
-            TCU_TRY(encode_one(*A, 0, M, K, X, st, stream));
+            TCU_TRY(encode_one(*A, 0, M, K, X, st, sc, stream));
         }
     }
     if (dA_val != nullptr) {

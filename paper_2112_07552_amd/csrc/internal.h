@@ -91,6 +91,15 @@ hipError_t launch_set_plan(StatusBlock *st, uint32_t slices, uint32_t bits, uint
                            bool fallback, hipStream_t s);
 hipError_t launch_encode(const tcu_relation &R, int transpose, int rows, int cols, double *out,
                          StatusBlock *st, int which, hipStream_t s);
+// The whole encoding of one relation: out zeroed, then the records placed.
+// Matrices of at least 1 GiB go window by window when `scratch` holds
+// encode_scratch_bytes(R, rows, cols) bytes (256-byte aligned); otherwise
+// (scratch NULL or too small, or a smaller matrix) one zero pass and one
+// scatter.  Same result either way.
+size_t encode_scratch_bytes(const tcu_relation &R, int rows, int cols);
+hipError_t launch_encode_zeroed(const tcu_relation &R, int transpose, int rows, int cols,
+                                double *out, StatusBlock *st, int which, void *scratch,
+                                size_t scratch_bytes, hipStream_t s);
 // dst[i] = src[row_i, col_i] for the records whose row lies in [r0, r1)
 // (r1 < 0: all rows); the launch with r0 = 0 also writes 0 for records
 // outside the matrix.

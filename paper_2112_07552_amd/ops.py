@@ -139,17 +139,21 @@ def unblock_slices(slices: torch.Tensor, lines: int, length: int, lines_pad: int
 
 def encode(group, key, val, rows: int, cols: int, transpose: bool = False,
            out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
-           unique: bool = False) -> torch.Tensor:
+           unique: bool = False, windows: bool = True) -> torch.Tensor:
     """Step a1 (Sections 3.1/3.3): dense FP64 encoding of one relation.
 
-    transpose=False: out[group, key] (A -> X);  True: out[key, group] (B -> Y)."""
+    transpose=False: out[group, key] (A -> X);  True: out[key, group] (B -> Y).
+    windows: give the library the scratch with which it fills a matrix of
+    1 GiB or more one window of rows at a time (tcu_encode_workspace_bytes);
+    False, or a smaller `ws`, fills it in one pass (same result)."""
     rel = make_relation(group, key, val, unique)
     dev = group.device
     if out is None:
         out = torch.empty((rows, cols), dtype=torch.float64, device=dev)
     _need_out(out, (rows, cols), dev)
     if ws is None:
-        ws = alloc_workspace(256, dev)
+        need = _lib.load().tcu_encode_workspace_bytes(C.byref(rel), rows, cols) if windows else 0
+        ws = alloc_workspace(max(256, need), dev)
     check(_lib.load().tcu_encode(C.byref(rel), int(transpose), rows, cols, _ptr(out), _ptr(ws),
                                  ws.numel(), _stream(dev)), "tcu_encode")
     return out

@@ -58,6 +58,58 @@ def test_workspace_bytes(lib):
     assert lib.tcu_workspace_bytes(C.byref(A), C.byref(B), M, K, N, 7, 0) == 0
 
 
+def _window_scratch(n, rows, cols, vb):
+    """The window-by-window encoding's scratch as documented in encode.hip:
+    window totals and offsets, a run table of windows x workgroups (8192
+    records each), and per slot (records plus up to 31 per run) a 4-byte
+    cell offset and a value."""
+    align = lambda x: (x + 255) // 256 * 256
+    wrows = min(max(1, (128 << 20) // (cols * 8)), rows)
+    wrows = max(wrows, -(-rows // 1024))
+    nw = -(-rows // wrows)
+    nwg = -(-n // 8192)
+    table = nw * nwg
+    slots = n + 31 * table
+    return align((2 * 1024 + 1) * 8) + align(4 * table) + align(4 * slots) + align(vb * slots)
+
+
+def test_encode_window_scratch_sizes(lib):
+    """Encodings of 1 GiB or more get the partition's scratch; smaller ones
+    none (a one-pass fill needs only the status block)."""
+    n = 1 << 30
+    for dtype, vb in ((_lib.TCU_F32, 4), (_lib.TCU_F64, 8)):
+        R = rel(n, dtype)
+        assert lib.tcu_encode_workspace_bytes(C.byref(R), 32768, 32768) == \
+            256 + _window_scratch(n, 32768, 32768, vb)
+    # 64 windows of 512 rows, 131072 workgroups: 8 GiB of slots for FP32 values
+    assert _window_scratch(n, 32768, 32768, 4) < 10.5 * 2 ** 30
+    # no values (a 0/1 encoding): cell offsets only
+    R0 = _lib.tcu_relation(n, 0x1000, 0x1000, None, _lib.TCU_F64, 0)
+    assert lib.tcu_encode_workspace_bytes(C.byref(R0), 32768, 32768) == \
+        256 + _window_scratch(n, 32768, 32768, 0)
+    # below 1 GiB: one pass, status block only
+    R = rel(1 << 24)
+    assert lib.tcu_encode_workspace_bytes(C.byref(R), 4096, 4096) == 256
+    assert lib.tcu_encode_workspace_bytes(C.byref(R), 8192, 16383) == 256
+    assert lib.tcu_encode_workspace_bytes(C.byref(R), 16384, 8192) == \
+        256 + _window_scratch(1 << 24, 16384, 8192, 8)
+    # a tall matrix is cut into at most 1024 windows
+    tall = (1 << 31) - 1
+    assert lib.tcu_encode_workspace_bytes(C.byref(R), tall, 128) == \
+        256 + _window_scratch(1 << 24, tall, 128, 8)
+    assert lib.tcu_encode_workspace_bytes(C.byref(R), 0, 8192) == 0
+    # the operator's workspace holds the larger operand's scratch when given
+    # the relations, and none without them
+    A, B = rel(n, _lib.TCU_F32), rel(n // 2, _lib.TCU_F64)
+    M = K = N = 32768
+    with_rel = lib.tcu_workspace_bytes(C.byref(A), C.byref(B), M, K, N, 3, _lib.TCU_WS_BACKWARD)
+    without = lib.tcu_workspace_bytes(None, None, M, K, N, 3, _lib.TCU_WS_BACKWARD)
+    assert with_rel - without == max(_window_scratch(n, M, K, 4), _window_scratch(n // 2, K, N, 8))
+    small_a, small_b = rel(1 << 24), rel(1 << 24)
+    assert lib.tcu_workspace_bytes(C.byref(small_a), C.byref(small_b), 4096, 4096, 4096, 0, 0) == \
+        lib.tcu_workspace_bytes(None, None, 4096, 4096, 4096, 0, 0)
+
+
 def test_argument_errors_return_before_launch(lib):
     A, B = rel(10), rel(10)
     cbuf = C.c_void_p(0x2000)
