@@ -392,6 +392,12 @@ constexpr int kCrtLenAlign = 64 * CrtCfg::NS;
 #define CRT_KCHUNK 8192
 #endif
 constexpr int kCrtChunk = CRT_KCHUNK;
+// workgroups per launch of the residue products, at most (and at least the
+// workgroups of one modulus): the moduli of a product are grouped into
+// launches of about 64 rounds of workgroups (measured: at 32768^3, one
+// modulus per launch 442 ms against 462 ms for all 15 moduli in one launch;
+// at 4096^3 one launch of all 14, 0.81 ms, against 0.86 ms one per launch)
+constexpr int64_t kCrtLaunchWgs = 16384;
 static_assert(kCrtChunk % kCrtLenAlign == 0, "chunks hold whole unrolled rounds");
 
 template <int V>
@@ -874,7 +880,6 @@ hipError_t launch_gemm_crt(int m, int n, int k, int L, int bits, const int8_t *x
     const CrtConsts cc = make_consts(L, bits);
     const int nblk = len_pad / 32;
     const int tiles_m = (m + CrtCfg::BM - 1) / CrtCfg::BM, tiles_n = (n + CrtCfg::BN - 1) / CrtCfg::BN;
-    const int64_t wgs = (int64_t)tiles_m * tiles_n * L;
     const int64_t plane_res = crt_residue_plane(m, n);
     using G = CrtCfg;
     const CertArgs none{};
@@ -882,25 +887,42 @@ hipError_t launch_gemm_crt(int m, int n, int k, int L, int bits, const int8_t *x
     hipError_t e = hipSuccess;
     {
         TraceScope ts(TCU_KERNEL_GEMM_CRT, m, n, k, L, L * 2.0 * m * n * (double)k, s);
-        // Contractions longer than kCrtChunk run as launches over chunks of k:
-        // the workgroups of one launch start together and stream the same
-        // k-slices of shared panels, so a chunk keeps them close enough in k
-        // for the caches to serve each slice to all of them; each later
-        // chunk adds the residues the earlier ones left.
-        for (int k0 = 0; k0 < len_pad && e == hipSuccess; k0 += kCrtChunk) {
-            const int kn = std::min(kCrtChunk, len_pad - k0);
-            // a chunk starts k0 / 32 k-steps into each plane: k0 bytes per line
-            const int8_t *xc = xs + (int64_t)k0 * x_lines_pad, *yc = ys + (int64_t)k0 * y_lines_pad;
-            // |sum| <= kn 2^14 (residues at most 128 in magnitude)
-            if (kn <= 4096 && k0 == 0)
-                gemm_crt_kernel<G, true, kEpiResidue><<<(unsigned)wgs, G::threads, 0, s>>>(
-                    m, n, kn / 32, tiles_m, tiles_n, xc, x_lines_pad, yc, y_lines_pad, px, py, cc,
-                    res, plane_res, none, nullptr, 0, 0);
-            else
-                gemm_crt_kernel<G, false, kEpiResidue><<<(unsigned)wgs, G::threads, 0, s>>>(
-                    m, n, kn / 32, tiles_m, tiles_n, xc, x_lines_pad, yc, y_lines_pad, px, py, cc,
-                    res, plane_res, none, nullptr, 0, k0 > 0 ? 1 : 0);
-            e = hipGetLastError();
+        // The workgroups of one launch start together and stream the same
+        // k-slices of shared panels, but drift apart in k over the launch's
+        // rounds, and the caches then serve each slice to fewer of them.  So
+        // a long product runs as several launches: groups of moduli, and
+        // contractions longer than kCrtChunk as chunks of k, each later chunk
+        // adding the residues the earlier ones left.
+        const int per = (int)std::max<int64_t>(
+            1, std::min<int64_t>(L, kCrtLaunchWgs / ((int64_t)tiles_m * tiles_n)));
+        for (int g0 = 0; g0 < L && e == hipSuccess; g0 += per) {
+            // moduli [g0, g0 + gn) in one launch per chunk
+            const int gn = std::min(per, L - g0);
+            CrtConsts cg = cc;
+            cg.L = gn;
+            for (int i = 0; i < gn; ++i) {
+                cg.mi[i] = cc.mi[g0 + i];
+                cg.c16[i] = cc.c16[g0 + i];
+                cg.inv_f[i] = cc.inv_f[g0 + i];
+            }
+            const int64_t gw = (int64_t)tiles_m * tiles_n * gn;
+            const int8_t *xg = xs + g0 * px, *yg = ys + g0 * py;
+            int8_t *rg = res + g0 * plane_res;
+            for (int k0 = 0; k0 < len_pad && e == hipSuccess; k0 += kCrtChunk) {
+                const int kn = std::min(kCrtChunk, len_pad - k0);
+                // a chunk starts k0 / 32 k-steps into each plane: k0 bytes per line
+                const int8_t *xc = xg + (int64_t)k0 * x_lines_pad, *yc = yg + (int64_t)k0 * y_lines_pad;
+                // |sum| <= kn 2^14 (residues at most 128 in magnitude)
+                if (kn <= 4096 && k0 == 0)
+                    gemm_crt_kernel<G, true, kEpiResidue><<<(unsigned)gw, G::threads, 0, s>>>(
+                        m, n, kn / 32, tiles_m, tiles_n, xc, x_lines_pad, yc, y_lines_pad, px, py,
+                        cg, rg, plane_res, none, nullptr, 0, 0);
+                else
+                    gemm_crt_kernel<G, false, kEpiResidue><<<(unsigned)gw, G::threads, 0, s>>>(
+                        m, n, kn / 32, tiles_m, tiles_n, xc, x_lines_pad, yc, y_lines_pad, px, py,
+                        cg, rg, plane_res, none, nullptr, 0, k0 > 0 ? 1 : 0);
+                e = hipGetLastError();
+            }
         }
     }
     if (e != hipSuccess) return e;

@@ -188,3 +188,30 @@ def test_certificate_need_matches_the_oracle(orc, precision, M, K, N, kind, tol)
         assert got[0] == info["slices"]
         if precision == "crt_i8":
             assert got[1] == info["bits"]
+
+
+def test_crt_product_in_several_launches(orc):
+    """A product with more workgroups than one launch takes: 8604^2 cells in
+    34 x 34 tiles and 15 moduli run as two launches per k-chunk (14 moduli,
+    then 1).  Sampled whole rows are still the oracle's product of the
+    truncations, and within the tolerance of the oracle's C."""
+    dev = cuda_or_skip()
+    M = N = 8604
+    K = 1024
+    tol = 1.5 * 2.0 ** -49
+    A, B = wl.mm_query(M, K, N, seed=21, values="uniform", device=dev)
+    Cg, _, ws = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, M, K, N,
+                                 precision="crt_i8", tol=tol, unique=True)
+    st, info = ops.sync_status(ws)
+    assert st == 0 and info["flags"] == 0 and info["slices"] == 15
+    rows = np.sort(np.random.default_rng(5).choice(M, 48, replace=False))
+    C = Cg[torch.as_tensor(rows, device=dev)].cpu().numpy()
+    RA, RB = to_orc(orc, A), to_orc(orc, B)
+    X, _ = orc.encode_A(RA, M, K)
+    Y, _ = orc.encode_B(RB, K, N)
+    # each row's truncation depends on that row alone
+    T = orc.trunc_product(np.ascontiguousarray(X[rows]), Y, info["bits"])
+    assert np.all(np.abs(C - T) <= 2.0 ** -50 * np.abs(T))
+    Co, _, _ = orc.join_agg(RA, RB, M, K, N, rows=rows)
+    So, _, _ = orc.join_agg(abs_rel(orc, RA), abs_rel(orc, RB), M, K, N, rows=rows)
+    assert err_cw(C, Co, So) <= tol
