@@ -387,16 +387,17 @@ constexpr int NUM_XCD = 8, GROUP_M = 4, RUN = 32;
 // k-steps of 32 per unrolled round of the main loop: the contraction length
 // of the residue planes is padded to a multiple of this
 constexpr int kCrtLenAlign = 64 * CrtCfg::NS;
-// k per launch of the residue products (a multiple of kCrtLenAlign)
-#ifndef CRT_KCHUNK
-#define CRT_KCHUNK 8192
-#endif
-constexpr int kCrtChunk = CRT_KCHUNK;
+// k per launch of the residue products (a multiple of kCrtLenAlign): every
+// int32 sum of a chunk stays below 32768 * 2^14 = 2^29 in magnitude, and a
+// contraction up to 131071 runs in at most four chunks
+constexpr int kCrtChunk = 32768;
 // workgroups per launch of the residue products, at most (and at least the
 // workgroups of one modulus): the moduli of a product are grouped into
-// launches of about 64 rounds of workgroups (measured: at 32768^3, one
-// modulus per launch 442 ms against 462 ms for all 15 moduli in one launch;
-// at 4096^3 one launch of all 14, 0.81 ms, against 0.86 ms one per launch)
+// launches of about 64 rounds of workgroups.  Measured at 32768^3, 15 moduli:
+// all moduli in one launch per 8192-long chunk of k 462 ms, one modulus per
+// launch 442 ms, and with one launch over all of k 428 ms (bands of tile rows
+// within a modulus gained nothing more); at 4096^3 one launch of all 14
+// moduli 0.81 ms against 0.86 ms one per launch.
 constexpr int64_t kCrtLaunchWgs = 16384;
 static_assert(kCrtChunk % kCrtLenAlign == 0, "chunks hold whole unrolled rounds");
 
@@ -890,8 +891,8 @@ hipError_t launch_gemm_crt(int m, int n, int k, int L, int bits, const int8_t *x
         // The workgroups of one launch start together and stream the same
         // k-slices of shared panels, but drift apart in k over the launch's
         // rounds, and the caches then serve each slice to fewer of them.  So
-        // a long product runs as several launches: groups of moduli, and
-        // contractions longer than kCrtChunk as chunks of k, each later chunk
+        // a large product runs as one launch per group of moduli; a
+        // contraction longer than kCrtChunk as chunks of k, each later chunk
         // adding the residues the earlier ones left.
         const int per = (int)std::max<int64_t>(
             1, std::min<int64_t>(L, kCrtLaunchWgs / ((int64_t)tiles_m * tiles_n)));
