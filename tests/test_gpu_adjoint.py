@@ -181,8 +181,9 @@ def test_autograd_checkpoint_modes_agree(checkpoint):
 
 def test_fwd_bwd_2pow24_records(orc):
     """2^24 records per table (N = 4096), seed 2, W = U[-1,1) (seed 1002):
-    sampled cells and Freivalds' check for C; oracle gradient on 4096 + 4096
-    sampled records; central differences (h = 1e-6) on 32 + 32 records."""
+    512 whole rows of C, 4096 sampled cells and Freivalds' check; oracle
+    gradient on 4096 + 4096 sampled records; central differences (h = 1e-6)
+    on 32 + 32 records."""
     from .test_gpu_parity import sampled_checks
     dev = cuda_or_skip()
     N = 4096
@@ -191,7 +192,7 @@ def test_fwd_bwd_2pow24_records(orc):
     Cg, _, ws = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, N, N, N,
                                  unique=True, for_backward=True)
     assert ops.sync_status(ws)[0] == 0
-    assert sampled_checks(orc, A, B, Cg, N, N, N, seed=2, ncells=4096) <= TOL
+    assert sampled_checks(orc, A, B, Cg, N, N, N, seed=2, ncells=4096, nrows=512) <= TOL
     W = wl.draw_values("uniform", N * N, 1002, 0, device=dev).reshape(N, N)
     dA, dB, ws = ops.join_agg_bwd(A.group, A.key, A.val, B.key, B.group, B.val, N, N, N, W,
                                   ws=ws, unique=True, saved_encodings=True)
