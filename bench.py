@@ -321,6 +321,27 @@ def block_errors(ref, Cm, dA, dB):
     return e
 
 
+def largest_edge(budget):
+    """The largest N (a multiple of 256) whose headline step fits in `budget`
+    bytes: both tables with FP32 values (12 B per record), W, C, dA and dB
+    (8 B each per cell or record), and the residue form's workspace with
+    backward as the library sizes it for these relations."""
+    from paper_2112_07552_amd import _lib
+
+    L = _lib.load()
+
+    def need(n):
+        rel = _lib.tcu_relation(n * n, 1, 1, 1, _lib.TCU_F32, _lib.TCU_REL_UNIQUE_CELLS)
+        ws = L.tcu_workspace_bytes(C.byref(rel), C.byref(rel), n, n, n, _lib.TCU_PREC_CRT_I8,
+                                   _lib.TCU_WS_BACKWARD)
+        return 2 * 12 * n * n + 4 * 8 * n * n + ws
+
+    n = 256
+    while need(n + 256) <= budget:
+        n += 256
+    return n
+
+
 def leg_headline(args, stream, hip):
     """2^30 records per table (N = 32768, FP32 mixture values, seed 4): the
     residue form's forward + checkpointed adjoint (the headline), its
@@ -847,7 +868,8 @@ def main():
                     help="comma-separated: headline, fp64_2pow24, mixed_2pow24, small, peaks, "
                          "queries, ooc (not in 'all'), or all")
     ap.add_argument("--n5", type=int, default=32768,
-                    help="edge of the headline workload (records per table = n5^2)")
+                    help="edge of the headline workload (records per table = n5^2); 0: the "
+                         "largest multiple of 256 whose step fits in 0.85 of the free memory")
     ap.add_argument("--block", type=int, default=256,
                     help="edge of the headline's oracle block (its CPU baseline and errors)")
     ap.add_argument("--fp64-steps", type=int, default=2,
@@ -886,6 +908,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if "headline" in legs:
+        if args.n5 == 0:
+            args.n5 = largest_edge(0.85 * torch.cuda.mem_get_info(dev)[0])
+            log(f"headline: largest edge that fits: N = {args.n5}")
         res["headline"] = leg_headline(args, stream, hip)
     if "fp64_2pow24" in legs:
         res["fp64_2pow24"] = leg_2pow24_fp64(args, stream, hip)
