@@ -135,7 +135,8 @@ typedef struct {
 /* Bytes of device workspace the calls below need for these shapes (Section
  * 3.3 encodings X and Y, plus the status block; with TCU_WS_BACKWARD the two
  * gradient matrices; in the mixed forms the certificate's planes, digit
- * slices or residues).  Given the relations (A and B not NULL), the size also
+ * slices or residues; in the FP64 form, for products with too few output
+ * tiles to fill the chip, the partial products of their split contraction).  Given the relations (A and B not NULL), the size also
  * holds the scratch with which an encoding of 1 GiB or more runs window by
  * window (tcu_encode); a workspace sized without it (A or B NULL) is still
  * accepted and encodes in one pass.  The workspace must be 256-byte aligned.

@@ -102,6 +102,7 @@ int mixed_plan(tcu_precision p, int32_t k, double tol, uint32_t need, double u,
 struct Layout {
     size_t x = 0, y = 0, g = 0, g2 = 0, mba = 0, mbb = 0, ea = 0, eb = 0, sa = 0, sb = 0, res = 0;
     size_t sxa = 0, sxb = 0, psa = 0, psb = 0, qa = 0, qb = 0;
+    size_t gsplit = 0, gsplit_bytes = 0;  // FP64 form: partial products of a split contraction
     size_t total = 0;
 };
 
@@ -176,14 +177,33 @@ Layout plan_layout(int32_t M, int32_t K, int32_t N, tcu_precision p, int flags,
             L.res = off;
             off += align_up(TCU_MAX_MODULI * out);
         }
-    } else if (with_count_planes) {
-        // the count's 0/1 planes (the mixed forms' magnitude planes hold them
-        // there)
-        L.qa = off; off += align_up(pad256(M) * qlen(K));
-        L.qb = off; off += align_up(pad256(N) * qlen(K));
+    } else {
+        if (with_count_planes) {
+            // the count's 0/1 planes (the mixed forms' magnitude planes hold
+            // them there)
+            L.qa = off; off += align_up(pad256(M) * qlen(K));
+            L.qb = off; off += align_up(pad256(N) * qlen(K));
+        }
+        // products with too few output tiles to fill the chip split their
+        // contraction over workgroups (C = X Y; with backward also dX = dC
+        // Y^T and dY = X^T dC), one partial product per k-chunk
+        size_t sp = gemm_f64_split_bytes(M, N, K);
+        if (bwd) sp = maxz(sp, maxz(gemm_f64_split_bytes(M, K, N), gemm_f64_split_bytes(K, N, M)));
+        if (sp > 0) {
+            L.gsplit = off;
+            L.gsplit_bytes = sp;
+            off += align_up(sp);
+        }
     }
     L.total = off;
     return L;
+}
+
+// The FP64 form's split-contraction partials, or NULL (no product of the
+// layout's shapes splits).
+double *split_part(void *ws, const Layout &L) {
+    return L.gsplit_bytes > 0 ? reinterpret_cast<double *>(static_cast<char *>(ws) + L.gsplit)
+                              : nullptr;
 }
 
 bool ws_ok(const void *ws, size_t ws_bytes, size_t need) {
@@ -597,12 +617,12 @@ tcu_status tcu::join_agg_fwd_ws(const tcu_relation *A, const tcu_relation *B, in
         // count below 2^53 is exact), C as scratch; counts beyond int32 are
         // saturated and flagged
         TCU_TRY(encode_both(*A, *B, M, K, N, X, Y, nullptr, true, sc, stream));
-        TCU_TRY(launch_gemm_f64(0, 0, M, N, K, X, K, Y, N, C, N, stream));
+        TCU_TRY(launch_gemm_f64_split(0, 0, M, N, K, X, K, Y, N, C, N, split_part(ws, L), stream));
         TCU_TRY(launch_f64_to_i32(C, count, (size_t)M * N, st, stream));
     }
     if (!is_split(p)) {
         TCU_TRY(encode_both(*A, *B, M, K, N, X, Y, st, false, sc, stream));
-        TCU_TRY(launch_gemm_f64(0, 0, M, N, K, X, K, Y, N, C, N, stream));
+        TCU_TRY(launch_gemm_f64_split(0, 0, M, N, K, X, K, Y, N, C, N, split_part(ws, L), stream));
         return TCU_OK;
     }
     // Mixed forms: each operand is encoded and at once reduced to its line
@@ -685,7 +705,8 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
     if (dA_val != nullptr) {
         // dX = dC * Y^T (M x K), then dA.val[i] = dX[g_i, k_i]
         if (!mixed) {
-            TCU_TRY(launch_gemm_f64(0, 1, M, K, N, dC, N, Y, N, G, K, stream));
+            TCU_TRY(launch_gemm_f64_split(0, 1, M, K, N, dC, N, Y, N, G, K, split_part(ws, L),
+                                          stream));
         } else {
             // dC: M lines (rows) of length N; Y^T: K lines = rows of Y, length N
             const SplitOperand a{dC, M, N, N, 0}, b{Y, K, N, N, 0};
@@ -719,7 +740,8 @@ tcu_status tcu_join_agg_bwd(const tcu_relation *A, const tcu_relation *B, int32_
             TCU_TRY(launch_gemm_f64(1, 0, K - k1, N, M, X + k1, K, dC, N, G2 + (size_t)k1 * N, N,
                                     stream));
         } else if (!mixed) {
-            TCU_TRY(launch_gemm_f64(1, 0, K, N, M, X, K, dC, N, G2, N, stream));
+            TCU_TRY(launch_gemm_f64_split(1, 0, K, N, M, X, K, dC, N, G2, N, split_part(ws, L),
+                                          stream));
         } else {
             // X^T: K lines = columns of X, length M; dC: N lines = columns, length M
             const SplitOperand a{X, M, K, K, 1}, b{dC, M, N, N, 1};

@@ -58,6 +58,21 @@ def test_workspace_bytes(lib):
     assert lib.tcu_workspace_bytes(C.byref(A), C.byref(B), M, K, N, 7, 0) == 0
 
 
+def test_fp64_workspace_holds_split_partials(lib):
+    """FP64 products with few output tiles split their contraction: at 1024^3
+    (64 tiles of 128 x 128) four 256-deep parts, each a 1024 x 1024 FP64
+    partial product in the workspace; at 4096^3 (1024 tiles) none."""
+    A, B = rel(1 << 20), rel(1 << 20)
+    mb = 1024 * 1024 * 8
+    assert lib.tcu_workspace_bytes(C.byref(A), C.byref(B), 1024, 1024, 1024, 0, 0) == \
+        256 + 2 * mb + 4 * mb
+    assert lib.tcu_gemm_f64_workspace_bytes(1024, 1024, 1024) == 4 * mb
+    assert lib.tcu_workspace_bytes(C.byref(A), C.byref(B), 1024, 1024, 1024, 0,
+                                   _lib.TCU_WS_BACKWARD) == 256 + 4 * mb + 4 * mb
+    big = lib.tcu_workspace_bytes(None, None, 4096, 4096, 4096, 0, 0)
+    assert big == 256 + 2 * 4096 * 4096 * 8
+
+
 def _window_scratch(n, rows, cols, vb):
     """The window-by-window encoding's scratch as documented in encode.hip:
     window totals and offsets, a run table of windows x workgroups (8192
