@@ -42,6 +42,13 @@ bool precision_ok(tcu_precision p) { return p == TCU_PREC_FP64 || is_split(p); }
 size_t pad128(int64_t x) { return (size_t)((x + 127) / 128 * 128); }
 size_t pad64(int64_t x) { return (size_t)((x + 63) / 64 * 64); }
 size_t pad256(int64_t x) { return (size_t)((x + 255) / 256 * 256); }
+// Line padding of the int8 planes of the residue form and the certificate:
+// the left operand's lines to the tile's 256 rows, the right operand's to the
+// columns of the tile its product uses (its lines are the product's columns).
+size_t padB(int64_t x) {
+    const int64_t a = crt_tile_cols(x);
+    return (size_t)((x + a - 1) / a * a);
+}
 size_t maxz(size_t a, size_t b) { return a > b ? a : b; }
 
 // Mixed forms: tolerances below 2^-50 are refused (the encodings carry 53
@@ -135,28 +142,29 @@ Layout plan_layout(int32_t M, int32_t K, int32_t N, tcu_precision p, int flags,
     if (is_split(p)) {
         const size_t digit = p == TCU_PREC_SPLIT_BF16 ? 2 : 1;
         const size_t planes = is_crt(p) ? TCU_MAX_MODULI : TCU_MAX_SLICES;
-        auto padl = [&](int64_t x) { return is_crt(p) ? pad256(x) : pad128(x); };
+        auto padlA = [&](int64_t x) { return is_crt(p) ? pad256(x) : pad128(x); };
+        auto padlB = [&](int64_t x) { return is_crt(p) ? padB(x) : pad128(x); };
         auto padk = [&](int64_t x) {
             const int64_t a = is_crt(p) ? crt_len_align() : 64;
             return (size_t)((x + a - 1) / a * a);
         };
         // (lines, length) of each operand: forward X (M, K) and Y (N, K);
         // backward W (M, N) and Y^T (K, N) for dX, X^T (K, M) and W (N, M) for dY
-        size_t la = padl(M), lb = padl(N);
-        size_t za = padl(M) * padk(K), zb = padl(N) * padk(K);
-        size_t qa = pad256(M) * qlen(K), qb = pad256(N) * qlen(K);
-        size_t na = pad256(M), nb = pad256(N);
+        size_t la = padlA(M), lb = padlB(N);
+        size_t za = padlA(M) * padk(K), zb = padlB(N) * padk(K);
+        size_t qa = pad256(M) * qlen(K), qb = padB(N) * qlen(K);
+        size_t na = pad256(M), nb = padB(N);
         // CRT: per-modulus residues of each product (m x n, rows padded to 32)
         size_t out = (size_t)crt_residue_plane(M, N);
         if (bwd) {
-            la = maxz(la, padl(K));
-            lb = maxz(lb, padl(K));
-            za = maxz(za, maxz(padl(M) * padk(N), padl(K) * padk(M)));
-            zb = maxz(zb, maxz(padl(K) * padk(N), padl(N) * padk(M)));
+            la = maxz(la, padlA(K));
+            lb = maxz(lb, padlB(K));
+            za = maxz(za, maxz(padlA(M) * padk(N), padlA(K) * padk(M)));
+            zb = maxz(zb, maxz(padlB(K) * padk(N), padlB(N) * padk(M)));
             qa = maxz(qa, maxz(pad256(M) * qlen(N), pad256(K) * qlen(M)));
-            qb = maxz(qb, maxz(pad256(K) * qlen(N), pad256(N) * qlen(M)));
+            qb = maxz(qb, maxz(padB(K) * qlen(N), padB(N) * qlen(M)));
             na = maxz(na, pad256(K));
-            nb = maxz(nb, pad256(K));
+            nb = maxz(nb, padB(K));
             out = maxz(out, maxz((size_t)crt_residue_plane(M, K), (size_t)crt_residue_plane(K, N)));
         }
         la = maxz(la, na);
@@ -182,7 +190,7 @@ Layout plan_layout(int32_t M, int32_t K, int32_t N, tcu_precision p, int flags,
             // the count's 0/1 planes (the mixed forms' magnitude planes hold
             // them there)
             L.qa = off; off += align_up(pad256(M) * qlen(K));
-            L.qb = off; off += align_up(pad256(N) * qlen(K));
+            L.qb = off; off += align_up(padB(N) * qlen(K));
         }
         // products with too few output tiles to fill the chip split their
         // contraction over workgroups (C = X Y; with backward also dX = dC
@@ -291,7 +299,8 @@ hipError_t certify_prepare(const SplitOperand &o, bool second, void *ws, const L
     return launch_mag_plane(o.Z, o.rows, o.cols, o.ld, o.axis, mb, ps,
                             at<double>(ws, second ? L.sxb : L.sxa),
                             second ? &st->umax_b : &st->umax_a,
-                            at<int8_t>(ws, second ? L.qb : L.qa), (int)pad256(lines),
+                            at<int8_t>(ws, second ? L.qb : L.qa),
+                            (int)(second ? padB(lines) : pad256(lines)),
                             (int)qlen(len), s);
 }
 
@@ -315,7 +324,7 @@ hipError_t certify_and_plan(int m, int n, int k, tcu_precision p, double tol, vo
     ca.need_bits = &st->need_bits;
     ca.need_slices = &st->need_slices;
     hipError_t e = launch_certify(m, n, k, at<int8_t>(ws, L.qa), (int)pad256(m),
-                                  at<int8_t>(ws, L.qb), (int)pad256(n), (int)qlen(k), ca,
+                                  at<int8_t>(ws, L.qb), (int)padB(n), (int)qlen(k), ca,
                                   !is_crt(p), s);
     if (e != hipSuccess) return e;
     StatusBlock host;
@@ -338,7 +347,7 @@ hipError_t certify_and_plan(int m, int n, int k, tcu_precision p, double tol, vo
         if (is_crt(p)) {
             mp->len_pad = (int)qlen(k);
             mp->la = (int)pad256(m);
-            mp->lb = (int)pad256(n);
+            mp->lb = (int)padB(n);
         } else {
             mp->len_pad = (int)pad64(k);
             mp->la = (int)pad128(m);
@@ -608,8 +617,8 @@ tcu_status tcu::join_agg_fwd_ws(const tcu_relation *A, const tcu_relation *B, in
         // int8 product with exact int32 sums (K < 2^31)
         int8_t *qa = at<int8_t>(ws, L.qa), *qb = at<int8_t>(ws, L.qb);
         TCU_TRY(launch_count_planes(*A, M, K, qa, (int)pad256(M), (int)qlen(K), stream));
-        TCU_TRY(launch_count_planes(*B, N, K, qb, (int)pad256(N), (int)qlen(K), stream));
-        TCU_TRY(launch_count_product(M, N, K, qa, (int)pad256(M), qb, (int)pad256(N),
+        TCU_TRY(launch_count_planes(*B, N, K, qb, (int)padB(N), (int)qlen(K), stream));
+        TCU_TRY(launch_count_product(M, N, K, qa, (int)pad256(M), qb, (int)padB(N),
                                      (int)qlen(K), count, N, stream));
     } else if (count != nullptr) {
         // the multiplicity encodings of Section 3.1, multiplied in FP64 (every

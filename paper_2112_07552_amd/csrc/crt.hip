@@ -378,11 +378,17 @@ struct Cfg {
     static_assert(2 * (PX + PY) % NW == 0, "planes must split evenly over the waves");
 };
 // 256 x 256 tiles, 8 waves, 4 stages of 32 KB (128 KB of LDS, one workgroup
-// per CU).
-#ifndef CRT_CFG
-#define CRT_CFG Cfg<256, 8, 4, 2>
-#endif
-using CrtCfg = CRT_CFG;
+// per CU); for wide outputs 256 x 384 tiles, 8 waves of 128 x 96, 4 stages of
+// 40 KB (all 160 KB of the CU's LDS, 256 VGPRs): a third fewer LDS fragment
+// reads and operand-panel bytes per MFMA.  Measured: the 2^30-record step
+// 1535 against 1586 ms; at 4096^3 the narrow tile fills the chip better
+// (0.84 against 0.85 ms, certificate 0.103 against 0.118 ms).
+using CrtCfg = Cfg<256, 8, 4, 2>;
+using CrtCfgWide = Cfg<384, 8, 4, 2>;
+static_assert(CrtCfg::NS == CrtCfgWide::NS && CrtCfg::BM == CrtCfgWide::BM,
+              "both tile shapes share the plane layout's length padding and row tiles");
+// output width from which products use the wide tile
+constexpr int kWideTileN = 16384;
 constexpr int NUM_XCD = 8, GROUP_M = 4, RUN = 32;
 // k-steps of 32 per unrolled round of the main loop: the contraction length
 // of the residue planes is padded to a multiple of this
@@ -853,6 +859,7 @@ int crt_max_moduli() { return kMaxMod; }
 int64_t crt_residue_plane(int64_t m, int64_t n) { return (m + 31) / 32 * 32 * n; }
 
 int crt_len_align() { return kCrtLenAlign; }
+int crt_tile_cols(int64_t n) { return n >= kWideTileN ? CrtCfgWide::BN : CrtCfg::BN; }
 
 hipError_t launch_crt_split(const double *Z, int rows, int cols, int64_t ld, int axis,
                             const unsigned long long *maxbits, int L, int bits, int8_t *out,
@@ -870,61 +877,97 @@ hipError_t launch_crt_split(const double *Z, int rows, int cols, int64_t ld, int
     return hipGetLastError();
 }
 
+namespace {
+
+// The residue products on tile shape G (see launch_gemm_crt).
+template <typename G>
+hipError_t gemm_crt_launches(int m, int n, int k, const CrtConsts &cc, const int8_t *xs,
+                             int x_lines_pad, const int8_t *ys, int y_lines_pad, int len_pad,
+                             int8_t *res, int64_t plane_res, hipStream_t s) {
+    const int L = cc.L;
+    const int tiles_m = (m + G::BM - 1) / G::BM, tiles_n = (n + G::BN - 1) / G::BN;
+    const CertArgs none{};
+    const int64_t px = (int64_t)x_lines_pad * len_pad, py = (int64_t)y_lines_pad * len_pad;
+    hipError_t e = hipSuccess;
+    // The workgroups of one launch start together and stream the same
+    // k-slices of shared panels, but drift apart in k over the launch's
+    // rounds, and the caches then serve each slice to fewer of them.  So a
+    // large product runs as one launch per group of moduli; a contraction
+    // longer than kCrtChunk as chunks of k, each later chunk adding the
+    // residues the earlier ones left.
+    const int per = (int)std::max<int64_t>(
+        1, std::min<int64_t>(L, kCrtLaunchWgs / ((int64_t)tiles_m * tiles_n)));
+    for (int g0 = 0; g0 < L && e == hipSuccess; g0 += per) {
+        // moduli [g0, g0 + gn) in one launch per chunk
+        const int gn = std::min(per, L - g0);
+        CrtConsts cg = cc;
+        cg.L = gn;
+        for (int i = 0; i < gn; ++i) {
+            cg.mi[i] = cc.mi[g0 + i];
+            cg.c16[i] = cc.c16[g0 + i];
+            cg.inv_f[i] = cc.inv_f[g0 + i];
+        }
+        const int64_t gw = (int64_t)tiles_m * tiles_n * gn;
+        const int8_t *xg = xs + g0 * px, *yg = ys + g0 * py;
+        int8_t *rg = res + g0 * plane_res;
+        for (int k0 = 0; k0 < len_pad && e == hipSuccess; k0 += kCrtChunk) {
+            const int kn = std::min(kCrtChunk, len_pad - k0);
+            // a chunk starts k0 / 32 k-steps into each plane: k0 bytes per line
+            const int8_t *xc = xg + (int64_t)k0 * x_lines_pad, *yc = yg + (int64_t)k0 * y_lines_pad;
+            // |sum| <= kn 2^14 (residues at most 128 in magnitude)
+            if (kn <= 4096 && k0 == 0)
+                gemm_crt_kernel<G, true, kEpiResidue><<<(unsigned)gw, G::threads, 0, s>>>(
+                    m, n, kn / 32, tiles_m, tiles_n, xc, x_lines_pad, yc, y_lines_pad, px, py,
+                    cg, rg, plane_res, none, nullptr, 0, 0);
+            else
+                gemm_crt_kernel<G, false, kEpiResidue><<<(unsigned)gw, G::threads, 0, s>>>(
+                    m, n, kn / 32, tiles_m, tiles_n, xc, x_lines_pad, yc, y_lines_pad, px, py,
+                    cg, rg, plane_res, none, nullptr, 0, k0 > 0 ? 1 : 0);
+            e = hipGetLastError();
+        }
+    }
+    return e;
+}
+
+// The certificate's or the counts' int8 product on tile shape G.
+template <typename G, int EPI>
+hipError_t gemm_crt_single(int m, int n, int k, const int8_t *qa, int a_lines_pad,
+                           const int8_t *qb, int b_lines_pad, int len_pad, const CertArgs &ca,
+                           int32_t *count, int64_t ldc, hipStream_t s) {
+    const CrtConsts cc = make_consts(1, 0);
+    const int tiles_m = (m + G::BM - 1) / G::BM, tiles_n = (n + G::BN - 1) / G::BN;
+    const int64_t pa = (int64_t)a_lines_pad * len_pad, pb = (int64_t)b_lines_pad * len_pad;
+    gemm_crt_kernel<G, false, EPI><<<(unsigned)(tiles_m * tiles_n), G::threads, 0, s>>>(
+        m, n, len_pad / 32, tiles_m, tiles_n, qa, a_lines_pad, qb, b_lines_pad, pa, pb, cc,
+        nullptr, 0, ca, count, ldc, 0);
+    return hipGetLastError();
+}
+
+// Operand planes fit the tile shape the product of width n uses.
+bool crt_planes_ok(int m, int n, int k, int a_lines_pad, int b_lines_pad, int len_pad) {
+    return a_lines_pad % CrtCfg::BM == 0 && b_lines_pad % crt_tile_cols(n) == 0 &&
+           len_pad % kCrtLenAlign == 0 && len_pad >= k && a_lines_pad >= m && b_lines_pad >= n;
+}
+
+}  // namespace
+
 hipError_t launch_gemm_crt(int m, int n, int k, int L, int bits, const int8_t *xs, int x_lines_pad,
                            const int8_t *ys, int y_lines_pad, int len_pad, int8_t *res,
                            const int *ex, const int *ey, double *C, int64_t ldc, int accumulate,
                            hipStream_t s) {
     if (m == 0 || n == 0) return hipSuccess;
-    if (x_lines_pad % CrtCfg::BM || y_lines_pad % CrtCfg::BN || len_pad % kCrtLenAlign || len_pad < k ||
-        x_lines_pad < m || y_lines_pad < n || L < 1 || L > kMaxMod)
+    if (!crt_planes_ok(m, n, k, x_lines_pad, y_lines_pad, len_pad) || L < 1 || L > kMaxMod)
         return hipErrorInvalidValue;
     const CrtConsts cc = make_consts(L, bits);
-    const int nblk = len_pad / 32;
-    const int tiles_m = (m + CrtCfg::BM - 1) / CrtCfg::BM, tiles_n = (n + CrtCfg::BN - 1) / CrtCfg::BN;
     const int64_t plane_res = crt_residue_plane(m, n);
-    using G = CrtCfg;
-    const CertArgs none{};
-    const int64_t px = (int64_t)x_lines_pad * len_pad, py = (int64_t)y_lines_pad * len_pad;
-    hipError_t e = hipSuccess;
+    hipError_t e;
     {
         TraceScope ts(TCU_KERNEL_GEMM_CRT, m, n, k, L, L * 2.0 * m * n * (double)k, s);
-        // The workgroups of one launch start together and stream the same
-        // k-slices of shared panels, but drift apart in k over the launch's
-        // rounds, and the caches then serve each slice to fewer of them.  So
-        // a large product runs as one launch per group of moduli; a
-        // contraction longer than kCrtChunk as chunks of k, each later chunk
-        // adding the residues the earlier ones left.
-        const int per = (int)std::max<int64_t>(
-            1, std::min<int64_t>(L, kCrtLaunchWgs / ((int64_t)tiles_m * tiles_n)));
-        for (int g0 = 0; g0 < L && e == hipSuccess; g0 += per) {
-            // moduli [g0, g0 + gn) in one launch per chunk
-            const int gn = std::min(per, L - g0);
-            CrtConsts cg = cc;
-            cg.L = gn;
-            for (int i = 0; i < gn; ++i) {
-                cg.mi[i] = cc.mi[g0 + i];
-                cg.c16[i] = cc.c16[g0 + i];
-                cg.inv_f[i] = cc.inv_f[g0 + i];
-            }
-            const int64_t gw = (int64_t)tiles_m * tiles_n * gn;
-            const int8_t *xg = xs + g0 * px, *yg = ys + g0 * py;
-            int8_t *rg = res + g0 * plane_res;
-            for (int k0 = 0; k0 < len_pad && e == hipSuccess; k0 += kCrtChunk) {
-                const int kn = std::min(kCrtChunk, len_pad - k0);
-                // a chunk starts k0 / 32 k-steps into each plane: k0 bytes per line
-                const int8_t *xc = xg + (int64_t)k0 * x_lines_pad, *yc = yg + (int64_t)k0 * y_lines_pad;
-                // |sum| <= kn 2^14 (residues at most 128 in magnitude)
-                if (kn <= 4096 && k0 == 0)
-                    gemm_crt_kernel<G, true, kEpiResidue><<<(unsigned)gw, G::threads, 0, s>>>(
-                        m, n, kn / 32, tiles_m, tiles_n, xc, x_lines_pad, yc, y_lines_pad, px, py,
-                        cg, rg, plane_res, none, nullptr, 0, 0);
-                else
-                    gemm_crt_kernel<G, false, kEpiResidue><<<(unsigned)gw, G::threads, 0, s>>>(
-                        m, n, kn / 32, tiles_m, tiles_n, xc, x_lines_pad, yc, y_lines_pad, px, py,
-                        cg, rg, plane_res, none, nullptr, 0, k0 > 0 ? 1 : 0);
-                e = hipGetLastError();
-            }
-        }
+        e = crt_tile_cols(n) == CrtCfgWide::BN
+                ? gemm_crt_launches<CrtCfgWide>(m, n, k, cc, xs, x_lines_pad, ys, y_lines_pad,
+                                                len_pad, res, plane_res, s)
+                : gemm_crt_launches<CrtCfg>(m, n, k, cc, xs, x_lines_pad, ys, y_lines_pad,
+                                            len_pad, res, plane_res, s);
     }
     if (e != hipSuccess) return e;
     const dim3 grid((unsigned)((n + kThreads / 4 - 1) / (kThreads / 4)), (unsigned)((m + 31) / 32));
@@ -952,24 +995,18 @@ hipError_t launch_certify(int m, int n, int k, const int8_t *qa, int a_lines_pad
                           const int8_t *qb, int b_lines_pad, int len_pad, const CertArgs &ca,
                           bool digits, hipStream_t s) {
     if (m == 0 || n == 0) return hipSuccess;
-    if (a_lines_pad % CrtCfg::BM || b_lines_pad % CrtCfg::BN || len_pad % kCrtLenAlign ||
-        len_pad < k || a_lines_pad < m || b_lines_pad < n)
-        return hipErrorInvalidValue;
-    const CrtConsts cc = make_consts(1, 0);
-    const int tiles_m = (m + CrtCfg::BM - 1) / CrtCfg::BM, tiles_n = (n + CrtCfg::BN - 1) / CrtCfg::BN;
-    using G = CrtCfg;
+    if (!crt_planes_ok(m, n, k, a_lines_pad, b_lines_pad, len_pad)) return hipErrorInvalidValue;
     TraceScope ts(TCU_KERNEL_CERTIFY, m, n, k, 1, 2.0 * m * n * (double)k, s);
-    const unsigned grid = (unsigned)(tiles_m * tiles_n);
-    const int64_t pa = (int64_t)a_lines_pad * len_pad, pb = (int64_t)b_lines_pad * len_pad;
+    const bool wide = crt_tile_cols(n) == CrtCfgWide::BN;
     if (digits)
-        gemm_crt_kernel<G, false, kEpiCertifyDigits><<<grid, G::threads, 0, s>>>(
-            m, n, len_pad / 32, tiles_m, tiles_n, qa, a_lines_pad, qb, b_lines_pad, pa, pb, cc,
-            nullptr, 0, ca, nullptr, 0, 0);
-    else
-        gemm_crt_kernel<G, false, kEpiCertify><<<grid, G::threads, 0, s>>>(
-            m, n, len_pad / 32, tiles_m, tiles_n, qa, a_lines_pad, qb, b_lines_pad, pa, pb, cc,
-            nullptr, 0, ca, nullptr, 0, 0);
-    return hipGetLastError();
+        return wide ? gemm_crt_single<CrtCfgWide, kEpiCertifyDigits>(
+                          m, n, k, qa, a_lines_pad, qb, b_lines_pad, len_pad, ca, nullptr, 0, s)
+                    : gemm_crt_single<CrtCfg, kEpiCertifyDigits>(
+                          m, n, k, qa, a_lines_pad, qb, b_lines_pad, len_pad, ca, nullptr, 0, s);
+    return wide ? gemm_crt_single<CrtCfgWide, kEpiCertify>(m, n, k, qa, a_lines_pad, qb,
+                                                            b_lines_pad, len_pad, ca, nullptr, 0, s)
+                : gemm_crt_single<CrtCfg, kEpiCertify>(m, n, k, qa, a_lines_pad, qb, b_lines_pad,
+                                                        len_pad, ca, nullptr, 0, s);
 }
 
 // A 1 at (line = group, position = key) of every in-range record of R in its
@@ -1002,19 +1039,14 @@ hipError_t launch_count_product(int m, int n, int k, const int8_t *qa, int a_lin
                                 const int8_t *qb, int b_lines_pad, int len_pad, int32_t *count,
                                 int64_t ldc, hipStream_t s) {
     if (m == 0 || n == 0) return hipSuccess;
-    if (a_lines_pad % CrtCfg::BM || b_lines_pad % CrtCfg::BN || len_pad % kCrtLenAlign ||
-        len_pad < k || a_lines_pad < m || b_lines_pad < n)
-        return hipErrorInvalidValue;
-    const CrtConsts cc = make_consts(1, 0);
-    const int tiles_m = (m + CrtCfg::BM - 1) / CrtCfg::BM, tiles_n = (n + CrtCfg::BN - 1) / CrtCfg::BN;
-    using G = CrtCfg;
-    const CertArgs none{};
+    if (!crt_planes_ok(m, n, k, a_lines_pad, b_lines_pad, len_pad)) return hipErrorInvalidValue;
     TraceScope ts(TCU_KERNEL_COUNT, m, n, k, 1, 2.0 * m * n * (double)k, s);
-    gemm_crt_kernel<G, false, kEpiCount><<<(unsigned)(tiles_m * tiles_n), G::threads, 0, s>>>(
-        m, n, len_pad / 32, tiles_m, tiles_n, qa, a_lines_pad, qb, b_lines_pad,
-        (int64_t)a_lines_pad * len_pad, (int64_t)b_lines_pad * len_pad, cc, nullptr, 0, none,
-        count, ldc, 0);
-    return hipGetLastError();
+    const CertArgs none{};
+    return crt_tile_cols(n) == CrtCfgWide::BN
+               ? gemm_crt_single<CrtCfgWide, kEpiCount>(m, n, k, qa, a_lines_pad, qb, b_lines_pad,
+                                                         len_pad, none, count, ldc, s)
+               : gemm_crt_single<CrtCfg, kEpiCount>(m, n, k, qa, a_lines_pad, qb, b_lines_pad,
+                                                     len_pad, none, count, ldc, s);
 }
 
 }  // namespace tcu

@@ -233,6 +233,9 @@ double crt_modulus_bits(int L);
 int crt_max_moduli();
 int64_t crt_residue_plane(int64_t m, int64_t n);
 int crt_len_align();  // the residue planes' length is a multiple of this
+// columns of the int8 products' tiles for an output n wide: the right
+// operand's planes hold a multiple of this many lines
+int crt_tile_cols(int64_t n);
 hipError_t launch_crt_split(const double *Z, int rows, int cols, int64_t ld, int axis,
                             const unsigned long long *maxbits, int L, int bits, int8_t *out,
                             int lines_pad, int len_pad, int *exps, hipStream_t s);

@@ -215,3 +215,16 @@ def test_crt_product_in_several_launches(orc):
     Co, _, _ = orc.join_agg(RA, RB, M, K, N, rows=rows)
     So, _, _ = orc.join_agg(abs_rel(orc, RA), abs_rel(orc, RB), M, K, N, rows=rows)
     assert err_cw(C, Co, So) <= tol
+
+
+def test_crt_wide_tiles_ragged(orc):
+    """Outputs of 16384 columns or more run on 256 x 384 tiles (residue
+    products and certificate); 16500 columns leave a ragged last tile.  The
+    result is the oracle's product of the truncations, within tol of C."""
+    dev = cuda_or_skip()
+    M, K, N = 96, 700, 16500
+    A, B = wl.mm_query(M, K, N, seed=23, values="loguniform", device=dev)
+    C, st, info, X, Y, Co, So = run_crt(orc, A, B, M, K, N, 1e-12, True)
+    assert st == 0
+    check_reconstruction(orc, C, info, X, Y)
+    assert err_cw(C, Co, So) <= 1e-12

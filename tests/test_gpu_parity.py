@@ -402,6 +402,7 @@ def _unique_cells(n, rows, cols, seed, tag, dev, bad=0):
     (1, 5000, 70, 0.05, 0),       # one group
     (513, 1, 600, 1.0, 0),        # K = 1: every pair joins
     (260, 700, 250, 0.1, 17),     # out-of-range records
+    (70, 300, 16500, 0.2, 0),     # wide output: 256 x 384 tiles, ragged
 ])
 def test_fwd_counts_int8_path_unique_cells(orc, M, K, N, fill, bad):
     """Unique cells on both sides: the counts come from the int8 product of
