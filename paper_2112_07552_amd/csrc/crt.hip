@@ -381,8 +381,9 @@ struct Cfg {
 // per CU); for wide outputs 256 x 384 tiles, 8 waves of 128 x 96, 4 stages of
 // 40 KB (all 160 KB of the CU's LDS, 256 VGPRs): a third fewer LDS fragment
 // reads and operand-panel bytes per MFMA.  Measured: the 2^30-record step
-// 1535 against 1586 ms; at 4096^3 the narrow tile fills the chip better
-// (0.84 against 0.85 ms, certificate 0.103 against 0.118 ms).
+// 1535 against 1586 ms; the narrow tile is faster at 8192^3 (6.72 against
+// 7.23 ms for 14 moduli) and 4096^3 (0.82-0.83 against 0.83-0.85 ms,
+// certificate 0.10 against 0.12 ms).
 using CrtCfg = Cfg<256, 8, 4, 2>;
 using CrtCfgWide = Cfg<384, 8, 4, 2>;
 static_assert(CrtCfg::NS == CrtCfgWide::NS && CrtCfg::BM == CrtCfgWide::BM,
