@@ -390,7 +390,11 @@ static_assert(CrtCfg::NS == CrtCfgWide::NS && CrtCfg::BM == CrtCfgWide::BM,
               "both tile shapes share the plane layout's length padding and row tiles");
 // output width from which products use the wide tile
 constexpr int kWideTileN = 16384;
-constexpr int NUM_XCD = 8, GROUP_M = 4, RUN = 32;
+// Tiles are numbered in groups GROUP_M tile rows deep, so a run of 32 tiles
+// (one per CU of an XCD) spans 8 tile rows and 4 columns: fewer of the wide
+// tile's 384-line column panels (measured at the 2^30 step: 1513 ms against
+// 1543-1557 ms for runs 4 rows deep; 16 rows deep 1508-1513 ms).
+constexpr int NUM_XCD = 8, GROUP_M = 8, RUN = 32;
 // k-steps of 32 per unrolled round of the main loop: the contraction length
 // of the residue planes is padded to a multiple of this
 constexpr int kCrtLenAlign = 64 * CrtCfg::NS;
