@@ -321,6 +321,12 @@ def block_errors(ref, Cm, dA, dB):
     return e
 
 
+def crt_tile(n):
+    """The residue GEMM's tile for an output n columns wide, as the library
+    chooses it (256 x 384 from 16384 columns, else 256 x 256)."""
+    return "256x384" if n >= 16384 else "256x256"
+
+
 def largest_edge(budget):
     """The largest N (a multiple of 256) whose headline step fits in `budget`
     bytes: both tables with FP32 values (12 B per record), W, C, dA and dB
@@ -954,8 +960,8 @@ def main():
                 "unit": "TOPS", "frac": g["achieved_tops"] / PEAK_I8_MFMA_TOPS,
                 "traffic": counter_traffic("counters_gemm_crt_mm_query_32768.md", "gemm_crt",
                                            "crt.hip"),
-                "kernel": "gemm_crt_kernel<Cfg<256, 8, 4, 2>, false, 0> (int8 residue "
-                          "products, all of the step's launches)",
+                "kernel": f"gemm_crt_kernel ({crt_tile(N)} tiles; the int8 residue "
+                          f"products, one launch per modulus, all of the step's launches)",
                 "launches": g["launches"], "avg_ms": g["avg_ms"],
                 "ops_per_launch": g["avg_ops_per_launch"]},
             "cpu_baseline": h.get("cpu_baseline"),
