@@ -14,7 +14,8 @@ the same step is the comparator.  Inputs are resident in HBM.
 The other legs of the same JSON line: the 2^24-record workloads (FP64 on
 U[-1,1), seed 2; every mixed form on log-uniform values, seed 3), the
 forward at 2^14 and 2^20 records (seeds 0 and 1), the library FP64 GEMM
-ceiling (torch.matmul), measured matrix-core rates, and the query family.
+ceiling (torch.matmul), the library int8 GEMM at the headline size
+(torch._int_mm), measured matrix-core rates, and the query family.
 
 The dominant kernel's duration is measured inside the timed steps: the
 library records HIP events around every launch of its matrix-core product
@@ -348,6 +349,26 @@ def largest_edge(budget):
     return n
 
 
+def library_int8(N, stream, steps=3):
+    """The vendor library's int8 GEMM (hipBLASLt through torch._int_mm, int32
+    sums, operands N x N and N x N transposed, its faster layout here) on one
+    modulus-sized product of the headline: a ceiling for the residue GEMM,
+    which runs the same contraction per modulus and also reduces its sums to
+    residues.  Never on the path."""
+    import torch
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    a = torch.randint(-128, 128, (N, N), dtype=torch.int8, device=dev, generator=g)
+    b = torch.randint(-128, 128, (N, N), dtype=torch.int8, device=dev, generator=g)
+    bt = b.t()
+    ms = time_loop(lambda: torch._int_mm(a, bt), steps, 1, stream)
+    del a, b, bt
+    torch.cuda.empty_cache()
+    return {"call": "torch._int_mm int8 x int8^T -> int32 (hipBLASLt)",
+            "m_n_k": [N, N, N], "ms": ms, "tops": 2.0 * N ** 3 / (ms * 1e-3) / 1e12}
+
+
 def leg_headline(args, stream, hip):
     """2^30 records per table (N = 32768, FP32 mixture values, seed 4): the
     residue form's forward + checkpointed adjoint (the headline), its
@@ -432,6 +453,12 @@ def leg_headline(args, stream, hip):
     del op, A, B, W
     torch.cuda.empty_cache()
     out["gemm_crt"] = gemm
+    lib = library_int8(N, stream)
+    if gemm is not None:
+        # the residue GEMM's rate per modulus-sized product, against the library's
+        lib["residue_gemm_tops"] = gemm["achieved_tops"]
+    log(f"headline: library int8 GEMM {lib['ms']:.2f} ms, {lib['tops']:.0f} TOPS")
+    out["library_int8_gemm"] = lib
     return out
 
 
@@ -980,7 +1007,8 @@ def main():
                 "kernel": f"gemm_crt_kernel ({crt_tile(N)} tiles; the int8 residue "
                           f"products, one launch per modulus, all of the step's launches)",
                 "launches": g["launches"], "avg_ms": g["avg_ms"],
-                "ops_per_launch": g["avg_ops_per_launch"]},
+                "ops_per_launch": g["avg_ops_per_launch"],
+                "library_int8_gemm_tops": h["library_int8_gemm"]["tops"]},
             "cpu_baseline": h.get("cpu_baseline"),
         })
     out["legs"] = res
