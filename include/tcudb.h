@@ -123,6 +123,9 @@ typedef struct {
     uint32_t need;         /* mixed forms: the last product certificate's
                               largest per-cell need in its form (bits or
                               digits; 255: a cell it could not bound)        */
+    uint32_t exceptions;   /* residue form: cells of the last product whose
+                              need exceeded `bits` (or that the certificate
+                              could not bound), recomputed one by one      */
 } tcu_status_info;
 
 #define TCU_FLAG_KEY_RANGE 1u /* a record had an out-of-range key or group    */
@@ -190,7 +193,9 @@ size_t tcu_encode_workspace_bytes(const tcu_relation *R, int32_t rows, int32_t c
  * largest normalised line sums (then |sum_k x'y'| < 2^(2b) min(u, k)).
  * Returns the digit count S = max(need, 1) (TCU_PREC_SPLIT_*, at most 8), or
  * for TCU_PREC_CRT_I8 the modulus count L, the smallest with
- * prod m_i > 4 * 2^(2b) min(max(u, 1), k), b = max(need, 1) <= 53 written to
+ * log2(prod m_i) > 2b + log2(min(max(u, 1), k)) + 1 + 1e-6 (so that prod m_i
+ * > 2 |P| (1 + 2^-38), which the reconstruction's rounding of P / prod m_i
+ * needs), b = max(need, 1) <= 53 written to
  * *bits (moduli 256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 217,
  * 211, 199, 197); TCU_ERR_INFEASIBLE when no plan exists (then the product
  * runs in FP64 and TCU_FLAG_FALLBACK is set), tol < 2^-50, or the residue
@@ -259,9 +264,15 @@ tcu_status tcu_gemm_f64_ws(int trans_a, int trans_b, int32_t m, int32_t n, int32
  * (tol <= 0 means 1e-12): the plan is certified for every cell of the
  * product from the operands (tcu_mixed_plan), and a product without a
  * certified plan runs in FP64 instead (TCU_FLAG_FALLBACK), whose error is
- * at most about K 2^-53 (|X||Y|)[g,h].  Planning reads the certificate back
- * to the host, so a mixed-form call SYNCHRONISES the stream once per product;
- * the FP64 form never does.  TCU_ERR_INFEASIBLE (launching nothing) for
+ * at most about K 2^-53 (|X||Y|)[g,h].  The residue form may instead take
+ * a width b below the largest need when few cells (at most 4096) need more
+ * than b or cannot be bounded and the narrower width saves moduli: those
+ * cells are then recomputed one by one after the reconstruction as
+ * compensated FP64 dot products (within about 2^-53 |C|), and their number
+ * is reported (tcu_status_info.exceptions).  Planning reads the certificate
+ * back to the host, so a mixed-form call SYNCHRONISES the stream once per
+ * product (twice when the residue form looks for such cells); the FP64
+ * form never does.  TCU_ERR_INFEASIBLE (launching nothing) for
  * tol < 2^-50 or, in the residue form, K > 131071.  The count output is
  * exact in every form.
  * Device-side conditions (out-of-range records, NaN/Inf in the mixed forms)

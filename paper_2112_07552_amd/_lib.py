@@ -66,7 +66,7 @@ class tcu_relation(C.Structure):
 class tcu_status_info(C.Structure):
     _fields_ = [("flags", C.c_uint32), ("slices", C.c_uint32),
                 ("skipped_a", C.c_uint64), ("skipped_b", C.c_uint64),
-                ("bits", C.c_uint32), ("need", C.c_uint32)]
+                ("bits", C.c_uint32), ("need", C.c_uint32), ("exceptions", C.c_uint32)]
 
 
 TCU_KERNEL_GEMM_F64 = 1

@@ -86,9 +86,11 @@ int mixed_plan(tcu_precision p, int32_t k, double tol, uint32_t need, double u,
     }
     const int b = need < 1 ? 1 : (int)need;
     if (b > 53) return TCU_ERR_INFEASIBLE;
-    // |P| < 2^(2b) min(u, k); the reconstruction needs M > 4 |P|
+    // |P| < 2^(2b) min(u, k); the reconstruction finds q = round(S / M) to
+    // within 2^-40, so it needs M > 2 |P| (1 + 2^-38); 1e-6 bits is a factor
+    // 1 + 6.9e-7, which also covers the roundings of the logarithms
     const double U = std::min(std::max(u, 1.0), (double)k);
-    const double need_bits = 2.0 * b + log2(U) + 2.0;
+    const double need_bits = 2.0 * b + log2(U) + 1.0 + 1e-6;
     for (int L = 1; L <= crt_max_moduli(); ++L)
         if (crt_modulus_bits(L) > need_bits) {
             if (bits_out != nullptr) *bits_out = b;
@@ -110,8 +112,12 @@ struct Layout {
     size_t x = 0, y = 0, g = 0, g2 = 0, mba = 0, mbb = 0, ea = 0, eb = 0, sa = 0, sb = 0, res = 0;
     size_t sxa = 0, sxb = 0, psa = 0, psb = 0, qa = 0, qb = 0;
     size_t gsplit = 0, gsplit_bytes = 0;  // FP64 form: partial products of a split contraction
+    size_t need = 0, exc = 0;  // residue form: per-cell needs, exception list
     size_t total = 0;
 };
+
+// Cells per segment of a residue-form product's exception list.
+constexpr uint32_t kExcCap = 4096;
 
 // Padding of the magnitude planes (the int8 GEMM's operand layout).
 size_t qlen(int64_t x) { return (size_t)((x + crt_len_align() - 1) / crt_len_align() * crt_len_align()); }
@@ -184,6 +190,10 @@ Layout plan_layout(int32_t M, int32_t K, int32_t N, tcu_precision p, int flags,
         if (is_crt(p)) {
             L.res = off;
             off += align_up(TCU_MAX_MODULI * out);
+            L.need = off;
+            off += align_up(out);
+            L.exc = off;
+            off += align_up((size_t)kExcThresholds * kExcCap * sizeof(int4));
         }
     } else {
         if (with_count_planes) {
@@ -285,6 +295,8 @@ struct SplitOperand {
 struct MixedPlan {
     int S = 0, bits = 0, len_pad = 0, la = 0, lb = 0;
     uint32_t need = 0;  // the certificate's need in this form
+    uint32_t exc = 0;   // residue form: cells needing more than `bits`, recomputed alone
+    int exc_last = -1;  // the last list segment they fill
 };
 
 // Step a0 for one operand: line maxima and sums of |z|, then the magnitude
@@ -304,8 +316,110 @@ hipError_t certify_prepare(const SplitOperand &o, bool second, void *ws, const L
                             (int)qlen(len), s);
 }
 
+// Exceptions of the residue form.  The certificate's plan truncates every
+// line to the widest need over all cells.  When a few cells need more than
+// the rest, a narrower width b can take fewer moduli: the cells needing more
+// than b (and any the certificate cannot bound) are then recomputed one by
+// one as compensated FP64 dot products after the reconstruction, which
+// keeps every cell within tol (|X||Y|)[g,h].  The candidate widths are the
+// widest ones at which the modulus count drops, level by level below the
+// certificate's plan; one scan of the need plane lists the cells above each
+// of them (in segments, so that a level whose cells fit the list is usable
+// even when a deeper one overflows), and the plan takes the level with the
+// least estimated time.
+
+// moduli for width b (0: none suffice)
+int crt_moduli_for(int32_t k, double tol, int b, double u) {
+    int32_t bits = 0;
+    const int r = mixed_plan(TCU_PREC_CRT_I8, k, tol, (uint32_t)b, u, &bits);
+    return r > 0 ? r : 0;
+}
+
+// Estimated seconds of the residue products (L moduli) of an m x n x k
+// product and of the FP64 product that replaces a plan without moduli
+// (L = 0); of the scan, which reads the need plane and synchronises once
+// more; and of recomputing cells alone (row and column read with a 64-byte
+// sector per element when strided).
+double crt_seconds(int L, int m, int n, int k) {
+    const double mnk = 2.0 * m * n * (double)k;
+    return L > 0 ? L * mnk / 2.5e15 : mnk / 6.0e13;
+}
+double scan_seconds(int m, int n) { return (double)((m + 31) / 32 * 32) * n / 2.0e12 + 2e-5; }
+double fixup_seconds(uint32_t cells, int k) {
+    return cells == 0 ? 0.0 : cells * 2.0 * k * 64.0 / 1.0e12 + 1e-5;
+}
+
+// Candidate widths, widest first, and their modulus counts: for each count
+// below the certificate's plan (L0 moduli; 0: no plan), the widest width
+// that takes it, from the widest allowed down (below the largest need, or
+// with cells the certificate cannot bound or wider than 53 bits, at most
+// the largest bounded need within 53).
+struct ExcLevels {
+    int n = 0;
+    int b[kExcThresholds] = {}, L[kExcThresholds] = {};
+};
+
+ExcLevels exception_levels(int32_t k, double tol, uint32_t need_all, uint32_t need_cert, double u,
+                           int L0) {
+    ExcLevels lv;
+    int hi;
+    if (need_all < kNeedUncertified && need_all <= 53)
+        hi = (int)need_all - 1;
+    else
+        hi = std::max(1, std::min((int)need_cert, 53));
+    int cur = L0;
+    for (int b = hi; b >= 1 && lv.n < kExcThresholds; --b) {
+        const int Lb = crt_moduli_for(k, tol, b, u);
+        if (Lb > 0 && (cur == 0 || Lb < cur)) {
+            lv.b[lv.n] = b;
+            lv.L[lv.n] = Lb;
+            ++lv.n;
+            cur = Lb;
+        }
+    }
+    return lv;
+}
+
+// Whether the scan pays: the first level's saving against twice its cost.
+// When even the smallest nonzero need exceeds the first level's width, every
+// such cell would be an exception: no scan.
+bool exception_scan_pays(int m, int n, int k, int L0, const ExcLevels &lv, uint32_t need_min) {
+    if (lv.n == 0 || need_min > (uint32_t)lv.b[0]) return false;
+    const double gain = crt_seconds(L0, m, n, k) - crt_seconds(lv.L[0], m, n, k);
+    return gain > 2.0 * scan_seconds(m, n);
+}
+
+struct ExcPlan {
+    int L = 0, bits = 0, last = -1;  // L = 0: keep the certificate's plan
+    uint32_t exc = 0;
+};
+
+// After the scan (seg[j]: cells listed in segment j, above cap: overflowed):
+// the level with the least estimated time, if it beats the certificate's
+// plan; a level needs every segment up to its own complete.
+ExcPlan exception_plan(int m, int n, int32_t k, int L0, const ExcLevels &lv,
+                       const uint32_t *seg) {
+    ExcPlan best;
+    double best_t = crt_seconds(L0, m, n, k);
+    uint32_t cells = 0;
+    for (int j = 0; j < lv.n; ++j) {
+        if (seg[j] > kExcCap) break;
+        cells += seg[j];
+        const double t = crt_seconds(lv.L[j], m, n, k) + fixup_seconds(cells, k);
+        if (t < best_t) {
+            best_t = t;
+            best.L = lv.L[j];
+            best.bits = lv.b[j];
+            best.last = j;
+            best.exc = cells;
+        }
+    }
+    return best;
+}
+
 // The certificate of a product whose operands went through certify_prepare,
-// then the plan.  Reads the certificate back: SYNCHRONISES the stream.
+// then the plan.  Reads the certificate back: SYNCHRONISES the stream (and
+// once more when it scans for exceptions).
 hipError_t certify_and_plan(int m, int n, int k, tcu_precision p, double tol, void *ws,
                             const Layout &L, StatusBlock *st, MixedPlan *mp, hipStream_t s) {
     tol = tol_or_default(tol);
@@ -323,6 +437,11 @@ hipError_t certify_and_plan(int m, int n, int k, tcu_precision p, double tol, vo
                                             0x1p-52) * (1.0 - 0x1p-40);
     ca.need_bits = &st->need_bits;
     ca.need_slices = &st->need_slices;
+    if (is_crt(p)) {
+        ca.need_plane = at<uint8_t>(ws, L.need);
+        ca.need_cert = &st->need_cert;
+        ca.need_min = &st->need_min;
+    }
     hipError_t e = launch_certify(m, n, k, at<int8_t>(ws, L.qa), (int)pad256(m),
                                   at<int8_t>(ws, L.qb), (int)padB(n), (int)qlen(k), ca,
                                   !is_crt(p), s);
@@ -341,6 +460,30 @@ hipError_t certify_and_plan(int m, int n, int k, tcu_precision p, double tol, vo
                        std::min(ua, ub), &bits);
     *mp = MixedPlan{};
     mp->need = is_crt(p) ? host.need_bits : host.need_slices;
+    if (is_crt(p) && !(host.flags & kFlagNonFinite)) {
+        // a narrower width whose few wider-need cells are recomputed alone
+        const int L0 = r > 0 ? r : 0;
+        const ExcLevels lv = exception_levels(k, tol, host.need_bits, host.need_cert,
+                                              std::min(ua, ub), L0);
+        if (exception_scan_pays(m, n, k, L0, lv, host.need_min)) {
+            ExcThresholds thr;
+            for (int j = 0; j < kExcThresholds; ++j)
+                thr.t[j] = j < lv.n ? (uint32_t)lv.b[j] : 255u;
+            e = launch_need_scan(at<uint8_t>(ws, L.need), m, n, thr, at<int4>(ws, L.exc),
+                                 kExcCap, st, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(&host, st, sizeof(host), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return e;
+            const ExcPlan xp = exception_plan(m, n, k, L0, lv, host.exc_seg);
+            if (xp.L > 0) {
+                r = xp.L;
+                bits = xp.bits;
+                mp->exc = xp.exc;
+                mp->exc_last = xp.last;
+            }
+        }
+    }
     if (r > 0) {
         mp->S = r;
         mp->bits = bits;
@@ -402,8 +545,11 @@ hipError_t finish_product(const SplitOperand &a, const SplitOperand &b, int m, i
     e = mixed_split(a, false, mp, p, ws, L, s);
     if (e == hipSuccess) e = mixed_split(b, true, mp, p, ws, L, s);
     if (e == hipSuccess) e = mixed_multiply(m, n, k, mp, p, ws, L, C, ldc, s);
+    if (e == hipSuccess && mp.exc > 0)
+        e = launch_exception_fixup(at<int4>(ws, L.exc), st, kExcCap, mp.exc_last, k, a.Z, a.ld,
+                                   a.axis, b.Z, b.ld, b.axis, C, ldc, s);
     if (e == hipSuccess)
-        e = launch_set_plan(st, (uint32_t)mp.S, (uint32_t)mp.bits, mp.need, false, s);
+        e = launch_set_plan(st, (uint32_t)mp.S, (uint32_t)mp.bits, mp.need, false, s, mp.exc);
     return e;
 }
 
@@ -884,6 +1030,7 @@ tcu_status tcu_sync_status(void *ws, hipStream_t stream, tcu_status_info *info) 
         info->skipped_b = host.skipped_b;
         info->bits = host.bits;
         info->need = host.need;
+        info->exceptions = host.exceptions;
     }
     if (host.flags & kFlagNonFinite) return TCU_ERR_NONFINITE;
     if (host.flags & kFlagKeyRange) return TCU_ERR_KEY_RANGE;

@@ -647,8 +647,12 @@ gemm_crt_kernel(int m, int n, int nblk, int tiles_m, int tiles_n, const int8_t *
         return;
     }
     if constexpr (EPI == kEpiCertify || EPI == kEpiCertifyDigits) {
-        // each cell's need; the wave's maximum goes out in one atomic
-        uint32_t need = 0;
+        // each cell's need; the wave's maxima go out in one atomic each.  The
+        // residue form also stores every cell's need (one byte, in the
+        // residues' order: one 16-byte store per lane and 32 x 32 block), and
+        // the largest and the smallest nonzero need among the cells the
+        // certificate bounds.
+        uint32_t need = 0, cneed = 0, mneed = kNeedUncertified;
 #pragma unroll
         for (int a = 0; a < WA; ++a) {
             const int rbase = m0 + wm * 32 * WA + a * 32;
@@ -658,6 +662,7 @@ gemm_crt_kernel(int m, int n, int nblk, int tiles_m, int tiles_n, const int8_t *
                 const int col = n0 + wn * 32 * WB + b * 32 + l32;
                 if (col >= n) continue;
                 const double sy = ca.sy[col];
+                uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
                     const int row = rbase + 8 * (i >> 2) + 4 * half + (i & 3);
@@ -666,14 +671,30 @@ gemm_crt_kernel(int m, int n, int nblk, int tiles_m, int tiles_n, const int8_t *
                     // in the exact and in the truncated product alike
                     const double sx = ca.sx[row];
                     const double r = (sx > 0.0 && sy > 0.0) ? 16384.0 * (sx + sy) : 0.0;
-                    need = max(need, EPI == kEpiCertify ? cert_bits(r, acc[a][b][i], ca)
-                                                        : cert_slices(r, acc[a][b][i], ca));
+                    const uint32_t c = EPI == kEpiCertify ? cert_bits(r, acc[a][b][i], ca)
+                                                          : cert_slices(r, acc[a][b][i], ca);
+                    need = max(need, c);
+                    if (c < kNeedUncertified) cneed = max(cneed, c);
+                    if (c > 0) mneed = min(mneed, c);
+                    w[i >> 2] |= c << (8 * (i & 3));
                 }
+                if (EPI == kEpiCertify && ca.need_plane != nullptr)
+                    *reinterpret_cast<uint4 *>(ca.need_plane +
+                                               ((int64_t)(rbase >> 5) * n + col) * 32 + 16 * half) =
+                        make_uint4(w[0], w[1], w[2], w[3]);
             }
         }
-        for (int off = 32; off > 0; off >>= 1)
+        for (int off = 32; off > 0; off >>= 1) {
             need = max(need, (uint32_t)__shfl_xor((int)need, off));
-        if (lane == 0) atomicMax(EPI == kEpiCertify ? ca.need_bits : ca.need_slices, need);
+            cneed = max(cneed, (uint32_t)__shfl_xor((int)cneed, off));
+            mneed = min(mneed, (uint32_t)__shfl_xor((int)mneed, off));
+        }
+        if (lane == 0) {
+            atomicMax(EPI == kEpiCertify ? ca.need_bits : ca.need_slices, need);
+            if (EPI == kEpiCertify && ca.need_cert != nullptr) atomicMax(ca.need_cert, cneed);
+            if (EPI == kEpiCertify && ca.need_min != nullptr && mneed < kNeedUncertified)
+                atomicMin(ca.need_min, mneed);
+        }
         return;
     }
     // epilogue: residues of the int32 sums as int8 in the accumulator's own
@@ -716,11 +737,13 @@ constexpr double kLimb = 1099511627776.0;  // 2^40
 
 // P from S = s2 2^80 + s1 2^40 + s0 (exact limb sums of r_i w_i):
 // q = round(S / M), the limbs of S - q M exactly, balanced carries (|p0|,
-// |p1| <= 2^39, so the sum rounds only at the end), one double.  S / M lies
-// within 1/4 of the integer q (|P| < M / 4) and below 15 * 128 in magnitude;
-// the roundings of sd (absolute error below 2^40, against M > 2^100) and of
-// sd * (1/M) (relative error under 3 * 2^-53) move it by less than 1e-12, so
-// a multiply by the reciprocal gives the same q as the division.
+// |p1| <= 2^39, so the sum rounds only at the end), one double.  The plan
+// keeps |P| < M / (2 (1 + 2^-38)), so S / M lies within 1/2 - 2^-39 of the
+// integer q, and |S / M| < 15 * 128 < 2^11.  Each of the two roundings of
+// sd is below 2^-42 M (the inner one only matters when M >= 2^80, and then
+// |s1| 2^40 < 1920 M), and the rounded reciprocal and the product add at
+// most 2 * 2^-53 * 2^11 relative to 1: sd * (1/M) lies within 2^-40 of
+// S / M and rounds to the same q.
 __device__ inline double crt_finish(double s0, double s1, double s2, const CrtConsts &cc) {
     const double sd = fma(s2, kLimb * kLimb, fma(s1, kLimb, s0));
     const double q = rint(sd * cc.inv_M);
@@ -977,6 +1000,165 @@ hipError_t launch_gemm_crt(int m, int n, int k, int L, int bits, const int8_t *x
     if (e != hipSuccess) return e;
     const dim3 grid((unsigned)((n + kThreads / 4 - 1) / (kThreads / 4)), (unsigned)((m + 31) / 32));
     kReconstruct[L](grid, s, m, n, res, plane_res, cc, ex, ey, C, ldc, accumulate);
+    return hipGetLastError();
+}
+
+namespace {
+
+// The segment of a cell with this need: the first j with need > t[j]
+// (kExcThresholds: none).
+__device__ inline int exc_segment(uint32_t need, const ExcThresholds &thr) {
+    int seg = kExcThresholds;
+#pragma unroll
+    for (int j = kExcThresholds - 1; j >= 0; --j)
+        if (need > thr.t[j]) seg = j;
+    return seg;
+}
+
+// The exception scan: one 16-byte chunk of the need plane per lane (half a
+// column of a 32-row block, the certificate's store), waves walking the
+// plane in step so that a segment's list slots are taken with one atomic
+// per wave.  A wave that has to drop cells of a full segment raises the
+// segment's count above cap once, so the count then says "overflowed".
+__global__ void __launch_bounds__(kThreads)
+need_scan_kernel(const uint8_t *__restrict__ plane, int m, int n, ExcThresholds thr,
+                 int4 *__restrict__ list, uint32_t cap, StatusBlock *st) {
+    const int64_t chunks = (int64_t)((m + 31) / 32) * n * 2;
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    bool full[kExcThresholds] = {}, marked[kExcThresholds] = {};
+    for (int64_t u0 = (int64_t)blockIdx.x * kThreads + (threadIdx.x & ~63); u0 < chunks;
+         u0 += stride) {
+        const int64_t u = u0 + lane;
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
+        int row0 = 0, col = 0;
+        if (u < chunks) {
+            const uint4 v = reinterpret_cast<const uint4 *>(plane)[u];
+            w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+            const int64_t rb = u / (2 * (int64_t)n), rem = u % (2 * (int64_t)n);
+            col = (int)(rem >> 1);
+            row0 = (int)(rb * 32) + 4 * (int)(rem & 1);
+        }
+        // segment of each of the lane's 16 cells (kExcThresholds: none)
+        uint32_t cnt[kExcThresholds] = {};
+        uint32_t any = 0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const uint32_t need = (w[i >> 2] >> (8 * (i & 3))) & 255u;
+            const int row = row0 + 8 * (i >> 2) + (i & 3);
+            const int seg = row < m ? exc_segment(need, thr) : kExcThresholds;
+#pragma unroll
+            for (int j = 0; j < kExcThresholds; ++j) cnt[j] += seg == j ? 1u : 0u;
+            any |= seg < kExcThresholds ? 1u : 0u;
+        }
+        if (__ballot(any) == 0ull) continue;
+#pragma unroll
+        for (int j = 0; j < kExcThresholds; ++j) {
+            // slots for this wave's cells of segment j: an inclusive scan over the lanes
+            uint32_t incl = cnt[j];
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t t = (uint32_t)__shfl_up((int)incl, off);
+                if (lane >= off) incl += t;
+            }
+            const uint32_t total = (uint32_t)__shfl((int)incl, 63);
+            if (total == 0) continue;
+            if (full[j]) {
+                if (!marked[j] && lane == 0) atomicMax(&st->exc_seg[j], cap + 1);
+                marked[j] = true;
+                continue;
+            }
+            uint32_t base = 0;
+            if (lane == 63) base = atomicAdd(&st->exc_seg[j], total);
+            base = (uint32_t)__shfl((int)base, 63);
+            full[j] = base + total >= cap;
+            uint32_t idx = base + incl - cnt[j];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const uint32_t need = (w[i >> 2] >> (8 * (i & 3))) & 255u;
+                const int row = row0 + 8 * (i >> 2) + (i & 3);
+                if (row < m && exc_segment(need, thr) == j) {
+                    if (idx < cap) list[(int64_t)j * cap + idx] = make_int4(row, col, (int)need, 0);
+                    ++idx;
+                }
+            }
+        }
+    }
+}
+
+// The fix-up: one wave per listed cell whose need exceeds b.  The dot
+// product of the cell's row of op(A) and column of op(B) is compensated
+// (Ogita, Rump and Oishi's Dot2: each product split exactly into its
+// rounded value and error by an FMA, each sum by TwoSum, the errors summed
+// apart), per lane over every 64th position, then over the lanes by the same
+// steps; the result is within about one rounding of the exact value.
+__device__ inline void two_sum(double a, double b, double &s, double &e) {
+    s = a + b;
+    const double z = s - a;
+    e = (a - (s - z)) + (b - z);
+}
+
+__global__ void __launch_bounds__(kThreads)
+exception_fixup_kernel(const int4 *__restrict__ list, const StatusBlock *st, uint32_t cap,
+                       int last, int k, const double *__restrict__ Za, int64_t lda, int axa,
+                       const double *__restrict__ Zb, int64_t ldb, int axb,
+                       double *__restrict__ C, int64_t ldc) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t nw = gridDim.x * (kThreads / 64);
+    // entries of segments 0 .. last, numbered one after the other
+    uint32_t seg_n[kExcThresholds], total = 0;
+#pragma unroll
+    for (int j = 0; j < kExcThresholds; ++j) {
+        seg_n[j] = j <= last ? min(st->exc_seg[j], cap) : 0u;
+        total += seg_n[j];
+    }
+    for (uint32_t e = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); e < total; e += nw) {
+        uint32_t j = 0, i = e;
+#pragma unroll
+        for (int jj = 0; jj < kExcThresholds - 1; ++jj)
+            if (j == (uint32_t)jj && i >= seg_n[jj]) {
+                i -= seg_n[jj];
+                j = jj + 1;
+            }
+        const int4 cell = list[(int64_t)j * cap + i];
+        const int64_t row = cell.x, col = cell.y;
+        double sum = 0.0, err = 0.0;
+        for (int t = lane; t < k; t += 64) {
+            const double x = axa == 0 ? Za[row * lda + t] : Za[(int64_t)t * lda + row];
+            const double y = axb == 0 ? Zb[col * ldb + t] : Zb[(int64_t)t * ldb + col];
+            const double p = x * y;
+            const double pe = fma(x, y, -p);
+            double se;
+            two_sum(sum, p, sum, se);
+            err += pe + se;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double s2 = __shfl_xor(sum, off), e2 = __shfl_xor(err, off);
+            double se;
+            two_sum(sum, s2, sum, se);
+            err += e2 + se;
+        }
+        if (lane == 0) C[row * ldc + col] = sum + err;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_need_scan(const uint8_t *plane, int m, int n, ExcThresholds thr, int4 *list,
+                            uint32_t cap, StatusBlock *st, hipStream_t s) {
+    if (m == 0 || n == 0) return hipSuccess;
+    const int64_t chunks = (int64_t)((m + 31) / 32) * n * 2;
+    const int64_t blocks = std::min<int64_t>((chunks + kThreads - 1) / kThreads, 4096);
+    need_scan_kernel<<<(unsigned)blocks, kThreads, 0, s>>>(plane, m, n, thr, list, cap, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_exception_fixup(const int4 *list, const StatusBlock *st, uint32_t cap, int last,
+                                  int k, const double *Za, int64_t lda, int axa, const double *Zb,
+                                  int64_t ldb, int axb, double *C, int64_t ldc, hipStream_t s) {
+    if (cap == 0 || last < 0 || last >= kExcThresholds) return hipErrorInvalidValue;
+    const unsigned blocks = (unsigned)std::min<uint32_t>(((last + 1) * cap + 3) / 4, 1024u);
+    exception_fixup_kernel<<<blocks, kThreads, 0, s>>>(list, st, cap, last, k, Za, lda, axa, Zb,
+                                                       ldb, axb, C, ldc);
     return hipGetLastError();
 }
 

@@ -44,14 +44,19 @@ __global__ void reset_plan_kernel(StatusBlock *st) {
     st->need_slices = 0;
     st->umax_a = 0;
     st->umax_b = 0;
+    st->need_cert = 0;
+    st->need_min = kNeedUncertified;
+    for (int j = 0; j < kExcThresholds; ++j) st->exc_seg[j] = 0;
+    st->exceptions = 0;
 }
 
 // The plan a mixed-form product ran with (slices = 0: FP64 fallback).
 __global__ void set_plan_kernel(StatusBlock *st, uint32_t slices, uint32_t bits, uint32_t need,
-                                int fallback) {
+                                int fallback, uint32_t exceptions) {
     st->slices = slices;
     st->bits = bits;
     st->need = need;
+    st->exceptions = exceptions;
     if (fallback) st->flags |= kFlagFallback;
 }
 
@@ -360,8 +365,8 @@ hipError_t launch_reset_plan(StatusBlock *st, hipStream_t s) {
 }
 
 hipError_t launch_set_plan(StatusBlock *st, uint32_t slices, uint32_t bits, uint32_t need,
-                           bool fallback, hipStream_t s) {
-    set_plan_kernel<<<1, 1, 0, s>>>(st, slices, bits, need, fallback ? 1 : 0);
+                           bool fallback, hipStream_t s, uint32_t exceptions) {
+    set_plan_kernel<<<1, 1, 0, s>>>(st, slices, bits, need, fallback ? 1 : 0, exceptions);
     return hipGetLastError();
 }
 

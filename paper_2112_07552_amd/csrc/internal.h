@@ -22,9 +22,15 @@ struct StatusBlock {
     uint32_t need;                  // the last product's need in its own form
     unsigned long long umax_a;      // bit pattern of max over lines of sum|z| 2^-e, operand A
     unsigned long long umax_b;      // the same for operand B
-    uint32_t pad[50];
+    uint32_t need_cert;             // certificate: largest need among the cells it bounds
+    uint32_t need_min;              // certificate: smallest nonzero need among those cells
+    uint32_t exc_seg[4];            // exception scan: cells listed per segment (kExcThresholds;
+                                    // above the segment's capacity: it overflowed)
+    uint32_t exceptions;            // residue form: cells of the last product recomputed alone
+    uint32_t pad[43];
 };
 static_assert(sizeof(StatusBlock) == 256, "status block must be 256 bytes");
+constexpr int kExcThresholds = 4;  // thresholds the exception scan counts above
 
 constexpr uint32_t kFlagKeyRange = 1u;
 constexpr uint32_t kFlagNonFinite = 2u;
@@ -85,10 +91,11 @@ size_t join_agg_fwd_ws_bytes(const tcu_relation *A, const tcu_relation *B, int32
 hipError_t launch_zero_f64(double *p, size_t n, hipStream_t s);
 hipError_t launch_clear_status(StatusBlock *st, hipStream_t s, uint32_t slices = 0);
 // status words of a mixed-form product: cleared before its certificate, and
-// the plan it ran with (slices = 0 and the fallback flag: FP64)
+// the plan it ran with (slices = 0 and the fallback flag: FP64; exceptions:
+// cells the residue form recomputed alone)
 hipError_t launch_reset_plan(StatusBlock *st, hipStream_t s);
 hipError_t launch_set_plan(StatusBlock *st, uint32_t slices, uint32_t bits, uint32_t need,
-                           bool fallback, hipStream_t s);
+                           bool fallback, hipStream_t s, uint32_t exceptions = 0);
 hipError_t launch_encode(const tcu_relation &R, int transpose, int rows, int cols, double *out,
                          StatusBlock *st, int which, hipStream_t s);
 // The whole encoding of one relation: out zeroed, then the records placed.
@@ -213,6 +220,11 @@ struct CertArgs {
     double kterm;           // 2^14 K
     double tdig[TCU_MAX_SLICES + 1];  // digit forms: tolerance left, per digit count
     uint32_t *need_bits, *need_slices;
+    // residue form: the need of every cell (bytes, the residue planes'
+    // layout, crt_residue_plane(m, n)), and the largest need and smallest
+    // nonzero need among the cells the certificate bounds; may be NULL
+    uint8_t *need_plane;
+    uint32_t *need_cert, *need_min;
 };
 hipError_t launch_mag_plane(const double *Z, int rows, int cols, int64_t ld, int axis,
                             const unsigned long long *maxbits, const double *sums, double *shat,
@@ -243,5 +255,23 @@ hipError_t launch_gemm_crt(int m, int n, int k, int L, int bits, const int8_t *x
                            const int8_t *ys, int y_lines_pad, int len_pad, int8_t *res,
                            const int *ex, const int *ey, double *C, int64_t ldc, int accumulate,
                            hipStream_t s);
+// Exceptions of the residue form (crt.hip).  Thresholds t[0] > t[1] > ...
+// (unused ones 255) cut the cells of the need plane into segments: a cell
+// belongs to the first j with need > t[j], and cells at or below every
+// threshold to none.  The scan lists segment j's cells, {row, col, need, 0},
+// at list + j * cap, and counts them in st->exc_seg[j]; a count above cap
+// means the segment overflowed (its list is incomplete).  The fix-up
+// recomputes every cell of segments 0 .. last as a compensated FP64 dot
+// product of its row of op(A) and column of op(B) and stores it into C.  An
+// operand with axis 0 is stored line by line (A: m x k; B: n x k), with
+// axis 1 position by position (A: k x m; B: k x n), leading dimension ld.
+struct ExcThresholds {
+    uint32_t t[4];
+};
+hipError_t launch_need_scan(const uint8_t *plane, int m, int n, ExcThresholds thr, int4 *list,
+                            uint32_t cap, StatusBlock *st, hipStream_t s);
+hipError_t launch_exception_fixup(const int4 *list, const StatusBlock *st, uint32_t cap, int last,
+                                  int k, const double *Za, int64_t lda, int axa, const double *Zb,
+                                  int64_t ldb, int axb, double *C, int64_t ldc, hipStream_t s);
 
 }  // namespace tcu

@@ -266,7 +266,7 @@ def sync_status(ws: torch.Tensor) -> Tuple[int, dict]:
     st = _lib.load().tcu_sync_status(_ptr(ws), _stream(ws.device), C.byref(info))
     return st, {"flags": info.flags, "slices": info.slices,
                 "skipped_a": info.skipped_a, "skipped_b": info.skipped_b,
-                "bits": info.bits, "need": info.need}
+                "bits": info.bits, "need": info.need, "exceptions": info.exceptions}
 
 
 def _checkpoint_needed(M: int, K: int, N: int, device) -> bool:

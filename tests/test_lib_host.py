@@ -197,18 +197,29 @@ def test_mixed_plan_host_only(lib):
         assert _plan(lib, p, 4096, 1e-12, 9, 1.0)[0] == _lib.TCU_ERR_INFEASIBLE
         assert _plan(lib, p, 4096, 1e-12, 255, 1.0)[0] == _lib.TCU_ERR_INFEASIBLE
     crt = _lib.TCU_PREC_CRT_I8
-    # the modulus count: the smallest L with prod m_i > 4 * 2^(2b) * min(max(u, 1), k)
+    # the modulus count: the smallest L with prod m_i > 2 |P| (1 + 2^-38) for
+    # every |P| <= 2^(2b) U, U = min(max(u, 1), k) -- the reconstruction
+    # rounds S / M to within 2^-40 of itself -- checked in exact integers
+    # (the library's 1e-6-bit margin is a factor 1 + 6.9e-7)
+    from fractions import Fraction
     for k, need, u in ((4096, 42, 4096.0), (4096, 46, 136.0), (32768, 48, 325.0),
-                       (1, 2, 0.9), (257, 53, 257.0), (100, 20, 1e9), (5000, 0, 0.0)):
+                       (32768, 51, 370.2), (1, 2, 0.9), (257, 53, 257.0), (100, 20, 1e9),
+                       (5000, 0, 0.0), (3570, 41, 3570.0)):
         b = max(need, 1)
-        U = min(max(u, 1.0), float(k))
-        want = next((L for L in range(1, 16)
-                     if math.log2(math.prod(MODULI[:L])) > 2 * b + math.log2(U) + 2), None)
+        U = Fraction(min(max(u, 1.0), float(k)))
+        bound = 2 * 2 ** (2 * b) * U * (1 + Fraction(1, 2 ** 38))
+        want = next((L for L in range(1, 16) if math.prod(MODULI[:L]) > bound), None)
         got, bits = _plan(lib, crt, k, 1e-12, need, u)
         if want is None:
             assert got == _lib.TCU_ERR_INFEASIBLE
         else:
+            # the margin can only add a modulus when prod m_i sits within a
+            # factor 1 + 6.9e-7 of the bound, which none of these cases does
             assert (got, bits) == (want, b), (k, need, u)
+            assert math.prod(MODULI[:got]) > bound
+    # a case the former M > 4 |P| rule planned one modulus wider: 2^(2*20+1) * 100
+    # lies below the first six moduli's product, 2^(2*20+2) * 100 above it
+    assert _plan(lib, crt, 100, 1e-12, 20, 1e9)[0] == 6
     # every modulus count is reachable
     seen = ({_plan(lib, crt, 131071, 1e-12, b, 131071.0)[0] for b in range(1, 54)} |
             {_plan(lib, crt, 1, 1e-12, b, 1.0)[0] for b in range(1, 54)})

@@ -47,7 +47,7 @@ def _noalloc(L, A, B, M, K, N, prec, tol, with_count, dev, sp):
     st = L.tcu_sync_status(C.c_void_p(status.data_ptr()), sp, C.byref(info))
     return Cm, cnt, st, {"flags": info.flags, "slices": info.slices,
                          "skipped_a": info.skipped_a, "skipped_b": info.skipped_b,
-                         "bits": info.bits, "need": info.need}
+                         "bits": info.bits, "need": info.need, "exceptions": info.exceptions}
 
 
 CASES = [
