@@ -689,10 +689,33 @@ gemm_crt_kernel(int m, int n, int nblk, int tiles_m, int tiles_n, const int8_t *
             cneed = max(cneed, (uint32_t)__shfl_xor((int)cneed, off));
             mneed = min(mneed, (uint32_t)__shfl_xor((int)mneed, off));
         }
+        // Every workgroup of the launch ends here at about the same time, and
+        // same-address atomics from all of them serialise.  The waves' values
+        // meet in LDS (free once every wave has left the main loop), and the
+        // workgroup skips an atomic that would not change the running maximum
+        // (or minimum); that value only moves one way, so a stale read can
+        // only cause an atomic that was not needed.
+        __syncthreads();
+        uint32_t *red = reinterpret_cast<uint32_t *>(lds);
         if (lane == 0) {
-            atomicMax(EPI == kEpiCertify ? ca.need_bits : ca.need_slices, need);
-            if (EPI == kEpiCertify && ca.need_cert != nullptr) atomicMax(ca.need_cert, cneed);
-            if (EPI == kEpiCertify && ca.need_min != nullptr && mneed < kNeedUncertified)
+            red[wave] = need;
+            red[G::NW + wave] = cneed;
+            red[2 * G::NW + wave] = mneed;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < G::NW; ++w) {
+                need = max(need, red[w]);
+                cneed = max(cneed, red[G::NW + w]);
+                mneed = min(mneed, red[2 * G::NW + w]);
+            }
+            uint32_t *nb = EPI == kEpiCertify ? ca.need_bits : ca.need_slices;
+            if (need > __atomic_load_n(nb, __ATOMIC_RELAXED)) atomicMax(nb, need);
+            if (EPI == kEpiCertify && ca.need_cert != nullptr &&
+                cneed > __atomic_load_n(ca.need_cert, __ATOMIC_RELAXED))
+                atomicMax(ca.need_cert, cneed);
+            if (EPI == kEpiCertify && ca.need_min != nullptr && mneed < kNeedUncertified &&
+                mneed < __atomic_load_n(ca.need_min, __ATOMIC_RELAXED))
                 atomicMin(ca.need_min, mneed);
         }
         return;
