@@ -112,3 +112,54 @@ def test_exceptions_leave_small_products_alone(orc):
     C64, _, _ = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, M, K, N,
                                  unique=True)
     assert torch.equal(Cg, C64)
+
+
+def test_adjoint_products_recompute_their_uncertifiable_cells(orc):
+    """The adjoint's products dX = dC Y^T and dY = X^T dC each hold one cell
+    the certificate cannot bound (the same construction on dC's row g* and
+    Y's row k*, and on X's column k0 and dC's column h0).  Both products run
+    in the residue form with that cell recomputed alone; the two gradient
+    records that read those cells, and a sample of the others, match the
+    oracle's closed form within tol."""
+    dev = cuda_or_skip()
+    M = K = N = 2048
+    gs, ks, h1 = 100, 300, 1500     # dX cell (gs, ks): dC row gs meets Y row ks at h1 only
+    k0, h0, g1 = 700, 200, 1800     # dY cell (k0, h0): X column k0 meets dC column h0 at g1 only
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(91)
+    X = torch.rand((M, K), generator=gen, dtype=torch.float64, device=dev) * 2 - 1
+    Y = torch.rand((K, N), generator=gen, dtype=torch.float64, device=dev) * 2 - 1
+    W = torch.rand((M, N), generator=gen, dtype=torch.float64, device=dev) * 2 - 1
+    W[gs, N // 2:] = 0.0
+    W[gs, h1] = 1e-9
+    Y[ks, : N // 2] = 0.0
+    X[M // 2:, k0] = 0.0
+    X[g1, k0] = 1e-9
+    W[: M // 2, h0] = 0.0
+    A = dense_relation_from_matrix(X, False)
+    B = dense_relation_from_matrix(Y, True)
+    dA, dB, ws = ops.join_agg_bwd(A.group, A.key, A.val, B.key, B.group, B.val, M, K, N, W,
+                                  precision="crt_i8", tol=1e-12, unique=True)
+    st, info = ops.sync_status(ws)  # the last product: dY
+    assert st == 0 and info["need"] == 255, info
+    assert info["flags"] & ops._lib.TCU_FLAG_FALLBACK == 0 and info["exceptions"] >= 1, info
+    ia = np.unique(np.concatenate([[gs * K + ks],
+                                   np.random.default_rng(4).choice(M * K, 2000, replace=False)]))
+    ib = np.unique(np.concatenate([[k0 * N + h0],
+                                   np.random.default_rng(5).choice(K * N, 2000, replace=False)]))
+    RA, RB = to_orc(orc, A), to_orc(orc, B)
+    Wn = W.cpu().numpy()
+    ga = orc.grad(RA, RB, M, K, N, Wn, "A", idx=ia)
+    gb = orc.grad(RA, RB, M, K, N, Wn, "B", idx=ib)
+    sa = orc.grad(abs_rel(orc, RA), abs_rel(orc, RB), M, K, N, np.abs(Wn), "A", idx=ia)
+    sb = orc.grad(abs_rel(orc, RA), abs_rel(orc, RB), M, K, N, np.abs(Wn), "B", idx=ib)
+    dAn, dBn = dA.cpu().numpy()[ia], dB.cpu().numpy()[ib]
+    assert err_cw(dAn, ga, sa) <= 1e-12
+    assert err_cw(dBn, gb, sb) <= 1e-12
+    # the two recomputed cells, within a rounding or two of their one term
+    exact_a = 1e-9 * float(Y[ks, h1])
+    exact_b = 1e-9 * float(W[g1, h0])
+    got_a = float(dA[gs * K + ks])
+    got_b = float(dB[k0 * N + h0])
+    assert abs(got_a - exact_a) <= 2.0 ** -51 * abs(exact_a)
+    assert abs(got_b - exact_b) <= 2.0 ** -51 * abs(exact_b)
