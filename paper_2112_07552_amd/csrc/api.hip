@@ -381,10 +381,13 @@ ExcLevels exception_levels(int32_t k, double tol, uint32_t need_all, uint32_t ne
 }
 
 // Whether the scan pays: the first level's saving against twice its cost.
-// When even the smallest nonzero need exceeds the first level's width, every
-// such cell would be an exception: no scan.
+// When even the smallest nonzero need of a bounded cell exceeds the first
+// level's width, every such cell would be an exception: no scan.  (With no
+// bounded cell of nonzero need, need_min stays 255 and only the cells the
+// certificate cannot bound can be exceptions.)
 bool exception_scan_pays(int m, int n, int k, int L0, const ExcLevels &lv, uint32_t need_min) {
-    if (lv.n == 0 || need_min > (uint32_t)lv.b[0]) return false;
+    if (lv.n == 0) return false;
+    if (need_min < kNeedUncertified && need_min > (uint32_t)lv.b[0]) return false;
     const double gain = crt_seconds(L0, m, n, k) - crt_seconds(lv.L[0], m, n, k);
     return gain > 2.0 * scan_seconds(m, n);
 }
