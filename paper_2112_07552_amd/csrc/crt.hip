@@ -1108,8 +1108,9 @@ need_scan_kernel(const uint8_t *__restrict__ plane, int m, int n, ExcThresholds 
     }
 }
 
-// The fix-up: one wave per listed cell whose need exceeds b.  The dot
-// product of the cell's row of op(A) and column of op(B) is compensated
+// The fix-up: one wave per listed cell of segments 0 .. last (every cell
+// whose need exceeds the chosen width).  The dot product of the cell's row
+// of op(A) and column of op(B) is compensated
 // (Ogita, Rump and Oishi's Dot2: each product split exactly into its
 // rounded value and error by an FMA, each sum by TwoSum, the errors summed
 // apart), per lane over every 64th position, then over the lanes by the same
