@@ -163,3 +163,40 @@ def test_adjoint_products_recompute_their_uncertifiable_cells(orc):
     got_b = float(dB[k0 * N + h0])
     assert abs(got_a - exact_a) <= 2.0 ** -51 * abs(exact_a)
     assert abs(got_b - exact_b) <= 2.0 ** -51 * abs(exact_b)
+
+
+def test_exceptions_at_ragged_corners_of_wide_tiles(orc):
+    """Rows 0 and m - 1 and columns 0 and n - 1 restricted as above: the four
+    corner cells (ragged last row block, ragged last 256 x 384 tile column)
+    cannot be bounded and are recomputed alone; everything else is the
+    residue form's."""
+    dev = cuda_or_skip()
+    M, K, N = 300, 1024, 16500
+    k1 = 700
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(93)
+    X = torch.rand((M, K), generator=gen, dtype=torch.float64, device=dev) * 2 - 1
+    Y = torch.rand((K, N), generator=gen, dtype=torch.float64, device=dev) * 2 - 1
+    for g in (0, M - 1):
+        X[g, K // 2:] = 0.0
+        X[g, k1] = 1e-9
+    for h in (0, N - 1):
+        Y[: K // 2, h] = 0.0
+    A = dense_relation_from_matrix(X, False)
+    B = dense_relation_from_matrix(Y, True)
+    Cg, _, ws = ops.join_agg_fwd(A.group, A.key, A.val, B.key, B.group, B.val, M, K, N,
+                                 precision="crt_i8", tol=1e-12, unique=True)
+    st, info = ops.sync_status(ws)
+    assert st == 0 and info["need"] == 255, info
+    assert info["flags"] & ops._lib.TCU_FLAG_FALLBACK == 0 and info["exceptions"] >= 4, info
+    rows = np.unique(np.concatenate([[0, M - 1], np.random.default_rng(6).choice(M, 30, replace=False)]))
+    C = Cg[torch.as_tensor(rows, device=dev)].cpu().numpy()
+    RA, RB = to_orc(orc, A), to_orc(orc, B)
+    Co, _, _ = orc.join_agg(RA, RB, M, K, N, rows=rows)
+    So, _, _ = orc.join_agg(abs_rel(orc, RA), abs_rel(orc, RB), M, K, N, rows=rows)
+    assert err_cw(C, Co, So) <= 1e-12
+    for g in (0, M - 1):
+        for h in (0, N - 1):
+            exact = 1e-9 * float(Y[k1, h])
+            got = C[int(np.searchsorted(rows, g)), h]
+            assert abs(got - exact) <= 2.0 ** -51 * abs(exact), (g, h, got, exact)
