@@ -510,47 +510,71 @@ __device__ inline void mma_half(const Frag<WA, WB> &f, i16v (&acc)[WA][WB]) {
             acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a[a], f.b[b], acc[a][b], 0, 0, 0);
 }
 
+// The products of one k-step (fragments f) and the LDS reads of the next
+// k-step's fragments (into nf, from k-step S of stage buffer RB).  IL: one
+// MFMA, then the reads and MFMAs alternating, then the remaining MFMAs, so
+// every read is issued while the matrix pipe has work queued (measured on
+// the residue products: 364-367 against 376-379 ms for 14 moduli at 32768^3,
+// 0.796-0.802 against 0.807-0.828 ms at 4096^3).  Otherwise the reads go
+// between the two halves of the MFMAs: the certificate's epilogue needs the
+// registers that the interleaved order keeps live (with it, it spilled).
+template <typename G, int RB, int S, bool IL>
+__device__ inline void kstep(const Frag<G::WA, G::WB> &f, Frag<G::WA, G::WB> &nf,
+                             const i4 *lds_a, const i4 *lds_b, i16v (&acc)[G::WA][G::WB]) {
+    if constexpr (IL) {
+        constexpr int NMF = G::WA * G::WB, NRD = G::WA + G::WB;
+        static_assert(NMF >= NRD, "more MFMAs than fragment reads per k-step");
+        mma_half<0>(f, acc);
+        read_frag<G, RB, S>(lds_a, lds_b, nf);
+        mma_half<1>(f, acc);
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+#pragma unroll
+        for (int i = 0; i < NRD; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
+            if (i + 1 < NRD) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, NMF - NRD, 0);
+        __builtin_amdgcn_sched_barrier(0);
+    } else {
+        mma_half<0>(f, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        read_frag<G, RB, S>(lds_a, lds_b, nf);
+        __builtin_amdgcn_sched_barrier(0);
+        mma_half<1>(f, acc);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // One stage of the main loop, stage index st held in buffer B.  fc holds
 // the fragments of its first k-step.  The second k-step's fragments (fm) are
-// read between the two halves of the first k-step's MFMAs, the next stage's
-// first k-step (into fc) between the halves of the second's, so every LDS
-// read has half a k-step of matrix work to land.  Every stage issues one
-// stage of loads (the last ones repeat stage nst - 1 into buffers no wave
-// reads any more), so "stage st + 1 has landed" is always "at most NS - 3
-// later stages in flight".
-template <typename G, int B>
+// read during the first k-step's MFMAs, the next stage's first k-step (into
+// fc) during the second's, so every LDS read has matrix work to land behind.
+// Every stage issues one stage of loads (the last ones repeat stage nst - 1
+// into buffers no wave reads any more), so "stage st + 1 has landed" is
+// always "at most NS - 3 later stages in flight".
+template <typename G, int B, bool IL>
 __device__ inline void crt_stage(int st, int nst, const StageLoads<G> &L, unsigned lds_addr,
                                  unsigned voff, const i4 *lds_a, const i4 *lds_b,
                                  Frag<G::WA, G::WB> &fc, Frag<G::WA, G::WB> &fm,
                                  i16v (&acc)[G::WA][G::WB]) {
     constexpr int NS = G::NS, PW = G::PER_WAVE;
-    mma_half<0>(fc, acc);
-    __builtin_amdgcn_sched_barrier(0);
-    read_frag<G, B, 1>(lds_a, lds_b, fm);
-    __builtin_amdgcn_sched_barrier(0);
-    mma_half<1>(fc, acc);
-    __builtin_amdgcn_sched_barrier(0);
+    kstep<G, B, 1, IL>(fc, fm, lds_a, lds_b, acc);
     wait_vm<(NS - 3) * PW>();
     barrier_nf();
     const int ist = st + NS - 1 < nst ? st + NS - 1 : nst - 1;
     issue<G>(L, ist, lds_addr + (unsigned)((B + NS - 1) % NS) * G::STAGE * 16u, voff);
     __builtin_amdgcn_sched_barrier(0);
-    mma_half<0>(fm, acc);
-    __builtin_amdgcn_sched_barrier(0);
-    read_frag<G, (B + 1) % NS, 0>(lds_a, lds_b, fc);
-    __builtin_amdgcn_sched_barrier(0);
-    mma_half<1>(fm, acc);
-    __builtin_amdgcn_sched_barrier(0);
+    kstep<G, (B + 1) % NS, 0, IL>(fm, fc, lds_a, lds_b, acc);
 }
 
-template <typename G, int B>
+template <typename G, int B, bool IL>
 __device__ inline void crt_stages(int st, int nst, const StageLoads<G> &L, unsigned lds_addr,
                                   unsigned voff, const i4 *lds_a, const i4 *lds_b,
                                   Frag<G::WA, G::WB> &fc, Frag<G::WA, G::WB> &fm,
                                   i16v (&acc)[G::WA][G::WB]) {
-    crt_stage<G, B>(st + B, nst, L, lds_addr, voff, lds_a, lds_b, fc, fm, acc);
+    crt_stage<G, B, IL>(st + B, nst, L, lds_addr, voff, lds_a, lds_b, fc, fm, acc);
     if constexpr (B + 1 < G::NS)
-        crt_stages<G, B + 1>(st, nst, L, lds_addr, voff, lds_a, lds_b, fc, fm, acc);
+        crt_stages<G, B + 1, IL>(st, nst, L, lds_addr, voff, lds_a, lds_b, fc, fm, acc);
 }
 
 // What the int8 GEMM does with its exact int32 sums.
@@ -625,7 +649,8 @@ gemm_crt_kernel(int m, int n, int nblk, int tiles_m, int tiles_n, const int8_t *
     Frag<WA, WB> fc, fm;
     read_frag<G, 0, 0>(lds_a, lds_b, fc);
     for (int st = 0; st < nst; st += NS)
-        crt_stages<G, 0>(st, nst, L, lds_addr, voff, lds_a, lds_b, fc, fm, acc);
+        crt_stages<G, 0, EPI == kEpiResidue>(st, nst, L, lds_addr, voff, lds_a, lds_b, fc, fm,
+                                             acc);
     wait_vm<0>();  // no load into LDS outlives the loop
 
     if constexpr (EPI == kEpiCount) {
