@@ -511,31 +511,42 @@ __device__ inline void mma_half(const Frag<WA, WB> &f, i16v (&acc)[WA][WB]) {
 }
 
 // The products of one k-step (fragments f) and the LDS reads of the next
-// k-step's fragments (into nf, from k-step S of stage buffer RB).  IL: one
-// MFMA, then the reads and MFMAs alternating, then the remaining MFMAs, so
-// every read is issued while the matrix pipe has work queued (measured on
-// the residue products: 364-367 against 376-379 ms for 14 moduli at 32768^3,
-// 0.796-0.802 against 0.807-0.828 ms at 4096^3).  Otherwise the reads go
-// between the two halves of the MFMAs: the certificate's epilogue needs the
-// registers that the interleaved order keeps live (with it, it spilled).
-template <typename G, int RB, int S, bool IL>
+// k-step's fragments (into nf, from k-step S of stage buffer RB); with
+// LOADS, also the global-to-LDS loads of stage `ist` into buffer `buf`.
+// IL: MFMA i, then load i and read i (while there are any), MFMA by MFMA,
+// so every read and load is issued while the matrix pipe has work queued
+// (measured on the residue products at 32768^3, 14 moduli: 364-367 against
+// 376-379 ms with the reads alone interleaved, MFMA first; 0.7% less again
+// with the loads interleaved too; 0.796-0.802 against 0.807-0.828 ms at
+// 4096^3).  Otherwise the reads go between the two halves of the MFMAs: the
+// certificate's epilogue needs the registers that the interleaved order
+// keeps live (with it, it spilled).
+template <typename G, int RB, int S, bool IL, bool LOADS>
 __device__ inline void kstep(const Frag<G::WA, G::WB> &f, Frag<G::WA, G::WB> &nf,
-                             const i4 *lds_a, const i4 *lds_b, i16v (&acc)[G::WA][G::WB]) {
+                             const i4 *lds_a, const i4 *lds_b, i16v (&acc)[G::WA][G::WB],
+                             const StageLoads<G> &L, int ist, unsigned buf, unsigned voff) {
+    constexpr int WA = G::WA, WB = G::WB, PW = G::PER_WAVE;
     if constexpr (IL) {
-        constexpr int NMF = G::WA * G::WB, NRD = G::WA + G::WB;
-        static_assert(NMF >= NRD, "more MFMAs than fragment reads per k-step");
-        mma_half<0>(f, acc);
-        read_frag<G, RB, S>(lds_a, lds_b, nf);
-        mma_half<1>(f, acc);
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+        static_assert(WA * WB >= WA + WB && WA * WB >= PW, "too few MFMAs to interleave");
 #pragma unroll
-        for (int i = 0; i < NRD; ++i) {
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
-            if (i + 1 < NRD) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        for (int i = 0; i < WA * WB; ++i) {
+            acc[i / WB][i % WB] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                f.a[i / WB], f.b[i % WB], acc[i / WB][i % WB], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (LOADS) {
+                if (i < PW) load_lds16(L.src[i] + (int64_t)ist * L.step[i], voff, buf + L.dst[i]);
+            }
+            if (i < WA)
+                nf.a[i] = lds_a[RB * G::STAGE + S * G::KS + i * 32];
+            else if (i < WA + WB)
+                nf.b[i - WA] = lds_b[RB * G::STAGE + S * G::KS + (i - WA) * 32];
+            __builtin_amdgcn_sched_barrier(0);
         }
-        __builtin_amdgcn_sched_group_barrier(0x008, NMF - NRD, 0);
-        __builtin_amdgcn_sched_barrier(0);
     } else {
+        if constexpr (LOADS) {
+            issue<G>(L, ist, buf, voff);
+            __builtin_amdgcn_sched_barrier(0);
+        }
         mma_half<0>(f, acc);
         __builtin_amdgcn_sched_barrier(0);
         read_frag<G, RB, S>(lds_a, lds_b, nf);
@@ -558,13 +569,13 @@ __device__ inline void crt_stage(int st, int nst, const StageLoads<G> &L, unsign
                                  Frag<G::WA, G::WB> &fc, Frag<G::WA, G::WB> &fm,
                                  i16v (&acc)[G::WA][G::WB]) {
     constexpr int NS = G::NS, PW = G::PER_WAVE;
-    kstep<G, B, 1, IL>(fc, fm, lds_a, lds_b, acc);
+    kstep<G, B, 1, IL, false>(fc, fm, lds_a, lds_b, acc, L, 0, 0u, voff);
     wait_vm<(NS - 3) * PW>();
     barrier_nf();
     const int ist = st + NS - 1 < nst ? st + NS - 1 : nst - 1;
-    issue<G>(L, ist, lds_addr + (unsigned)((B + NS - 1) % NS) * G::STAGE * 16u, voff);
-    __builtin_amdgcn_sched_barrier(0);
-    kstep<G, (B + 1) % NS, 0, IL>(fm, fc, lds_a, lds_b, acc);
+    kstep<G, (B + 1) % NS, 0, IL, true>(fm, fc, lds_a, lds_b, acc, L, ist,
+                                        lds_addr + (unsigned)((B + NS - 1) % NS) * G::STAGE * 16u,
+                                        voff);
 }
 
 template <typename G, int B, bool IL>
