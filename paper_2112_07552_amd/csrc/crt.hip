@@ -297,7 +297,9 @@ mag_cols_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
                 const unsigned long long *__restrict__ maxbits, const double *__restrict__ sums,
                 int parts, double *__restrict__ shat, unsigned long long *umax,
                 int8_t *__restrict__ out, int lines_pad) {
-    const int p0 = blockIdx.x * 64, l0 = blockIdx.y * 64;
+    // consecutive workgroups take consecutive column tiles of the same rows,
+    // so the workgroups in flight read long runs of each row
+    const int l0 = blockIdx.x * 64, p0 = blockIdx.y * 64;
     const int r = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int col = l0 + r;
     const int e = col < cols ? line_exp(maxbits[col]) : 0;
@@ -310,7 +312,7 @@ mag_cols_kernel(const double *__restrict__ Z, int rows, int cols, int64_t ld,
         off += ld;
     }
     *reinterpret_cast<uint4 *>(out + res_offset(col, p0 + 16 * g, lines_pad)) = pack16(q);
-    if (blockIdx.x == 0 && g == 0) {
+    if (blockIdx.y == 0 && g == 0) {
         double sh = 0.0;
         if (col < cols) {
             double sm = 0.0;
@@ -1232,9 +1234,9 @@ hipError_t launch_mag_plane(const double *Z, int rows, int cols, int64_t ld, int
         mag_rows_kernel<<<grid, kThreads, 0, s>>>(Z, rows, cols, ld, maxbits, sums, shat, umax,
                                                   out, lines_pad);
     else
-        mag_cols_kernel<<<grid, kThreads, 0, s>>>(Z, rows, cols, ld, maxbits, sums,
-                                                  col_sum_parts(rows), shat, umax, out,
-                                                  lines_pad);
+        mag_cols_kernel<<<dim3(grid.y, grid.x), kThreads, 0, s>>>(Z, rows, cols, ld, maxbits,
+                                                                  sums, col_sum_parts(rows),
+                                                                  shat, umax, out, lines_pad);
     return hipGetLastError();
 }
 
